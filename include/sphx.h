@@ -1,0 +1,183 @@
+/*
+ * sphx -- MI355X (gfx950) library for the per-step particle loop of the
+ * two-phase weakly compressible SPH method of Wei et al., "Behavior of Oil
+ * under Breaking Waves by a Two-phase SPH Model" (arXiv 1702.07760), Sec. II.
+ *
+ * C ABI.  Plain pointers and sizes only.  Every call returns an sphx_status;
+ * nothing throws across the boundary.  A context is not thread-safe; distinct
+ * contexts are independent.  All device work is queued on the stream given to
+ * sphx_create (a HIP stream handle, never the legacy null stream if the step
+ * is to be graph-captured).
+ *
+ * Ownership.  Host input arrays are copied during the call that takes them.
+ * Device memory for the particle state is one caller-owned workspace of
+ * sphx_workspace_size() bytes, bound with sphx_bind_workspace(); it must
+ * outlive the context.  The step path (build, renormalise, rates, integrate,
+ * step) never allocates.  The read-back calls (sphx_get_field,
+ * sphx_get_neighbors, sphx_get_state) synchronise the stream and may allocate
+ * temporary host or device memory.
+ *
+ * Errors.  Argument errors return SPHX_E_ARG (or SPHX_E_STATE for calls in the
+ * wrong order) and leave the context unchanged.  Faults found on the device
+ * (non-finite state, particles leaving a non-periodic domain, a time step
+ * violating the neighbour-skin bound) are sticky bits of a device status word,
+ * reported by the next sphx_sync or read-back call and cleared by it.
+ * sphx_last_error() gives a readable message for the last failing call.
+ */
+#ifndef SPHX_H
+#define SPHX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sphx_ctx sphx_ctx;
+
+typedef enum {
+    SPHX_OK = 0,
+    SPHX_E_ARG = 1,        /* invalid argument; nothing changed */
+    SPHX_E_NODEV = 2,      /* no usable gfx950 device */
+    SPHX_E_HIP = 3,        /* a HIP runtime call failed */
+    SPHX_E_WORKSPACE = 4,  /* workspace missing, too small or misaligned (256 B) */
+    SPHX_E_STATE = 5,      /* call out of order (e.g. step before init_particles) */
+    SPHX_E_NONFINITE = 6,  /* device: a rate or state value became NaN/Inf */
+    SPHX_E_DOMAIN = 7,     /* device: a particle left a non-periodic domain */
+    SPHX_E_DT = 8          /* device: dt * max|u| exceeded half the neighbour skin */
+} sphx_status;
+
+typedef enum { SPHX_FP64 = 0, SPHX_FP32_CELLREL = 1 } sphx_precision;
+typedef enum { SPHX_FLUID = 0, SPHX_WALL = 1, SPHX_MOVING = 2 } sphx_kind;
+
+#define SPHX_MAX_PISTON 16
+
+/* One phase: reference density rho0 (Eq. (3)), kinematic viscosity nu = mu/rho0
+ * (Eqs. (10), (12)), sound speed c0 giving beta = rho0 c0^2 / gamma (Eq. (4)). */
+typedef struct {
+    double rho0, nu, c0;
+} sphx_phase;
+
+/* Parameters of one simulation instance (one independent tank). */
+typedef struct {
+    int32_t dim;          /* 2 or 3; the same for every instance of a context */
+    int32_t visc_form;    /* 0: Eq. (10) kinematic harmonic mean; 1: Eq. (11) dynamic */
+    int32_t cont_form;    /* 0: Eq. (6) volume form; 1: Eq. (5) mass form */
+    int32_t renorm_every; /* Eq. (7) at steps with step % renorm_every == 0; 0 = never */
+    double h;             /* smoothing length; Wendland C2 kernel of support 2h */
+    double gamma;         /* Tait exponent; must be 7 (Eq. (3)) */
+    double delta_coef;    /* delta = delta_coef * h (Eq. (9)) */
+    double alpha_s;       /* interfacial tension coefficient (Eq. (15)) */
+    double gravity[3];
+    double lo[3], hi[3];  /* domain box; cells tile it; periodic period = hi - lo */
+    int32_t periodic[3];
+    double skin_coef;     /* cells are >= (2 + skin_coef) h; dt <= 0.5 skin_coef h / max|u| */
+    double c_cfl, c_force, c_visc, c_st; /* time-step coefficients */
+    double dt_fixed;      /* > 0: fixed step instead of the adaptive one */
+    int32_t n_piston;     /* MOVING particles follow x = x0 + d(t) e_x with */
+    double piston_t_end;  /* d(t) = sum_k a_k (cos(w_k t' + phi_k) - cos phi_k), t' = min(t, t_end) */
+    double piston_a[SPHX_MAX_PISTON], piston_w[SPHX_MAX_PISTON], piston_phi[SPHX_MAX_PISTON];
+} sphx_params;
+
+/* Field ids for sphx_get_field.  Vector fields are n x 3 (row-major, unused
+ * components zero), scalars n; always FP64 and in original particle order. */
+enum {
+    SPHX_F_X = 0, SPHX_F_U = 1, SPHX_F_RHO = 2,
+    SPHX_F_A = 3,            /* total acceleration of the last rate evaluation (0 for non-fluid) */
+    SPHX_F_DRHO = 4,         /* density rate of the last rate evaluation */
+    SPHX_F_AP = 5, SPHX_F_AV = 6, SPHX_F_AS = 7, /* terms of Eqs. (8), (10)/(11), (17); need SPHX_OPT_DEBUG_TERMS */
+    SPHX_F_P = 12,           /* Tait pressure of the current density */
+    SPHX_F_GRADC = 13        /* colour gradient of the last rate evaluation (Eq. (16)) */
+};
+
+/* Options for sphx_set_option. */
+enum {
+    SPHX_OPT_DEBUG_TERMS = 1, /* 1: compute_forces also stores the three acceleration terms */
+    SPHX_OPT_BLOCK = 2,       /* threads per block of the neighbour passes: 64..1024, multiple of 64 */
+    SPHX_OPT_XCD_REMAP = 3,   /* 1: map consecutive particle tiles to one XCD (default 1) */
+    SPHX_OPT_GRAPH = 4,       /* 1: sphx_step replays a captured hipGraph per step (default 1) */
+    SPHX_OPT_PERSISTENT = 5   /* >0: neighbour passes run as a persistent grid of this many blocks per CU */
+};
+
+/* Run statistics, from the device after sphx_sync. */
+typedef struct {
+    int64_t steps;            /* steps completed (instance 0) */
+    double t;                 /* simulated time of instance 0 */
+    double dt;                /* last time step of instance 0 */
+    int64_t interactions;     /* ordered pairs (i, j != i, r_ij < 2h) summed over every
+                                 force evaluation since the last reset */
+    int64_t ncells;           /* cells over all instances */
+} sphx_stats;
+
+/* Bytes of device workspace for ninst instances holding counts[b] particles. */
+size_t sphx_workspace_size(int32_t precision, const sphx_params* per_inst, int32_t ninst,
+                           const int64_t* counts);
+
+/* Create a context.  per_inst[ninst]; phases[ninst * nphase] (row b holds the phases of
+ * instance b; nphase 1 or 2, phase 0 is water and boundary particles must be phase 0);
+ * counts[ninst] particles per instance; stream is a hipStream_t (may be NULL: the legacy
+ * stream, no graph capture). */
+sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sphx_phase* phases,
+                        int32_t nphase, int32_t ninst, const int64_t* counts, void* stream,
+                        sphx_ctx** out);
+void sphx_destroy(sphx_ctx* ctx);
+const char* sphx_last_error(const sphx_ctx* ctx);
+
+/* Bind caller-owned device memory (>= sphx_workspace_size bytes, 256-byte aligned). */
+sphx_status sphx_bind_workspace(sphx_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* Copy the particle state from host arrays in original order (n = sum of counts):
+ * x, u: n x 3 FP64 row-major; rho, m: n FP64; phase, kind: n uint8.  Validates every
+ * value (finite, inside the box, positive density and mass, phase < nphase, boundary
+ * particles in phase 0) and then builds the neighbour structure. */
+sphx_status sphx_init_particles(sphx_ctx* ctx, const double* x, const double* u, const double* rho,
+                                const double* m, const uint8_t* phase, const uint8_t* kind);
+
+/* Neighbour search at the current positions: cell hash, stable sort by cell (ties by
+ * original index), reorder of the state, cell start table. */
+sphx_status sphx_build_neighbors(sphx_ctx* ctx);
+
+/* Eq. (7): rho_i = sum m_j W_ij / sum (m_j/rho_j) W_ij over i and its same-phase
+ * neighbours, every particle at once from the old densities. */
+sphx_status sphx_renormalize_density(sphx_ctx* ctx);
+
+/* Rates at the current state, no state change: Tait pressure (Eqs. (3)-(4)), colour
+ * gradient and surface stress (Eqs. (14)-(16)), density rate (Eq. (6) or (5)) and
+ * acceleration (Eqs. (8), (10) or (11), (17), gravity). */
+sphx_status sphx_compute_forces(sphx_ctx* ctx);
+
+/* One midpoint predictor-corrector step from the rates of the last compute_forces:
+ * time step (dt > 0 fixes it, dt <= 0 takes the adaptive one on the device),
+ * predictor, rates at the predicted state, corrector.  The neighbour structure is
+ * rebuilt by the next build_neighbors. */
+sphx_status sphx_integrate_step(sphx_ctx* ctx, double dt);
+
+/* nsteps full steps: build, renormalise when due, rates, integrate.  Each step is one
+ * replay of a captured hipGraph when SPHX_OPT_GRAPH is on and the stream allows it. */
+sphx_status sphx_step(sphx_ctx* ctx, int32_t nsteps);
+
+sphx_status sphx_set_option(sphx_ctx* ctx, int32_t option, int64_t value);
+
+/* Wait for the stream; map the device status word to a status and clear it. */
+sphx_status sphx_sync(sphx_ctx* ctx);
+sphx_status sphx_get_stats(sphx_ctx* ctx, sphx_stats* out);
+sphx_status sphx_reset_interactions(sphx_ctx* ctx);
+
+/* Copy one field to host_out in original particle order, FP64 (see the field ids). */
+sphx_status sphx_get_field(sphx_ctx* ctx, int32_t field, double* host_out);
+
+/* Neighbour lists at the current positions in CSR form, original ids, ascending:
+ * off[n+1], ids[need].  *need receives the total; ids is written when cap >= need. */
+sphx_status sphx_get_neighbors(sphx_ctx* ctx, int64_t* off, int32_t* ids, int64_t cap,
+                               int64_t* need);
+
+/* Opaque snapshot of the full state (including compensation terms, time, step count
+ * and the time step); a restored context continues bit-identically. */
+sphx_status sphx_get_state(sphx_ctx* ctx, void* host_blob, size_t cap, size_t* need);
+sphx_status sphx_set_state(sphx_ctx* ctx, const void* host_blob, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,984 @@
+// C-ABI runtime of the sphx library: validation, workspace carving, step
+// sequencing, hipGraph capture and read-back in original particle order.
+#include "sphx.h"
+#include "sphx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+using namespace sphx;
+
+struct sphx_ctx {
+    int precision = 0, dim = 0, ninst = 0, nphase = 0;
+    int64_t n = 0;
+    std::vector<sphx_params> params;
+    std::vector<sphx_phase> phases;     // ninst * 2 (nphase == 1 duplicates phase 0)
+    std::vector<int64_t> counts, offsets;
+    std::vector<InstDev> inst;
+    uint32_t ncell = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    Dev dev{};
+    Launch launch{};
+    int cur = 0;
+    bool bound = false, inited = false, nb_valid = false, rates_valid = false;
+    bool has_moving = false;
+    int64_t step_host = 0;
+    int renorm_every = 1;
+    bool use_graph = true;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    std::string err;
+};
+
+namespace {
+
+sphx_status fail(sphx_ctx* c, sphx_status s, const char* fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIP_OK(c, call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess) return fail((c), SPHX_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- geometry
+
+struct Grid {
+    int32_t nc[3];
+    double cs[3];
+};
+
+bool grid_of(const sphx_params& p, Grid& g, std::string& why)
+{
+    const double reach = (2.0 + p.skin_coef) * p.h;
+    for (int d = 0; d < 3; ++d) {
+        if (d >= p.dim) { g.nc[d] = 1; g.cs[d] = 1.0; continue; }
+        const double L = p.hi[d] - p.lo[d];
+        double k = std::floor(L / reach);
+        if (!(k >= 1.0)) k = 1.0;
+        if (k > 1e7) { why = "domain too large for the cell grid"; return false; }
+        g.nc[d] = (int32_t)k;
+        g.cs[d] = L / k;
+        if (p.periodic[d] && g.nc[d] < 3) { why = "a periodic dimension needs at least 3 cells (period >= 3 (2 + skin) h)"; return false; }
+    }
+    return true;
+}
+
+bool check_params(const sphx_params& p, int dim, std::string& why)
+{
+    auto fin = [](double v) { return std::isfinite(v); };
+    if (p.dim != 2 && p.dim != 3) { why = "dim must be 2 or 3"; return false; }
+    if (p.dim != dim) { why = "every instance must have the same dim"; return false; }
+    if (!(fin(p.h) && p.h > 0)) { why = "h must be positive"; return false; }
+    if (p.gamma != 7.0) { why = "gamma must be 7"; return false; }
+    if (!(fin(p.delta_coef) && p.delta_coef >= 0)) { why = "delta_coef must be >= 0"; return false; }
+    if (!(fin(p.alpha_s) && p.alpha_s >= 0)) { why = "alpha_s must be >= 0"; return false; }
+    if (p.visc_form != 0 && p.visc_form != 1) { why = "visc_form must be 0 or 1"; return false; }
+    if (p.cont_form != 0 && p.cont_form != 1) { why = "cont_form must be 0 or 1"; return false; }
+    if (p.renorm_every < 0) { why = "renorm_every must be >= 0"; return false; }
+    if (!(fin(p.skin_coef) && p.skin_coef > 0 && p.skin_coef <= 2)) { why = "skin_coef must be in (0, 2]"; return false; }
+    if (!(p.c_cfl > 0 && p.c_force > 0 && p.c_visc > 0 && p.c_st > 0)) { why = "time-step coefficients must be positive"; return false; }
+    if (!(fin(p.dt_fixed) && p.dt_fixed >= 0)) { why = "dt_fixed must be >= 0"; return false; }
+    if (p.n_piston < 0 || p.n_piston > SPHX_MAX_PISTON) { why = "n_piston out of range"; return false; }
+    for (int d = 0; d < 3; ++d) {
+        if (!fin(p.gravity[d])) { why = "gravity must be finite"; return false; }
+        if (d >= p.dim) continue;
+        if (!(fin(p.lo[d]) && fin(p.hi[d]) && p.hi[d] > p.lo[d])) { why = "lo < hi required"; return false; }
+        if (p.periodic[d] != 0 && p.periodic[d] != 1) { why = "periodic must be 0 or 1"; return false; }
+    }
+    Grid g;
+    return grid_of(p, g, why);
+}
+
+InstDev make_inst(const sphx_params& p, const sphx_phase* ph2, int nphase, uint32_t cell_base)
+{
+    InstDev I;
+    std::memset(&I, 0, sizeof I);
+    Grid g;
+    std::string why;
+    grid_of(p, g, why);
+    I.ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        const bool act = d < p.dim;
+        I.lo[d] = act ? p.lo[d] : 0.0;
+        I.hi[d] = act ? p.hi[d] : 1.0;
+        I.span[d] = I.hi[d] - I.lo[d];
+        I.cs[d] = g.cs[d];
+        I.nc[d] = g.nc[d];
+        I.periodic[d] = act ? p.periodic[d] : 0;
+        I.g[d] = act ? p.gravity[d] : 0.0;
+        I.ncell *= (uint32_t)g.nc[d];
+        I.f_cs[d] = (float)g.cs[d];
+        I.f_g[d] = (float)I.g[d];
+    }
+    I.cell_base = cell_base;
+    I.dim = p.dim;
+    I.visc_form = p.visc_form;
+    I.cont_form = p.cont_form;
+    I.renorm_every = p.renorm_every;
+    const double h = p.h;
+    const double alpha = p.dim == 2 ? 7.0 / (4.0 * M_PI * h * h) : 21.0 / (16.0 * M_PI * h * h * h);
+    I.h = h;
+    I.inv_h = 1.0 / h;
+    I.cut2 = 4.0 * h * h;
+    I.wcoef = alpha;
+    I.fcoef = -5.0 * alpha / (h * h);
+    const double delta = p.delta_coef * h;
+    I.delta2 = delta * delta;
+    I.alpha_s = p.alpha_s;
+    I.skin = p.skin_coef * h;
+    double cmax = 0, numax = 0, rho0min = std::numeric_limits<double>::infinity();
+    for (int q = 0; q < 2; ++q) {
+        const sphx_phase& f = ph2[q];
+        I.rho0[q] = f.rho0;
+        I.beta[q] = f.rho0 * f.c0 * f.c0 / p.gamma;
+        I.nu[q] = f.nu;
+        if (q < nphase) {
+            cmax = std::max(cmax, f.c0);
+            numax = std::max(numax, f.nu);
+            rho0min = std::min(rho0min, f.rho0);
+        }
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double v;
+            if (p.visc_form == 1) {
+                const double ma = ph2[a].nu * ph2[a].rho0, mb = ph2[b].nu * ph2[b].rho0;
+                v = (ma + mb) > 0 ? 2.0 * ma * mb / (ma + mb) : 0.0;   // Eq. (13)
+            } else {
+                const double na = ph2[a].nu, nb = ph2[b].nu;
+                v = (na + nb) > 0 ? 2.0 * na * nb / (na + nb) : 0.0;   // Eq. (12)
+            }
+            I.vpair[a][b] = 2.0 * v;
+            I.f_vpair[a][b] = (float)(2.0 * v);
+        }
+    I.dt_fixed = p.dt_fixed;
+    I.c_cfl = p.c_cfl;
+    I.c_force = p.c_force;
+    I.cmax = cmax;
+    double lim = std::numeric_limits<double>::infinity();
+    if (numax > 0) lim = std::min(lim, p.c_visc * h * h / numax);
+    if (p.alpha_s > 0 && nphase == 2) lim = std::min(lim, p.c_st * std::sqrt(rho0min * h * h * h / (2.0 * M_PI * p.alpha_s)));
+    I.dt_const = lim;
+    I.n_piston = p.n_piston;
+    I.piston_t_end = p.piston_t_end;
+    for (int k = 0; k < p.n_piston; ++k) {
+        I.pa[k] = p.piston_a[k];
+        I.pw[k] = p.piston_w[k];
+        I.pphi[k] = p.piston_phi[k];
+    }
+    I.f_inv_h = (float)I.inv_h;
+    I.f_cut2 = (float)I.cut2;
+    I.f_fcoef = (float)I.fcoef;
+    I.f_wcoef = (float)I.wcoef;
+    I.f_delta2 = (float)I.delta2;
+    I.f_alpha_s = (float)I.alpha_s;
+    I.f_rho0[0] = (float)I.rho0[0];
+    I.f_rho0[1] = (float)I.rho0[1];
+    return I;
+}
+
+// ---------------------------------------------------------------- workspace
+
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T> T* take(size_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T) + (count == 0 ? 0 : 0);
+        return p;
+    }
+};
+
+// Lays every device array out in the workspace (or only measures when base is null).
+size_t carve(Dev& d, void* base, int precision, int64_t n, uint32_t ncell, int ninst)
+{
+    Carver c(base);
+    const size_t R = precision == 0 ? 8 : 4;
+    const size_t un = (size_t)n;
+    d.inst = c.take<InstDev>(ninst);
+    d.run = c.take<InstRun>(ninst);
+    d.status = c.take<uint32_t>(1);
+    d.inter = c.take<unsigned long long>(1);
+    d.cnt = c.take<uint32_t>(ncell);
+    d.cstart = c.take<uint32_t>((size_t)ncell + 1);
+    d.scan_tmp = c.take<uint32_t>((ncell + 2047) / 2048 + 1);
+    d.cellmask = c.take<uint32_t>((size_t)ncell * 2);
+    d.cellmix = c.take<uint8_t>(ncell);
+    d.newkey = c.take<uint32_t>(un);
+    d.slot = c.take<uint32_t>(un);
+    d.tsrc = c.take<uint32_t>(un);
+    d.tid = c.take<uint32_t>(un);
+    d.perm = c.take<uint32_t>(un);
+    for (int s = 0; s < 2; ++s) {
+        d.S[s].pos = c.take<char>(un * 4 * R);
+        d.S[s].vel = c.take<char>(un * 4 * R);
+        d.S[s].aux = c.take<char>(un * 4 * R);
+        d.S[s].rho = c.take<char>(un * R);
+        d.S[s].plo = precision ? c.take<float4>(un) : nullptr;
+        d.S[s].vlo = precision ? c.take<float4>(un) : nullptr;
+        d.O[s].key = c.take<uint32_t>(un);
+        d.O[s].id = c.take<uint32_t>(un);
+        d.O[s].info = c.take<uint32_t>(un);
+        d.O[s].ref = c.take<double4>(un);
+    }
+    d.star.pos = c.take<char>(un * 4 * R);
+    d.star.vel = c.take<char>(un * 4 * R);
+    d.star.aux = c.take<char>(un * 4 * R);
+    d.star.rho = c.take<char>(un * R);
+    d.star.plo = nullptr;
+    d.star.vlo = nullptr;
+    d.rho_tmp = c.take<char>(un * R);
+    d.acc = c.take<char>(un * 4 * R);
+    d.gc = c.take<char>(un * 4 * R);
+    d.terms = c.take<char>(un * 12 * R);
+    return (c.off + 255) & ~size_t(255);
+}
+
+bool setup_cells(const sphx_params* per, int ninst, std::vector<uint32_t>& base, uint32_t& total, std::string& why)
+{
+    uint64_t acc = 0;
+    base.resize(ninst);
+    for (int b = 0; b < ninst; ++b) {
+        Grid g;
+        if (!grid_of(per[b], g, why)) return false;
+        base[b] = (uint32_t)acc;
+        acc += (uint64_t)g.nc[0] * g.nc[1] * g.nc[2];
+        if (acc >= (1ull << 31)) { why = "too many cells"; return false; }
+    }
+    total = (uint32_t)acc;
+    return true;
+}
+
+// ---------------------------------------------------------------- stepping
+
+sphx_status status_of(sphx_ctx* c)
+{
+    uint32_t st = 0;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    HIP_OK(c, hipMemcpy(&st, c->dev.status, sizeof st, hipMemcpyDeviceToHost));
+    if (st) {
+        const uint32_t zero = 0;
+        HIP_OK(c, hipMemcpy(c->dev.status, &zero, sizeof zero, hipMemcpyHostToDevice));
+    }
+    if (st & ST_NONFINITE) return fail(c, SPHX_E_NONFINITE, "a rate or state value became non-finite");
+    if (st & ST_DOMAIN) return fail(c, SPHX_E_DOMAIN, "a particle left a non-periodic domain");
+    if (st & ST_DT) return fail(c, SPHX_E_DT, "dt * max|u| exceeded half the neighbour skin");
+    return SPHX_OK;
+}
+
+void enqueue_build(sphx_ctx* c)
+{
+    launch_build(c->dev, c->cur, c->launch, c->stream);
+    c->cur = 1 - c->cur;
+}
+
+void enqueue_integrate(sphx_ctx* c, double dt_override)
+{
+    launch_dt(c->dev, dt_override, c->stream);
+    launch_predict(c->dev, c->cur, c->launch, c->stream);
+    launch_rates(c->dev, c->cur, true, false, c->launch, c->stream);
+    launch_correct(c->dev, c->cur, c->launch, c->stream);
+    launch_finish(c->dev, c->stream);
+}
+
+// One full step from a valid neighbour structure; ends with a rebuilt one.
+void enqueue_step(sphx_ctx* c, bool renorm)
+{
+    if (renorm) launch_renorm(c->dev, c->cur, c->launch, c->stream);
+    launch_begin_step(c->dev, c->stream);
+    launch_rates(c->dev, c->cur, false, true, c->launch, c->stream);
+    enqueue_integrate(c, 0.0);
+    enqueue_build(c);
+}
+
+void drop_graphs(sphx_ctx* c)
+{
+    for (auto& row : c->graph)
+        for (auto& g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
+bool renorm_due(const sphx_ctx* c, int64_t step)
+{
+    return c->renorm_every > 0 && step % c->renorm_every == 0;
+}
+
+} // namespace
+
+// ----------------------------------------------------------- checkpoints
+
+namespace {
+struct BlobHeader {
+    uint64_t magic;
+    int32_t precision, dim, ninst, cur;
+    int64_t n, step_host;
+    uint32_t ncell, nb_valid, rates_valid, pad;
+};
+constexpr uint64_t kMagic = 0x5350485853543031ull;   // "SPHXST01"
+
+struct Span { void* p; size_t bytes; };
+
+std::vector<Span> state_spans(sphx_ctx* c)
+{
+    const size_t n = (size_t)c->n, R = c->precision ? 4 : 8;
+    Dev& d = c->dev;
+    const int s = c->cur;
+    std::vector<Span> v = {
+        {d.S[s].pos, n * 4 * R}, {d.S[s].vel, n * 4 * R}, {d.S[s].aux, n * 4 * R}, {d.S[s].rho, n * R},
+        {d.O[s].key, n * 4}, {d.O[s].id, n * 4}, {d.O[s].info, n * 4}, {d.cstart, ((size_t)c->ncell + 1) * 4},
+        {d.cellmix, c->ncell},
+        {d.run, sizeof(InstRun) * c->ninst}, {d.acc, n * 4 * R}, {d.gc, n * 4 * R}};
+    if (c->precision) {
+        v.push_back({d.S[s].plo, n * 16});
+        v.push_back({d.S[s].vlo, n * 16});
+    }
+    if (d.O[s].ref) v.push_back({d.O[s].ref, n * 32});
+    return v;
+}
+} // namespace
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+size_t sphx_workspace_size(int32_t precision, const sphx_params* per_inst, int32_t ninst, const int64_t* counts)
+{
+    if (!per_inst || !counts || ninst < 1 || (precision != 0 && precision != 1)) return 0;
+    int64_t n = 0;
+    for (int b = 0; b < ninst; ++b) {
+        if (counts[b] < 1) return 0;
+        n += counts[b];
+    }
+    std::vector<uint32_t> base;
+    uint32_t total;
+    std::string why;
+    if (!setup_cells(per_inst, ninst, base, total, why)) return 0;
+    Dev d{};
+    return carve(d, nullptr, precision, n, total, ninst);
+}
+
+sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sphx_phase* phases, int32_t nphase,
+                        int32_t ninst, const int64_t* counts, void* stream, sphx_ctx** out)
+{
+    if (!out) return SPHX_E_ARG;
+    *out = nullptr;
+    sphx_ctx tmp;
+    if (!per_inst || !phases || !counts) return fail(&tmp, SPHX_E_ARG, "null argument");
+    if (precision != SPHX_FP64 && precision != SPHX_FP32_CELLREL) return SPHX_E_ARG;
+    if (ninst < 1 || ninst > (1 << 20) || nphase < 1 || nphase > 2) return SPHX_E_ARG;
+    int64_t n = 0;
+    for (int b = 0; b < ninst; ++b) {
+        if (counts[b] < 1) return SPHX_E_ARG;
+        n += counts[b];
+    }
+    if (n >= (1ll << 31)) return SPHX_E_ARG;
+    std::string why;
+    for (int b = 0; b < ninst; ++b) {
+        if (!check_params(per_inst[b], per_inst[0].dim, why)) return SPHX_E_ARG;
+        if (per_inst[b].renorm_every != per_inst[0].renorm_every) return SPHX_E_ARG;
+        for (int q = 0; q < nphase; ++q) {
+            const sphx_phase& f = phases[(size_t)b * nphase + q];
+            if (!(std::isfinite(f.rho0) && f.rho0 > 0 && std::isfinite(f.nu) && f.nu >= 0 && std::isfinite(f.c0) && f.c0 > 0))
+                return SPHX_E_ARG;
+        }
+    }
+    std::vector<uint32_t> base;
+    uint32_t total;
+    if (!setup_cells(per_inst, ninst, base, total, why)) return SPHX_E_ARG;
+
+    int devid = 0;
+    if (hipGetDevice(&devid) != hipSuccess) return SPHX_E_NODEV;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, devid) != hipSuccess) return SPHX_E_NODEV;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SPHX_E_NODEV;
+
+    sphx_ctx* c = new sphx_ctx();
+    c->precision = precision;
+    c->dim = per_inst[0].dim;
+    c->ninst = ninst;
+    c->nphase = nphase;
+    c->n = n;
+    c->params.assign(per_inst, per_inst + ninst);
+    c->phases.resize((size_t)ninst * 2);
+    for (int b = 0; b < ninst; ++b)
+        for (int q = 0; q < 2; ++q) c->phases[(size_t)b * 2 + q] = phases[(size_t)b * nphase + (q < nphase ? q : 0)];
+    c->counts.assign(counts, counts + ninst);
+    c->offsets.resize(ninst + 1);
+    c->offsets[0] = 0;
+    for (int b = 0; b < ninst; ++b) c->offsets[b + 1] = c->offsets[b] + counts[b];
+    c->ncell = total;
+    c->inst.resize(ninst);
+    for (int b = 0; b < ninst; ++b) c->inst[b] = make_inst(per_inst[b], &c->phases[(size_t)b * 2], nphase, base[b]);
+    c->stream = (hipStream_t)stream;
+    c->num_cu = prop.multiProcessorCount;
+    c->launch.num_cu = c->num_cu;
+    c->renorm_every = per_inst[0].renorm_every;
+    c->use_graph = stream != nullptr;
+    *out = c;
+    return SPHX_OK;
+}
+
+void sphx_destroy(sphx_ctx* c)
+{
+    if (!c) return;
+    drop_graphs(c);
+    delete c;
+}
+
+const char* sphx_last_error(const sphx_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+sphx_status sphx_bind_workspace(sphx_ctx* c, void* dev_ptr, size_t bytes)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(c, SPHX_E_WORKSPACE, "workspace must be non-null and 256-byte aligned");
+    Dev d{};
+    const size_t need = carve(d, nullptr, c->precision, c->n, c->ncell, c->ninst);
+    if (bytes < need) return fail(c, SPHX_E_WORKSPACE, "workspace too small: %zu < %zu bytes", bytes, need);
+    drop_graphs(c);
+    c->dev = Dev{};
+    carve(c->dev, dev_ptr, c->precision, c->n, c->ncell, c->ninst);
+    c->dev.precision = c->precision;
+    c->dev.dim = c->dim;
+    c->dev.ninst = c->ninst;
+    c->dev.n = c->n;
+    c->dev.ncell = c->ncell;
+    c->ws = dev_ptr;
+    c->ws_bytes = bytes;
+    c->bound = true;
+    c->inited = false;
+    return SPHX_OK;
+}
+
+sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, const double* rho, const double* m,
+                                const uint8_t* phase, const uint8_t* kind)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->bound) return fail(c, SPHX_E_STATE, "bind a workspace first");
+    if (!x || !u || !rho || !m || !phase || !kind) return fail(c, SPHX_E_ARG, "null array");
+    const int64_t n = c->n;
+    const bool f32 = c->precision == 1;
+    const size_t R = f32 ? 4 : 8;
+    // validate everything before touching the device
+    bool moving = false;
+    for (int b = 0; b < c->ninst; ++b) {
+        const sphx_params& p = c->params[b];
+        for (int64_t i = c->offsets[b]; i < c->offsets[b + 1]; ++i) {
+            for (int d = 0; d < 3; ++d) {
+                if (!std::isfinite(u[3 * i + d])) return fail(c, SPHX_E_ARG, "particle %lld: non-finite velocity", (long long)i);
+                if (d >= c->dim) continue;
+                const double v = x[3 * i + d];
+                if (!std::isfinite(v)) return fail(c, SPHX_E_ARG, "particle %lld: non-finite position", (long long)i);
+                const bool inside = p.periodic[d] ? (v >= p.lo[d] && v < p.hi[d]) : (v >= p.lo[d] && v <= p.hi[d]);
+                if (!inside) return fail(c, SPHX_E_ARG, "particle %lld outside the domain", (long long)i);
+            }
+            if (!(std::isfinite(rho[i]) && rho[i] > 0)) return fail(c, SPHX_E_ARG, "particle %lld: density must be positive", (long long)i);
+            if (!(std::isfinite(m[i]) && m[i] > 0)) return fail(c, SPHX_E_ARG, "particle %lld: mass must be positive", (long long)i);
+            if (phase[i] >= c->nphase) return fail(c, SPHX_E_ARG, "particle %lld: phase out of range", (long long)i);
+            if (kind[i] > SPHX_MOVING) return fail(c, SPHX_E_ARG, "particle %lld: bad kind", (long long)i);
+            if (kind[i] != SPHX_FLUID && phase[i] != 0) return fail(c, SPHX_E_ARG, "particle %lld: boundary particles carry phase 0", (long long)i);
+            moving |= kind[i] == SPHX_MOVING;
+        }
+    }
+    c->has_moving = moving;
+    drop_graphs(c);
+
+    std::vector<char> pos(n * 4 * R), vel(n * 4 * R), aux(n * 4 * R), rh(n * R);
+    std::vector<float4> plo(f32 ? n : 0), vlo(f32 ? n : 0);
+    std::vector<uint32_t> key(n), id(n), info(n);
+    std::vector<double4> ref(n);
+    for (int b = 0; b < c->ninst; ++b) {
+        const InstDev& I = c->inst[b];
+        for (int64_t i = c->offsets[b]; i < c->offsets[b + 1]; ++i) {
+            const double xi[3] = {x[3 * i], c->dim > 1 ? x[3 * i + 1] : 0.0, c->dim > 2 ? x[3 * i + 2] : 0.0};
+            id[i] = (uint32_t)i;
+            info[i] = make_info(phase[i], kind[i], (uint32_t)b);
+            ref[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
+            int cc[3];
+            for (int d = 0; d < 3; ++d) {
+                double k = d < c->dim ? std::floor((xi[d] - I.lo[d]) / I.cs[d]) : 0.0;
+                k = std::min(std::max(k, 0.0), (double)(I.nc[d] - 1));
+                cc[d] = (int)k;
+            }
+            key[i] = I.cell_base + (uint32_t)cc[0] + (uint32_t)I.nc[0] * ((uint32_t)cc[1] + (uint32_t)I.nc[1] * (uint32_t)cc[2]);
+            const double r0 = I.rho0[phase[i]];
+            if (!f32) {
+                ((double4*)pos.data())[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
+                ((double4*)vel.data())[i] = make_double4(u[3 * i], c->dim > 1 ? u[3 * i + 1] : 0.0, c->dim > 2 ? u[3 * i + 2] : 0.0, 0.0);
+                ((double4*)aux.data())[i] = make_double4(m[i], 0.0, 0.0, 0.0);
+                ((double*)rh.data())[i] = rho[i];
+            } else {
+                float o[3], e[3], uu[3], ue[3];
+                for (int d = 0; d < 3; ++d) {
+                    const double off = d < c->dim ? (xi[d] - I.lo[d]) - (double)cc[d] * I.cs[d] : 0.0;
+                    o[d] = (float)off;
+                    e[d] = (float)(off - (double)o[d]);
+                    const double ud = d < c->dim ? u[3 * i + d] : 0.0;
+                    uu[d] = (float)ud;
+                    ue[d] = (float)(ud - (double)uu[d]);
+                }
+                const double dr = rho[i] - r0;
+                const float drf = (float)dr;
+                uint32_t kb = key[i];
+                float kf;
+                std::memcpy(&kf, &kb, 4);
+                ((float4*)pos.data())[i] = make_float4(o[0], o[1], o[2], kf);
+                plo[i] = make_float4(e[0], e[1], e[2], (float)(dr - (double)drf));
+                ((float4*)vel.data())[i] = make_float4(uu[0], uu[1], uu[2], 0.0f);
+                vlo[i] = make_float4(ue[0], ue[1], ue[2], 0.0f);
+                ((float4*)aux.data())[i] = make_float4((float)m[i], 0.0f, 0.0f, 0.0f);
+                ((float*)rh.data())[i] = drf;
+            }
+        }
+    }
+    Dev& d = c->dev;
+    const hipStream_t s = c->stream;
+    HIP_OK(c, hipMemcpyAsync((void*)d.inst, c->inst.data(), sizeof(InstDev) * c->ninst, hipMemcpyHostToDevice, s));
+    std::vector<InstRun> run(c->ninst);
+    std::memset(run.data(), 0, sizeof(InstRun) * c->ninst);
+    HIP_OK(c, hipMemcpyAsync(d.run, run.data(), sizeof(InstRun) * c->ninst, hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemsetAsync(d.status, 0, sizeof(uint32_t), s));
+    HIP_OK(c, hipMemsetAsync(d.inter, 0, sizeof(unsigned long long), s));
+    HIP_OK(c, hipMemsetAsync(d.cnt, 0, sizeof(uint32_t) * c->ncell, s));
+    HIP_OK(c, hipMemsetAsync(d.cellmask, 0, sizeof(uint32_t) * 2 * (size_t)c->ncell, s));
+    HIP_OK(c, hipMemsetAsync(d.acc, 0, n * 4 * R, s));
+    HIP_OK(c, hipMemsetAsync(d.gc, 0, n * 4 * R, s));
+    HIP_OK(c, hipMemsetAsync(d.terms, 0, n * 12 * R, s));
+    HIP_OK(c, hipMemcpyAsync(d.S[0].pos, pos.data(), pos.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemcpyAsync(d.S[0].vel, vel.data(), vel.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemcpyAsync(d.S[0].aux, aux.data(), aux.size(), hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemcpyAsync(d.S[0].rho, rh.data(), rh.size(), hipMemcpyHostToDevice, s));
+    if (f32) {
+        HIP_OK(c, hipMemcpyAsync(d.S[0].plo, plo.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
+        HIP_OK(c, hipMemcpyAsync(d.S[0].vlo, vlo.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
+    }
+    HIP_OK(c, hipMemcpyAsync(d.O[0].key, key.data(), n * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemcpyAsync(d.O[0].id, id.data(), n * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemcpyAsync(d.O[0].info, info.data(), n * 4, hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemcpyAsync(d.O[0].ref, ref.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
+    // the gather moves `ref` only when some particle is MOVING
+    if (!moving) {
+        d.O[0].ref = nullptr;
+        d.O[1].ref = nullptr;
+    } else {
+        Dev tmp{};
+        carve(tmp, c->ws, c->precision, c->n, c->ncell, c->ninst);
+        d.O[0].ref = tmp.O[0].ref;
+        d.O[1].ref = tmp.O[1].ref;
+    }
+    c->cur = 0;
+    launch_derive(d, 0, c->launch, s);
+    enqueue_build(c);
+    c->step_host = 0;
+    c->inited = true;
+    c->nb_valid = true;
+    c->rates_valid = false;
+    HIP_OK(c, hipGetLastError());
+    HIP_OK(c, hipStreamSynchronize(s));
+    return SPHX_OK;
+}
+
+sphx_status sphx_build_neighbors(sphx_ctx* c)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    enqueue_build(c);
+    c->nb_valid = true;
+    c->rates_valid = false;
+    HIP_OK(c, hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status sphx_renormalize_density(sphx_ctx* c)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (!c->nb_valid) enqueue_build(c), c->nb_valid = true;
+    launch_renorm(c->dev, c->cur, c->launch, c->stream);
+    c->rates_valid = false;
+    HIP_OK(c, hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status sphx_compute_forces(sphx_ctx* c)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (!c->nb_valid) enqueue_build(c), c->nb_valid = true;
+    launch_begin_step(c->dev, c->stream);
+    launch_rates(c->dev, c->cur, false, true, c->launch, c->stream);
+    c->rates_valid = true;
+    HIP_OK(c, hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status sphx_integrate_step(sphx_ctx* c, double dt)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (!c->rates_valid) return fail(c, SPHX_E_STATE, "compute_forces first");
+    if (!std::isfinite(dt)) return fail(c, SPHX_E_ARG, "dt must be finite");
+    enqueue_integrate(c, dt > 0 ? dt : 0.0);
+    c->rates_valid = false;
+    c->nb_valid = false;
+    c->step_host += 1;
+    HIP_OK(c, hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status sphx_step(sphx_ctx* c, int32_t nsteps)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (nsteps < 0) return fail(c, SPHX_E_ARG, "nsteps must be >= 0");
+    if (!c->nb_valid) {
+        enqueue_build(c);
+        c->nb_valid = true;
+    }
+    for (int32_t k = 0; k < nsteps; ++k) {
+        const bool due = renorm_due(c, c->step_host);
+        const int cur = c->cur;
+        if (c->use_graph) {
+            hipGraphExec_t& g = c->graph[cur][due ? 1 : 0];
+            if (!g) {
+                hipGraph_t graph = nullptr;
+                if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                    enqueue_step(c, due);
+                    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+                    c->cur = cur;   // capture only recorded the launches
+                    if (e == hipSuccess && graph && hipGraphInstantiate(&g, graph, nullptr, nullptr, 0) == hipSuccess) {
+                        (void)hipGraphDestroy(graph);
+                    } else {
+                        if (graph) (void)hipGraphDestroy(graph);
+                        g = nullptr;
+                        c->use_graph = false;
+                        (void)hipGetLastError();
+                    }
+                } else {
+                    c->use_graph = false;
+                    (void)hipGetLastError();
+                }
+            }
+            if (g) {
+                HIP_OK(c, hipGraphLaunch(g, c->stream));
+                c->cur = 1 - cur;
+            } else {
+                enqueue_step(c, due);
+            }
+        } else {
+            enqueue_step(c, due);
+        }
+        c->step_host += 1;
+    }
+    c->rates_valid = false;
+    c->nb_valid = true;
+    HIP_OK(c, hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
+{
+    if (!c) return SPHX_E_ARG;
+    switch (option) {
+    case SPHX_OPT_DEBUG_TERMS: c->launch.debug_terms = value != 0; break;
+    case SPHX_OPT_BLOCK:
+        if (value < 64 || value > 1024 || value % 64) return fail(c, SPHX_E_ARG, "block must be a multiple of 64 in [64, 1024]");
+        c->launch.block = (int)value;
+        break;
+    case SPHX_OPT_XCD_REMAP: c->launch.xcd_remap = value != 0; break;
+    case SPHX_OPT_GRAPH: c->use_graph = value != 0 && c->stream != nullptr; break;
+    default: return fail(c, SPHX_E_ARG, "unknown option %d", (int)option);
+    }
+    drop_graphs(c);
+    return SPHX_OK;
+}
+
+sphx_status sphx_sync(sphx_ctx* c)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->bound) return fail(c, SPHX_E_STATE, "no workspace");
+    return status_of(c);
+}
+
+sphx_status sphx_get_stats(sphx_ctx* c, sphx_stats* out)
+{
+    if (!c || !out) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    const sphx_status st = status_of(c);
+    InstRun r;
+    unsigned long long inter = 0;
+    HIP_OK(c, hipMemcpy(&r, c->dev.run, sizeof r, hipMemcpyDeviceToHost));
+    HIP_OK(c, hipMemcpy(&inter, c->dev.inter, sizeof inter, hipMemcpyDeviceToHost));
+    out->steps = r.step;
+    out->t = r.t;
+    out->dt = r.dt;
+    out->interactions = (int64_t)inter;
+    out->ncells = c->ncell;
+    return st;
+}
+
+sphx_status sphx_reset_interactions(sphx_ctx* c)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->bound) return fail(c, SPHX_E_STATE, "no workspace");
+    HIP_OK(c, hipMemsetAsync(c->dev.inter, 0, sizeof(unsigned long long), c->stream));
+    return SPHX_OK;
+}
+
+sphx_status sphx_get_field(sphx_ctx* c, int32_t field, double* out)
+{
+    if (!c || !out) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    const sphx_status st = status_of(c);
+    const int64_t n = c->n;
+    const bool f32 = c->precision == 1;
+    const size_t R = f32 ? 4 : 8;
+    const Dev& d = c->dev;
+    const StateSet& S = d.S[c->cur];
+    const Sorted& O = d.O[c->cur];
+    std::vector<uint32_t> id(n), info(n), key(n);
+    HIP_OK(c, hipMemcpy(id.data(), O.id, n * 4, hipMemcpyDeviceToHost));
+    HIP_OK(c, hipMemcpy(info.data(), O.info, n * 4, hipMemcpyDeviceToHost));
+    HIP_OK(c, hipMemcpy(key.data(), O.key, n * 4, hipMemcpyDeviceToHost));
+    auto fetch4 = [&](const void* src, std::vector<double>& v) -> sphx_status {
+        std::vector<char> raw(n * 4 * R);
+        HIP_OK(c, hipMemcpy(raw.data(), src, raw.size(), hipMemcpyDeviceToHost));
+        v.resize(n * 4);
+        for (int64_t k = 0; k < 4 * n; ++k) v[k] = f32 ? (double)((float*)raw.data())[k] : ((double*)raw.data())[k];
+        return SPHX_OK;
+    };
+    auto fetch1 = [&](const void* src, std::vector<double>& v) -> sphx_status {
+        std::vector<char> raw(n * R);
+        HIP_OK(c, hipMemcpy(raw.data(), src, raw.size(), hipMemcpyDeviceToHost));
+        v.resize(n);
+        for (int64_t k = 0; k < n; ++k) v[k] = f32 ? (double)((float*)raw.data())[k] : ((double*)raw.data())[k];
+        return SPHX_OK;
+    };
+    std::vector<float4> lo;
+    auto rho_of = [&](const std::vector<double>& r, int64_t k) {
+        if (!f32) return r[k];
+        const InstDev& I = c->inst[info_inst(info[k])];
+        return I.rho0[info_phase(info[k])] + r[k] + (double)lo[k].w;
+    };
+    std::vector<double> a, b;
+    sphx_status e = SPHX_OK;
+    switch (field) {
+    case SPHX_F_X: {
+        if ((e = fetch4(S.pos, a))) return e;
+        if (f32) {
+            lo.resize(n);
+            HIP_OK(c, hipMemcpy(lo.data(), S.plo, n * sizeof(float4), hipMemcpyDeviceToHost));
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            double* o = out + 3 * (size_t)id[k];
+            if (!f32) {
+                for (int q = 0; q < 3; ++q) o[q] = q < c->dim ? a[4 * k + q] : 0.0;
+            } else {
+                const InstDev& I = c->inst[info_inst(info[k])];
+                uint32_t l = key[k] - I.cell_base;
+                int cc[3];
+                cc[0] = (int)(l % (uint32_t)I.nc[0]);
+                l /= (uint32_t)I.nc[0];
+                cc[1] = (int)(l % (uint32_t)I.nc[1]);
+                cc[2] = (int)(l / (uint32_t)I.nc[1]);
+                const float e3[3] = {lo[k].x, lo[k].y, lo[k].z};
+                for (int q = 0; q < 3; ++q)
+                    o[q] = q < c->dim ? I.lo[q] + (double)cc[q] * I.cs[q] + a[4 * k + q] + (double)e3[q] : 0.0;
+            }
+        }
+        break;
+    }
+    case SPHX_F_U: {
+        if ((e = fetch4(S.vel, a))) return e;
+        std::vector<float4> vl;
+        if (f32) {
+            vl.resize(n);
+            HIP_OK(c, hipMemcpy(vl.data(), S.vlo, n * sizeof(float4), hipMemcpyDeviceToHost));
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            double* o = out + 3 * (size_t)id[k];
+            const float e3[3] = {f32 ? vl[k].x : 0.f, f32 ? vl[k].y : 0.f, f32 ? vl[k].z : 0.f};
+            for (int q = 0; q < 3; ++q) o[q] = q < c->dim ? a[4 * k + q] + (double)e3[q] : 0.0;
+        }
+        break;
+    }
+    case SPHX_F_RHO:
+    case SPHX_F_P: {
+        if ((e = fetch1(S.rho, a))) return e;
+        if (f32) {
+            lo.resize(n);
+            HIP_OK(c, hipMemcpy(lo.data(), S.plo, n * sizeof(float4), hipMemcpyDeviceToHost));
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            const double r = rho_of(a, k);
+            if (field == SPHX_F_RHO) out[id[k]] = r;
+            else {
+                const InstDev& I = c->inst[info_inst(info[k])];
+                const uint32_t ph = info_phase(info[k]);
+                const double y = r / I.rho0[ph], y2 = y * y, y4 = y2 * y2;
+                out[id[k]] = I.beta[ph] * (y4 * y2 * y - 1.0);
+            }
+        }
+        break;
+    }
+    case SPHX_F_A:
+    case SPHX_F_DRHO:
+    case SPHX_F_GRADC: {
+        if ((e = fetch4(field == SPHX_F_GRADC ? d.gc : d.acc, a))) return e;
+        for (int64_t k = 0; k < n; ++k) {
+            if (field == SPHX_F_DRHO) out[id[k]] = a[4 * k + 3];
+            else
+                for (int q = 0; q < 3; ++q) out[3 * (size_t)id[k] + q] = q < c->dim ? a[4 * k + q] : 0.0;
+        }
+        break;
+    }
+    case SPHX_F_AP:
+    case SPHX_F_AV:
+    case SPHX_F_AS: {
+        if (!c->launch.debug_terms) return fail(c, SPHX_E_STATE, "enable SPHX_OPT_DEBUG_TERMS before compute_forces");
+        std::vector<char> raw(n * 12 * R);
+        HIP_OK(c, hipMemcpy(raw.data(), d.terms, raw.size(), hipMemcpyDeviceToHost));
+        const int t = field - SPHX_F_AP;
+        for (int64_t k = 0; k < n; ++k)
+            for (int q = 0; q < 3; ++q) {
+                const size_t at = (size_t)(3 * k + t) * 4 + q;
+                out[3 * (size_t)id[k] + q] = q < c->dim ? (f32 ? (double)((float*)raw.data())[at] : ((double*)raw.data())[at]) : 0.0;
+            }
+        break;
+    }
+    default: return fail(c, SPHX_E_ARG, "unknown field %d", (int)field);
+    }
+    (void)b;
+    return st;
+}
+
+sphx_status sphx_get_neighbors(sphx_ctx* c, int64_t* off, int32_t* ids, int64_t cap, int64_t* need)
+{
+    if (!c || !off || !need) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (!c->nb_valid) enqueue_build(c), c->nb_valid = true;
+    const int64_t n = c->n;
+    uint32_t *dcnt = nullptr, *doff = nullptr, *dids = nullptr;
+    HIP_OK(c, hipMalloc(&dcnt, n * 4));
+    launch_export(c->dev, c->cur, 0, nullptr, dcnt, c->launch, c->stream);
+    std::vector<uint32_t> cnt(n), id(n);
+    hipError_t e = hipMemcpyAsync(cnt.data(), dcnt, n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(id.data(), c->dev.O[c->cur].id, n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(dcnt);
+        return fail(c, SPHX_E_HIP, "neighbour count: %s", hipGetErrorString(e));
+    }
+    std::vector<uint32_t> soff(n + 1, 0);
+    for (int64_t k = 0; k < n; ++k) soff[k + 1] = soff[k] + cnt[k];
+    const int64_t total = soff[n];
+    // per original id
+    std::vector<int64_t> ocnt(n);
+    for (int64_t k = 0; k < n; ++k) ocnt[id[k]] = cnt[k];
+    off[0] = 0;
+    for (int64_t i = 0; i < n; ++i) off[i + 1] = off[i] + ocnt[i];
+    *need = total;
+    if (!ids || cap < total) {
+        (void)hipFree(dcnt);
+        return SPHX_OK;
+    }
+    std::vector<uint32_t> sids(total > 0 ? total : 1);
+    e = hipMalloc(&doff, (n + 1) * 4);
+    if (e == hipSuccess) e = hipMalloc(&dids, (total > 0 ? total : 1) * 4);
+    if (e == hipSuccess) e = hipMemcpyAsync(doff, soff.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) {
+        launch_export(c->dev, c->cur, 1, doff, dids, c->launch, c->stream);
+        e = hipMemcpyAsync(sids.data(), dids, total * 4, hipMemcpyDeviceToHost, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dcnt);
+    if (doff) (void)hipFree(doff);
+    if (dids) (void)hipFree(dids);
+    if (e != hipSuccess) return fail(c, SPHX_E_HIP, "neighbour export: %s", hipGetErrorString(e));
+    for (int64_t k = 0; k < n; ++k) {
+        int32_t* dst = ids + off[id[k]];
+        for (uint32_t q = 0; q < cnt[k]; ++q) dst[q] = (int32_t)sids[soff[k] + q];
+        std::sort(dst, dst + cnt[k]);
+    }
+    return status_of(c);
+}
+
+
+sphx_status sphx_get_state(sphx_ctx* c, void* blob, size_t cap, size_t* need)
+{
+    if (!c || !need) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    auto spans = state_spans(c);
+    size_t total = sizeof(BlobHeader);
+    for (auto& s : spans) total += s.bytes;
+    *need = total;
+    if (!blob || cap < total) return SPHX_OK;
+    const sphx_status st = status_of(c);
+    BlobHeader h{kMagic, c->precision, c->dim, c->ninst, c->cur, c->n, c->step_host, c->ncell,
+                 (uint32_t)c->nb_valid, (uint32_t)c->rates_valid, 0};
+    char* p = (char*)blob;
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    for (auto& s : spans) {
+        HIP_OK(c, hipMemcpy(p, s.p, s.bytes, hipMemcpyDeviceToHost));
+        p += s.bytes;
+    }
+    return st;
+}
+
+sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
+{
+    if (!c || !blob) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first (same scene layout)");
+    BlobHeader h;
+    if (bytes < sizeof h) return fail(c, SPHX_E_ARG, "blob too small");
+    std::memcpy(&h, blob, sizeof h);
+    if (h.magic != kMagic || h.precision != c->precision || h.dim != c->dim || h.ninst != c->ninst || h.n != c->n ||
+        h.ncell != c->ncell)
+        return fail(c, SPHX_E_ARG, "blob does not match this context");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    c->cur = h.cur;
+    auto spans = state_spans(c);
+    size_t total = sizeof h;
+    for (auto& s : spans) total += s.bytes;
+    if (bytes != total) return fail(c, SPHX_E_ARG, "blob size mismatch");
+    const char* p = (const char*)blob + sizeof h;
+    for (auto& s : spans) {
+        HIP_OK(c, hipMemcpy(s.p, p, s.bytes, hipMemcpyHostToDevice));
+        p += s.bytes;
+    }
+    // the next build (from set cur) accumulates into the cell mask of parity cur
+    HIP_OK(c, hipMemset(c->dev.cellmask + (size_t)c->cur * c->ncell, 0, (size_t)c->ncell * 4));
+    HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * 4));
+    c->step_host = h.step_host;
+    c->nb_valid = h.nb_valid != 0;
+    c->rates_valid = h.rates_valid != 0;
+    drop_graphs(c);
+    return SPHX_OK;
+}
+
+} // extern "C"

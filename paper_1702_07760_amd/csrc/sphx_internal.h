@@ -1,0 +1,123 @@
+// Internal interface between the C-ABI runtime (sphx_api.hip) and the gfx950
+// kernels (sphx_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sphx {
+
+constexpr int kMaxPiston = 16;
+
+// Status word bits (sticky, set by kernels with atomicOr).
+enum : uint32_t { ST_NONFINITE = 1u, ST_DOMAIN = 2u, ST_DT = 4u };
+
+// Particle info word: phase in bit 0, kind in bits 1-2, instance in bits 8-31.
+__host__ __device__ inline uint32_t info_phase(uint32_t w) { return w & 1u; }
+__host__ __device__ inline uint32_t info_kind(uint32_t w) { return (w >> 1) & 3u; }
+__host__ __device__ inline uint32_t info_inst(uint32_t w) { return w >> 8; }
+__host__ __device__ inline uint32_t make_info(uint32_t phase, uint32_t kind, uint32_t inst)
+{
+    return (phase & 1u) | ((kind & 3u) << 1) | (inst << 8);
+}
+enum : uint32_t { K_FLUID = 0, K_WALL = 1, K_MOVING = 2 };
+
+// Per-instance constants, built on the host from sphx_params + sphx_phase.
+struct InstDev {
+    double lo[3], hi[3], span[3], cs[3];
+    int32_t nc[3];
+    int32_t periodic[3];
+    uint32_t cell_base, ncell;
+    int32_t dim, visc_form, cont_form, renorm_every;
+    double h, inv_h, cut2, wcoef, fcoef, delta2, alpha_s, skin;
+    double g[3];
+    double rho0[2], beta[2], nu[2];
+    double vpair[2][2];   // 2 nu_ij (Eq. (10)) or 2 mu_ij (Eq. (11)) by phase pair
+    double dt_fixed, c_cfl, c_force, cmax, dt_const; // dt_const: min of viscous and capillary limits
+    int32_t n_piston;
+    double piston_t_end;
+    double pa[kMaxPiston], pw[kMaxPiston], pphi[kMaxPiston];
+    // FP32 copies for the cell-relative kernels
+    float f_cs[3], f_inv_h, f_cut2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3];
+    float f_vpair[2][2], f_rho0[2];
+};
+
+// Per-instance run variables on the device.
+struct InstRun {
+    unsigned long long umax2;  // bit pattern of max |u|^2 (FP64, non-negative)
+    unsigned long long amax2;  // bit pattern of max |a|^2
+    double dt, t, t_next;
+    long long step;
+};
+
+// One copy of the cell-sorted particle state.
+struct StateSet {
+    void* pos;   // R4: FP64 (x, y, z, 0); FP32 (ox, oy, oz, bits(cell key))
+    void* vel;   // R4: (ux, uy, uz, V = m / rho)
+    void* aux;   // R4: (m, m P / rho^2, interface flag, 0)
+    void* rho;   // FP64: rho; FP32: rho - rho0
+    float4* plo; // FP32 only: compensation of (ox, oy, oz, rho - rho0)
+    float4* vlo; // FP32 only: compensation of (ux, uy, uz)
+};
+
+struct Sorted {          // arrays shared by the state sets of one sort order
+    uint32_t* key;       // global cell key (instance cell base + local linear cell)
+    uint32_t* id;        // original particle index
+    uint32_t* info;
+    double4* ref;        // x0 of MOVING particles (absolute)
+};
+
+struct Dev {
+    int precision;       // 0 FP64, 1 FP32 cell-relative
+    int dim;
+    int ninst;
+    int64_t n;
+    uint32_t ncell;      // total over instances
+    const InstDev* inst; // device
+    InstRun* run;        // device
+    uint32_t* status;
+    unsigned long long* inter;
+    // build scratch
+    uint32_t* cnt;       // ncell
+    uint32_t* cstart;    // ncell + 1
+    uint32_t* scan_tmp;  // block sums
+    uint32_t* newkey;    // n (old order)
+    uint32_t* slot;      // n
+    uint32_t* tsrc;      // n
+    uint32_t* tid;       // n
+    uint32_t* perm;      // n
+    uint32_t* cellmask;  // 2 x ncell: phases present (one mask per build parity)
+    uint8_t* cellmix;    // ncell: both phases within the 3^d cell neighbourhood
+    // state
+    StateSet S[2];       // double-buffered current state
+    Sorted O[2];
+    StateSet star;       // predicted state
+    void* rho_tmp;       // renormalised density (R)
+    void* acc;           // R4: (ax, ay, az, drho)
+    void* gc;            // R4: (gx, gy, gz, |g|)
+    void* terms;         // 3 x R4 per particle (debug)
+    double4* newref;     // unused placeholder
+};
+
+struct Launch {
+    int block = 256;
+    int xcd_remap = 1;
+    int persistent = 0;  // blocks per CU when > 0
+    int num_cu = 256;
+    bool debug_terms = false;
+};
+
+// --- launchers (sphx_kernels.hip); all asynchronous on the given stream ---
+void launch_build(const Dev& d, int cur, const Launch& L, hipStream_t s);   // S[cur] -> S[1-cur]
+void launch_renorm(const Dev& d, int cur, const Launch& L, hipStream_t s);
+void launch_rates(const Dev& d, int cur, bool star, bool reduce_max, const Launch& L, hipStream_t s);
+void launch_dt(const Dev& d, double dt_fixed_override, hipStream_t s);
+void launch_predict(const Dev& d, int cur, const Launch& L, hipStream_t s);
+void launch_correct(const Dev& d, int cur, const Launch& L, hipStream_t s);
+void launch_finish(const Dev& d, hipStream_t s);
+void launch_begin_step(const Dev& d, hipStream_t s);
+void launch_derive(const Dev& d, int cur, const Launch& L, hipStream_t s);
+// neighbour export: counts (pass 0) or ids (pass 1) in sorted order
+void launch_export(const Dev& d, int cur, int pass, const uint32_t* off, uint32_t* out,
+                   const Launch& L, hipStream_t s);
+
+} // namespace sphx

@@ -1,0 +1,1062 @@
+// gfx950 kernels of the two-phase WCSPH step (arXiv 1702.07760, Sec. II).
+//
+// Layout: particles live in cell-sorted order, structure-of-arrays of 16/32-byte
+// records so that a wave reads them coalesced.  One lane owns one particle i and
+// gathers over its neighbours j (no atomics on floating-point data; the only
+// atomics are integer counters, cell masks and the max-reductions of the time
+// step, all order-independent).  Neighbour candidates are the particles of the
+// 3^d cells around i, read as contiguous x-rows of the sorted arrays.
+//
+// Two precision forms share every kernel through the template parameter R:
+//   double : absolute FP64 positions, FP64 everything;
+//   float  : positions as (cell, FP32 offset inside the cell), density as
+//            rho - rho0 in FP32, FP64 only for the Tait pressure, the time-step
+//            reduction and the cell origins; compensated (Kahan) updates.
+#include "sphx_internal.h"
+
+#include <math.h>
+
+namespace sphx {
+
+template <class R> struct V4;
+template <> struct V4<double> { using T = double4; };
+template <> struct V4<float> { using T = float4; };
+template <class R> using R4 = typename V4<R>::T;
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ uint32_t tile_index(int remap)
+{
+    const uint32_t b = blockIdx.x, G = gridDim.x;
+    if (!remap) return b;
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+    // run of tiles so that neighbouring particles share one L2.
+    const uint32_t X = 8, full = (G / X) * X;
+    if (b >= full) return b;
+    return (b % X) * (G / X) + b / X;
+}
+
+__device__ __forceinline__ int wrapi(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+__device__ __forceinline__ void cell_of_key(const InstDev& I, uint32_t key, int c[3])
+{
+    uint32_t l = key - I.cell_base;
+    c[0] = (int)(l % (uint32_t)I.nc[0]);
+    l /= (uint32_t)I.nc[0];
+    c[1] = (int)(l % (uint32_t)I.nc[1]);
+    c[2] = (int)(l / (uint32_t)I.nc[1]);
+}
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Tait pressure, Eqs. (3)-(4), gamma = 7, evaluated in FP64 from rho / rho0.
+__device__ __forceinline__ double tait(double y, double beta)
+{
+    const double y2 = y * y, y4 = y2 * y2;
+    return beta * (y4 * y2 * y - 1.0);
+}
+
+// Piston displacement d(t) and velocity (MOVING particles).
+__device__ inline void piston(const InstDev& I, double t, double& d, double& v)
+{
+    const double te = t < I.piston_t_end ? t : I.piston_t_end;
+    d = 0.0;
+    v = 0.0;
+    for (int k = 0; k < I.n_piston; ++k) {
+        d += I.pa[k] * (cos(I.pw[k] * te + I.pphi[k]) - cos(I.pphi[k]));
+        if (t < I.piston_t_end) v -= I.pa[k] * I.pw[k] * sin(I.pw[k] * t + I.pphi[k]);
+    }
+}
+
+// --------------------------------------------------------- lane geometry
+
+// What lane i needs to turn a candidate record into r_ij = x_i - x_j.
+template <class R> struct Lane;
+
+template <> struct Lane<double> {
+    double x[3];
+    int c[3];
+    __device__ void load(const InstDev& I, const double4& p, uint32_t key)
+    {
+        x[0] = p.x; x[1] = p.y; x[2] = p.z;
+        cell_of_key(I, key, c);
+    }
+};
+
+template <> struct Lane<float> {
+    float o[3];
+    int c[3];
+    __device__ void load(const InstDev& I, const float4& p, uint32_t key)
+    {
+        o[0] = p.x; o[1] = p.y; o[2] = p.z;
+        cell_of_key(I, key, c);
+    }
+};
+
+// Per-row constants (the y/z cell offsets of a stencil row are fixed).
+template <class R> struct Row { R y, z; uint32_t base; };
+
+template <int DIM>
+__device__ __forceinline__ double dist2(double rx, double ry, double rz)
+{
+    // the same rounding as the oracle: fma(rz, rz, fma(ry, ry, rx*rx))
+    return DIM == 3 ? fma(rz, rz, fma(ry, ry, rx * rx)) : fma(ry, ry, rx * rx);
+}
+
+template <int DIM>
+__device__ __forceinline__ float dist2(float rx, float ry, float rz)
+{
+    return DIM == 3 ? fmaf(rz, rz, fmaf(ry, ry, rx * rx)) : fmaf(ry, ry, rx * rx);
+}
+
+__device__ __forceinline__ double min_image(double v, const InstDev& I, int d)
+{
+    if (I.periodic[d]) {
+        const double L = I.span[d];
+        if (v > 0.5 * L) v -= L;
+        else if (v < -0.5 * L) v += L;
+    }
+    return v;
+}
+
+// r_ij for candidate record pj (FP64: absolute positions, minimal image).
+template <int DIM>
+__device__ __forceinline__ void pair_r(const InstDev& I, const Lane<double>& L, const Row<double>&,
+                                       const double4& pj, double r[3])
+{
+    r[0] = min_image(L.x[0] - pj.x, I, 0);
+    r[1] = min_image(L.x[1] - pj.y, I, 1);
+    r[2] = DIM == 3 ? min_image(L.x[2] - pj.z, I, 2) : 0.0;
+}
+
+// r_ij for candidate record pj (FP32: cell offsets; pj.w holds j's cell key).
+template <int DIM>
+__device__ __forceinline__ void pair_r(const InstDev& I, const Lane<float>& L, const Row<float>& row,
+                                       const float4& pj, float r[3])
+{
+    int dcx = L.c[0] - (int)(__float_as_uint(pj.w) - row.base);
+    if (I.periodic[0]) dcx = dcx > 1 ? dcx - I.nc[0] : (dcx < -1 ? dcx + I.nc[0] : dcx);
+    r[0] = fmaf((float)dcx, I.f_cs[0], L.o[0] - pj.x);
+    r[1] = row.y - pj.y;
+    r[2] = DIM == 3 ? row.z - pj.z : 0.0f;
+}
+
+template <class R> __device__ __forceinline__ R cut2_of(const InstDev& I);
+template <> __device__ __forceinline__ double cut2_of<double>(const InstDev& I) { return I.cut2; }
+template <> __device__ __forceinline__ float cut2_of<float>(const InstDev& I) { return I.f_cut2; }
+
+// Visit every j != i with |r_ij|^2 < 4h^2 among the 3^d cells around i's cell.
+template <class R, int DIM, class Body>
+__device__ __forceinline__ void for_neighbors(const InstDev& I, const uint32_t* __restrict__ cstart,
+                                              const R4<R>* __restrict__ pos, uint32_t i,
+                                              const Lane<R>& L, Body&& body)
+{
+    const R cut2 = cut2_of<R>(I);
+    const int nx = I.nc[0];
+    const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+        int cz = L.c[2] + dz;
+        if (DIM == 3) {
+            if (I.periodic[2]) cz = wrapi(cz, I.nc[2]);
+            else if (cz < 0 || cz >= I.nc[2]) continue;
+        }
+        for (int dy = -1; dy <= 1; ++dy) {
+            int cy = L.c[1] + dy;
+            if (I.periodic[1]) cy = wrapi(cy, I.nc[1]);
+            else if (cy < 0 || cy >= I.nc[1]) continue;
+            Row<R> row;
+            row.base = I.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)I.nc[1] * (uint32_t)cz);
+            if constexpr (sizeof(R) == 4) {
+                const Lane<float>& Lf = reinterpret_cast<const Lane<float>&>(L);
+                row.y = Lf.o[1] - (float)dy * I.f_cs[1];
+                row.z = DIM == 3 ? Lf.o[2] - (float)dz * I.f_cs[2] : 0.0f;
+            }
+            uint32_t a0, b0, a1 = 0, b1 = 0;
+            const int x0 = L.c[0] - 1, x1 = L.c[0] + 1;
+            if (!I.periodic[0]) {
+                a0 = cstart[row.base + (uint32_t)max(x0, 0)];
+                b0 = cstart[row.base + (uint32_t)min(x1, nx - 1) + 1];
+            } else if (x0 < 0) {
+                a0 = cstart[row.base + (uint32_t)(nx - 1)];
+                b0 = cstart[row.base + (uint32_t)nx];
+                a1 = cstart[row.base];
+                b1 = cstart[row.base + (uint32_t)x1 + 1];
+            } else if (x1 >= nx) {
+                a0 = cstart[row.base + (uint32_t)x0];
+                b0 = cstart[row.base + (uint32_t)nx];
+                a1 = cstart[row.base];
+                b1 = cstart[row.base + 1];
+            } else {
+                a0 = cstart[row.base + (uint32_t)x0];
+                b0 = cstart[row.base + (uint32_t)x1 + 1];
+            }
+            for (int seg = 0; seg < 2; ++seg) {
+                const uint32_t a = seg ? a1 : a0, b = seg ? b1 : b0;
+                for (uint32_t k = a; k < b; ++k) {
+                    const R4<R> pj = pos[k];
+                    R r[3];
+                    pair_r<DIM>(I, L, row, pj, r);
+                    const R r2 = dist2<DIM>(r[0], r[1], r[2]);
+                    if (r2 < cut2 && k != i) body(k, r, r2);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------- neighbour build
+
+// a1: cell hash.  FP64 takes floor((x - lo)/s); FP32 moves an offset that left
+// its cell into the neighbouring cell, folding the rounding of the shift into
+// the compensation term.  Each particle bumps its cell counter (the returned
+// value is its provisional slot) and marks its phase in the cell mask.
+template <class R, int DIM>
+__global__ void k_hash(Dev d, int cur, uint32_t* __restrict__ cellmask)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n) return;
+    const Sorted& O = d.O[cur];
+    const uint32_t info = O.info[k];
+    const InstDev& I = d.inst[info_inst(info)];
+    int c[3] = {0, 0, 0};
+    bool out = false;
+    if constexpr (sizeof(R) == 8) {
+        const double4 p = ((const double4*)d.S[cur].pos)[k];
+        const double x[3] = {p.x, p.y, p.z};
+        for (int dd = 0; dd < DIM; ++dd) {
+            if (!isfinite(x[dd])) atomicOr(d.status, ST_NONFINITE);
+            double v = floor((x[dd] - I.lo[dd]) / I.cs[dd]);
+            int ci = isfinite(v) ? (int)fmax(fmin(v, 1e9), -1e9) : 0;
+            if (ci < 0 || ci >= I.nc[dd]) {
+                if (!I.periodic[dd]) out = true;
+                ci = ci < 0 ? 0 : I.nc[dd] - 1;
+            }
+            c[dd] = ci;
+        }
+    } else {
+        float4* pos = (float4*)d.S[cur].pos;
+        float4 p = pos[k];
+        float4 lo = d.S[cur].plo[k];
+        cell_of_key(I, O.key[k], c);
+        float o[3] = {p.x, p.y, p.z};
+        float e[3] = {lo.x, lo.y, lo.z};
+        for (int dd = 0; dd < DIM; ++dd) {
+            if (!isfinite(o[dd])) {
+                atomicOr(d.status, ST_NONFINITE);
+                o[dd] = 0.0f;
+            }
+            const float s = I.f_cs[dd];
+            const float sh = fminf(fmaxf(floorf(o[dd] / s), -1.0e6f), 1.0e6f);
+            if (sh != 0.0f) {
+                // o - sh*s with its rounding error kept (TwoSum); sh*s is exact for |sh| <= 2
+                const float b = -sh * s;
+                const float sum = o[dd] + b;
+                const float bv = sum - o[dd];
+                const float err = (o[dd] - (sum - bv)) + (b - bv);
+                o[dd] = sum;
+                e[dd] += err;
+                int ci = c[dd] + (int)sh;
+                if (I.periodic[dd]) {
+                    ci = ((ci % I.nc[dd]) + I.nc[dd]) % I.nc[dd];
+                } else if (ci < 0 || ci >= I.nc[dd]) {
+                    out = true;
+                    ci = ci < 0 ? 0 : I.nc[dd] - 1;
+                }
+                c[dd] = ci;
+            }
+        }
+        pos[k] = make_float4(o[0], o[1], o[2], p.w);
+        d.S[cur].plo[k] = make_float4(e[0], e[1], e[2], lo.w);
+    }
+    if (out) atomicOr(d.status, ST_DOMAIN);
+    const uint32_t key = I.cell_base + (uint32_t)c[0] +
+                         (uint32_t)I.nc[0] * ((uint32_t)c[1] + (uint32_t)I.nc[1] * (uint32_t)c[2]);
+    d.newkey[k] = key;
+    d.slot[k] = atomicAdd(&d.cnt[key], 1u);
+    atomicOr(&cellmask[key], 1u << info_phase(info));
+}
+
+// a4 (cell start table): exclusive scan of the per-cell counts in three passes.
+constexpr int SCAN_THREADS = 256, SCAN_ITEMS = 8, SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& total)
+{
+    __shared__ uint32_t wsum[SCAN_THREADS / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+    total = 0;
+    for (int k = 0; k < SCAN_THREADS / 64; ++k) {
+        if (k < w) base += wsum[k];
+        total += wsum[k];
+    }
+    __syncthreads();
+    return base + incl - v;
+}
+
+__global__ void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ sums)
+{
+    const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j)
+        if (base + j < n) s += in[base + j];
+    uint32_t total;
+    block_exclusive_scan(s, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_top(uint32_t* __restrict__ sums, uint32_t ntiles)
+{
+    // one block; each thread owns a run of ceil(ntiles / 256) tile sums
+    const uint32_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
+    const uint32_t a = threadIdx.x * per;
+    uint32_t s = 0;
+    for (uint32_t j = 0; j < per; ++j)
+        if (a + j < ntiles) s += sums[a + j];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, total);
+    for (uint32_t j = 0; j < per; ++j)
+        if (a + j < ntiles) {
+            const uint32_t v = sums[a + j];
+            sums[a + j] = run;
+            run += v;
+        }
+}
+
+// Writes cstart[0..n] and clears the counters for the next build.
+__global__ void k_scan_down(uint32_t* __restrict__ cnt, uint32_t n, const uint32_t* __restrict__ sums,
+                            uint32_t* __restrict__ out)
+{
+    const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    uint32_t v[SCAN_ITEMS];
+    uint32_t s = 0;
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        v[j] = base + j < n ? cnt[base + j] : 0u;
+        s += v[j];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(s, total) + sums[blockIdx.x];
+    for (int j = 0; j < SCAN_ITEMS; ++j) {
+        const uint32_t idx = base + j;
+        if (idx < n) {
+            out[idx] = run;
+            cnt[idx] = 0u;
+            if (idx == n - 1) out[n] = run + v[j];
+        }
+        run += v[j];
+    }
+}
+
+// Provisional scatter into the cell's segment.
+__global__ void k_scatter(Dev d, int cur)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n) return;
+    const uint32_t p = d.cstart[d.newkey[k]] + d.slot[k];
+    d.tsrc[p] = k;
+    d.tid[p] = d.O[cur].id[k];
+}
+
+// a2 made unique: within a cell, order by original id (rank = number of smaller ids).
+__global__ void k_rank(Dev d)
+{
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= d.n) return;
+    const uint32_t src = d.tsrc[s];
+    const uint32_t key = d.newkey[src];
+    const uint32_t a = d.cstart[key], b = d.cstart[key + 1];
+    const uint32_t me = d.tid[s];
+    uint32_t r = 0;
+    for (uint32_t t = a; t < b; ++t) r += d.tid[t] < me ? 1u : 0u;
+    d.perm[a + r] = src;
+}
+
+// a3: permute the state into the new order (S[cur] -> S[1-cur]).
+template <class R>
+__global__ void k_gather(Dev d, int cur, int with_ref)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n) return;
+    const uint32_t src = d.perm[k];
+    const int nxt = 1 - cur;
+    const Sorted& A = d.O[cur];
+    const Sorted& B = d.O[nxt];
+    const uint32_t key = d.newkey[src];
+    B.key[k] = key;
+    B.id[k] = A.id[src];
+    B.info[k] = A.info[src];
+    if (with_ref) B.ref[k] = A.ref[src];
+    const StateSet& SA = d.S[cur];
+    const StateSet& SB = d.S[nxt];
+    R4<R> p = ((const R4<R>*)SA.pos)[src];
+    if constexpr (sizeof(R) == 4) p.w = __uint_as_float(key);
+    ((R4<R>*)SB.pos)[k] = p;
+    ((R4<R>*)SB.vel)[k] = ((const R4<R>*)SA.vel)[src];
+    ((R4<R>*)SB.aux)[k] = ((const R4<R>*)SA.aux)[src];
+    ((R*)SB.rho)[k] = ((const R*)SA.rho)[src];
+    if constexpr (sizeof(R) == 4) {
+        SB.plo[k] = SA.plo[src];
+        SB.vlo[k] = SA.vlo[src];
+    }
+}
+
+// Per cell: do both phases occur among the 3^d surrounding cells?  Also clears the
+// other parity's mask for the next build.
+template <int DIM>
+__global__ void k_cellmix(Dev d, const uint32_t* __restrict__ mask, uint32_t* __restrict__ mask_next)
+{
+    const uint32_t cidx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cidx >= d.ncell) return;
+    int lo = 0, hi = d.ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (d.inst[mid].cell_base <= cidx) lo = mid;
+        else hi = mid - 1;
+    }
+    const InstDev& I = d.inst[lo];
+    int c[3];
+    cell_of_key(I, cidx, c);
+    uint32_t m = 0;
+    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int q[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
+                bool skip = false;
+                for (int a = 0; a < DIM; ++a) {
+                    if (I.periodic[a]) q[a] = wrapi(q[a], I.nc[a]);
+                    else if (q[a] < 0 || q[a] >= I.nc[a]) skip = true;
+                }
+                if (skip) continue;
+                m |= mask[I.cell_base + (uint32_t)q[0] + (uint32_t)I.nc[0] * ((uint32_t)q[1] + (uint32_t)I.nc[1] * (uint32_t)q[2])];
+            }
+    d.cellmix[cidx] = m == 3u ? 1 : 0;
+    mask_next[cidx] = 0u;
+}
+
+// ------------------------------------------------------ per-particle state
+
+// Density of particle k as FP64 (FP32 form stores rho - rho0).
+template <class R>
+__device__ __forceinline__ double rho_of(const InstDev& I, uint32_t phase, R stored)
+{
+    if constexpr (sizeof(R) == 8) return stored;
+    else return I.rho0[phase] + (double)stored;
+}
+
+// Derived quantities of one particle: V = m / rho into vel.w, m P / rho^2 into aux.y.
+template <class R>
+__device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R stored, R4<R>& vel, R4<R>& aux)
+{
+    const double rho = rho_of<R>(I, phase, stored);
+    const double y = sizeof(R) == 8 ? rho / I.rho0[phase] : 1.0 + (double)stored / I.rho0[phase];
+    const double P = tait(y, I.beta[phase]);
+    const double m = (double)aux.x;
+    vel.w = (R)(m / rho);
+    aux.y = (R)(m * (P / (rho * rho)));
+}
+
+// After Eq. (7): move the renormalised density into the state and re-derive.
+template <class R>
+__global__ void k_derive(Dev d, int cur, int from_tmp)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n) return;
+    const uint32_t info = d.O[cur].info[k];
+    const InstDev& I = d.inst[info_inst(info)];
+    const StateSet& S = d.S[cur];
+    R r = from_tmp ? ((const R*)d.rho_tmp)[k] : ((const R*)S.rho)[k];
+    if (from_tmp) {
+        ((R*)S.rho)[k] = r;
+        if constexpr (sizeof(R) == 4) S.plo[k].w = 0.0f;   // a fresh value: no carried error
+    }
+    R4<R> vel = ((R4<R>*)S.vel)[k];
+    R4<R> aux = ((R4<R>*)S.aux)[k];
+    derive_one<R>(I, info_phase(info), r, vel, aux);
+    ((R4<R>*)S.vel)[k] = vel;
+    ((R4<R>*)S.aux)[k] = aux;
+}
+
+// -------------------------------------------------------- Eq. (7) renormalise
+
+template <class R> __device__ __forceinline__ R kernel_w(const InstDev& I, R r2);
+template <> __device__ __forceinline__ double kernel_w<double>(const InstDev& I, double r2)
+{
+    const double q = sqrt(r2) * I.inv_h, t = 1.0 - 0.5 * q, t2 = t * t;
+    return I.wcoef * (t2 * t2) * (2.0 * q + 1.0);
+}
+template <> __device__ __forceinline__ float kernel_w<float>(const InstDev& I, float r2)
+{
+    const float q = sqrtf(r2) * I.f_inv_h, t = 1.0f - 0.5f * q, t2 = t * t;
+    return I.f_wcoef * (t2 * t2) * (2.0f * q + 1.0f);
+}
+
+template <class R> __device__ __forceinline__ R kernel_f(const InstDev& I, R r2);
+template <> __device__ __forceinline__ double kernel_f<double>(const InstDev& I, double r2)
+{
+    const double t = 1.0 - 0.5 * (sqrt(r2) * I.inv_h);
+    return I.fcoef * (t * t * t);
+}
+template <> __device__ __forceinline__ float kernel_f<float>(const InstDev& I, float r2)
+{
+    const float t = 1.0f - 0.5f * (sqrtf(r2) * I.f_inv_h);
+    return I.f_fcoef * (t * t * t);
+}
+
+template <class R, int DIM>
+__device__ __forceinline__ void renorm_one(const Dev& d, int cur, uint32_t i)
+{
+    const Sorted& O = d.O[cur];
+    const StateSet& S = d.S[cur];
+    const R4<R>* pos = (const R4<R>*)S.pos;
+    const R4<R>* vel = (const R4<R>*)S.vel;
+    const R4<R>* aux = (const R4<R>*)S.aux;
+    const R* rho = (const R*)S.rho;
+    const uint32_t info = O.info[i];
+    const InstDev& I = d.inst[info_inst(info)];
+    const uint32_t ph = info_phase(info);
+    Lane<R> L;
+    L.load(I, pos[i], O.key[i]);
+    const R w0 = kernel_w<R>(I, (R)0);
+    R num, den;
+    if constexpr (sizeof(R) == 8) {
+        // Eq. (7) as written: sum m_j W_ij / sum (m_j / rho_j) W_ij, self included
+        num = aux[i].x * w0;
+        den = vel[i].w * w0;
+        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R*, R r2) {
+            if (info_phase(O.info[k]) != ph) return;
+            const R w = kernel_w<R>(I, r2);
+            num += aux[k].x * w;
+            den += vel[k].w * w;
+        });
+        ((R*)d.rho_tmp)[i] = num / den;
+    } else {
+        // the same quotient minus rho0, as a V_j W_ij-weighted mean of (rho_j - rho0):
+        // m_j - rho0 V_j = V_j (rho_j - rho0), so nothing cancels in FP32
+        num = vel[i].w * w0 * rho[i];
+        den = vel[i].w * w0;
+        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R*, R r2) {
+            if (info_phase(O.info[k]) != ph) return;
+            const R vw = vel[k].w * kernel_w<R>(I, r2);
+            num += vw * rho[k];
+            den += vw;
+        });
+        ((R*)d.rho_tmp)[i] = num / den;
+    }
+}
+
+template <class R, int DIM>
+__global__ void k_renorm(Dev d, int cur, int remap)
+{
+    const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
+    if (i >= d.n) return;
+    renorm_one<R, DIM>(d, cur, i);
+}
+
+// ----------------------------------------------- Eq. (16) colour gradient (pass A)
+
+template <class R, int DIM>
+__global__ void k_colour(Dev d, int cur, int star, int remap)
+{
+    const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
+    const bool valid = i < d.n;
+    const Sorted& O = d.O[cur];
+    const StateSet& S = star ? d.star : d.S[cur];
+    R4<R>* gc = (R4<R>*)d.gc;
+    R4<R>* aux = (R4<R>*)S.aux;
+    const bool mixed = valid && d.cellmix[O.key[i]] != 0;
+    if (!valid) return;
+    R g[3] = {0, 0, 0};
+    R gn = 0;
+    if (mixed) {
+        const R4<R>* pos = (const R4<R>*)S.pos;
+        const R4<R>* vel = (const R4<R>*)S.vel;
+        const uint32_t info = O.info[i];
+        const InstDev& I = d.inst[info_inst(info)];
+        const uint32_t ph = info_phase(info);
+        Lane<R> L;
+        L.load(I, pos[i], O.key[i]);
+        R s[3] = {0, 0, 0};
+        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R* r, R r2) {
+            if (info_phase(O.info[k]) == ph) return;       // C_j^y = 1 only for the other phase
+            const R vk = vel[k].w;                          // 1 / sigma_k
+            const R f = kernel_f<R>(I, r2) * (vk * vk);
+            s[0] += f * r[0];
+            s[1] += f * r[1];
+            s[2] += f * r[2];
+        });
+        const R vi = vel[i].w;                              // sigma_i = 1 / V_i
+        g[0] = s[0] / vi;
+        g[1] = s[1] / vi;
+        g[2] = s[2] / vi;
+        gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    }
+    R4<R> out;
+    out.x = g[0]; out.y = g[1]; out.z = g[2]; out.w = gn;
+    gc[i] = out;
+    aux[i].z = gn > 0 ? (R)1 : (R)0;
+}
+
+// ------------------------------------------ Eqs. (6), (8), (10)/(11), (17) (pass B)
+
+// (T V^2) . w for T = alpha (|g|^2 I / d - g g^T) / |g|, with c = alpha V^2 / |g|.
+template <class R, int DIM>
+__device__ __forceinline__ void tension_dot(R c, const R g[3], R gn2, const R w[3], R out[3])
+{
+    const R gw = g[0] * w[0] + g[1] * w[1] + g[2] * w[2];
+    const R iso = gn2 / (R)DIM;
+    for (int a = 0; a < 3; ++a) out[a] = c * (iso * w[a] - g[a] * gw);
+}
+
+template <class R, int DIM, bool REDUCE, bool TERMS>
+__global__ void k_force(Dev d, int cur, int star, int remap)
+{
+    const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
+    const bool valid = i < d.n;
+    const Sorted& O = d.O[cur];
+    const StateSet& S = star ? d.star : d.S[cur];
+    const R4<R>* pos = (const R4<R>*)S.pos;
+    const R4<R>* vel = (const R4<R>*)S.vel;
+    const R4<R>* aux = (const R4<R>*)S.aux;
+    const R4<R>* gc = (const R4<R>*)d.gc;
+    double umag2 = 0.0, amag2 = 0.0;
+    unsigned long long nint = 0;
+    uint32_t inst = 0;
+    if (valid) {
+        const uint32_t info = O.info[i];
+        inst = info_inst(info);
+        const InstDev& I = d.inst[inst];
+        const uint32_t ph = info_phase(info);
+        const bool fluid = info_kind(info) == K_FLUID;
+        Lane<R> L;
+        L.load(I, pos[i], O.key[i]);
+        const R4<R> vi = vel[i];
+        const R4<R> xi = aux[i];                 // (m, m A, flag)
+        const R mi = xi.x;
+        const R Ai = xi.y / mi;                  // P_i / rho_i^2
+        const bool fli = xi.z != (R)0;
+        R gi[3] = {0, 0, 0}, ci = 0, gi2 = 0;
+        if (fli) {
+            const R4<R> g4 = gc[i];
+            gi[0] = g4.x; gi[1] = g4.y; gi[2] = g4.z;
+            gi2 = g4.w * g4.w;
+            ci = (sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s) * (vi.w * vi.w) / g4.w;
+        }
+        R vp0, vp1, delta2;
+        if constexpr (sizeof(R) == 8) { vp0 = I.vpair[ph][0]; vp1 = I.vpair[ph][1]; delta2 = I.delta2; }
+        else { vp0 = I.f_vpair[ph][0]; vp1 = I.f_vpair[ph][1]; delta2 = I.f_delta2; }
+        const bool massform = I.cont_form == 1;
+        R cont = 0, ap[3] = {0, 0, 0}, av[3] = {0, 0, 0}, as[3] = {0, 0, 0};
+        uint32_t cnt = 0;
+        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R* r, R r2) {
+            ++cnt;
+            const R F = kernel_f<R>(I, r2);
+            const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
+            const R4<R> vk = vel[k];
+            const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
+            const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+            const R4<R> xk = aux[k];
+            cont += (massform ? xk.x : vk.w) * udw;                   // Eq. (6) / (5)
+            if (!fluid) return;
+            const R pc = xk.x * Ai + xk.y;                            // m_j (A_i + A_j)
+            ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
+            const uint32_t pk = info_phase(O.info[k]);
+            const R lap = (F * r2) / (r2 + delta2);                   // r.gradW / (r^2 + delta^2)
+            const R cv = vk.w * (pk ? vp1 : vp0) * lap;
+            av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
+            const bool flk = xk.z != (R)0;
+            if (fli || flk) {
+                R t[3];
+                if (fli) {
+                    tension_dot<R, DIM>(ci, gi, gi2, w, t);
+                    as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+                }
+                if (flk) {
+                    const R4<R> g4 = gc[k];
+                    const R gk[3] = {g4.x, g4.y, g4.z};
+                    const R ck = (sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s) * (vk.w * vk.w) / g4.w;
+                    tension_dot<R, DIM>(ck, gk, g4.w * g4.w, w, t);
+                    as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+                }
+            }
+        });
+        nint = cnt;
+        const double rho_i = rho_of<R>(I, ph, ((const R*)S.rho)[i]);
+        R4<R> out;
+        out.w = massform ? cont : (R)rho_i * cont;
+        R a[3] = {0, 0, 0};
+        if (fluid) {
+            const R vfac = I.visc_form == 1 ? (R)(1.0 / rho_i) : (R)1;
+            for (int q = 0; q < 3; ++q) {
+                av[q] *= vfac;
+                as[q] /= mi;
+                const R gq = sizeof(R) == 8 ? (R)I.g[q] : (R)I.f_g[q];
+                a[q] = ap[q] + av[q] + as[q] + gq;
+            }
+        }
+        out.x = a[0]; out.y = a[1]; out.z = a[2];
+        ((R4<R>*)d.acc)[i] = out;
+        if (TERMS) {
+            R4<R>* T = (R4<R>*)d.terms;
+            R4<R> t;
+            t.w = 0;
+            t.x = fluid ? ap[0] : 0; t.y = fluid ? ap[1] : 0; t.z = fluid ? ap[2] : 0;
+            T[3 * (size_t)i + 0] = t;
+            t.x = av[0]; t.y = av[1]; t.z = av[2];
+            T[3 * (size_t)i + 1] = t;
+            t.x = as[0]; t.y = as[1]; t.z = as[2];
+            T[3 * (size_t)i + 2] = t;
+        }
+        if (!isfinite((double)out.x) || !isfinite((double)out.y) || !isfinite((double)out.z) ||
+            !isfinite((double)out.w))
+            atomicOr(d.status, ST_NONFINITE);
+        if (REDUCE) {
+            const uint32_t kind = info_kind(info);
+            if (kind != K_WALL) {
+                const double ux = vi.x, uy = vi.y, uz = vi.z;
+                umag2 = ux * ux + uy * uy + uz * uz;
+            }
+            if (fluid) amag2 = (double)a[0] * a[0] + (double)a[1] * a[1] + (double)a[2] * a[2];
+        }
+    }
+    // wave-level reductions: interaction count always, |u|^2 and |a|^2 maxima at S^n
+    const unsigned long long wsum = wave_sum(nint);
+    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(d.inter, wsum);
+    if (REDUCE) {
+        const uint32_t inst0 = __shfl(inst, 0, 64);
+        const bool uniform = __all(!valid || inst == inst0);
+        if (uniform) {
+            const double um = wave_max(umag2), am = wave_max(amag2);
+            if ((threadIdx.x & 63) == 0) {
+                atomicMax(&d.run[inst0].umax2, (unsigned long long)__double_as_longlong(um));
+                atomicMax(&d.run[inst0].amax2, (unsigned long long)__double_as_longlong(am));
+            }
+        } else if (valid) {
+            atomicMax(&d.run[inst].umax2, (unsigned long long)__double_as_longlong(umag2));
+            atomicMax(&d.run[inst].amax2, (unsigned long long)__double_as_longlong(amag2));
+        }
+    }
+}
+
+// ----------------------------------------------------------- time step (a9)
+
+__global__ void k_begin_step(Dev d)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= d.ninst) return;
+    d.run[b].umax2 = 0ull;
+    d.run[b].amax2 = 0ull;
+}
+
+__global__ void k_dt(Dev d, double dt_override)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= d.ninst) return;
+    const InstDev& I = d.inst[b];
+    InstRun& R = d.run[b];
+    const double umax = sqrt(__longlong_as_double((long long)R.umax2));
+    const double amax = sqrt(__longlong_as_double((long long)R.amax2));
+    double dt;
+    if (dt_override > 0.0) dt = dt_override;
+    else if (I.dt_fixed > 0.0) dt = I.dt_fixed;
+    else {
+        dt = I.c_cfl * I.h / (I.cmax + umax);
+        if (amax > 0.0) dt = fmin(dt, I.c_force * sqrt(I.h / amax));
+        dt = fmin(dt, I.dt_const);
+        if (umax > 0.0) dt = fmin(dt, 0.5 * I.skin / umax);
+    }
+    // the corrector reuses the cells of S^n: every pair within 2h at the predicted
+    // positions must still lie in neighbouring cells
+    if (dt * umax > 0.5 * I.skin * (1.0 + 1e-12) || !(dt > 0.0)) atomicOr(d.status, ST_DT);
+    R.dt = dt;
+    R.t_next = R.t + dt;
+}
+
+__global__ void k_finish(Dev d)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= d.ninst) return;
+    d.run[b].t = d.run[b].t_next;
+    d.run[b].step += 1;
+}
+
+// -------------------------------------------------------- integrator (a10)
+
+// Moving particle position at time t, written into a record of the set (FP64 absolute;
+// FP32 as the offset inside the particle's current cell).
+template <class R>
+__device__ __forceinline__ void moving_state(const InstDev& I, const double4& x0, uint32_t key, double t,
+                                             R4<R>& p, R4<R>& v)
+{
+    double dd, vv;
+    piston(I, t, dd, vv);
+    const double x[3] = {x0.x + dd, x0.y, x0.z};
+    if constexpr (sizeof(R) == 8) {
+        p.x = x[0]; p.y = x[1]; p.z = x[2];
+    } else {
+        int c[3];
+        cell_of_key(I, key, c);
+        p.x = (float)((x[0] - I.lo[0]) - (double)c[0] * I.cs[0]);
+        p.y = (float)((x[1] - I.lo[1]) - (double)c[1] * I.cs[1]);
+        p.z = (float)((x[2] - I.lo[2]) - (double)c[2] * I.cs[2]);
+    }
+    v.x = (R)vv; v.y = 0; v.z = 0;
+}
+
+__device__ __forceinline__ double wrap_coord(double x, const InstDev& I, int d)
+{
+    if (I.periodic[d]) {
+        if (x >= I.hi[d]) x -= I.span[d];
+        else if (x < I.lo[d]) x += I.span[d];
+    }
+    return x;
+}
+
+// Kahan-compensated s += y with the running compensation e.
+__device__ __forceinline__ void kahan_add(float& s, float& e, float y)
+{
+    const float yy = y + e;
+    const float t = s + yy;
+    e = yy - (t - s);
+    s = t;
+}
+
+// S* = S^n + dt/2 R(S^n)
+template <class R, int DIM>
+__global__ void k_predict(Dev d, int cur)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n) return;
+    const Sorted& O = d.O[cur];
+    const StateSet& S = d.S[cur];
+    const uint32_t info = O.info[k];
+    const uint32_t b = info_inst(info);
+    const InstDev& I = d.inst[b];
+    const double hdt = 0.5 * d.run[b].dt;
+    const uint32_t kind = info_kind(info);
+    R4<R> p = ((const R4<R>*)S.pos)[k];
+    R4<R> v = ((const R4<R>*)S.vel)[k];
+    R4<R> x = ((const R4<R>*)S.aux)[k];
+    const R4<R> a = ((const R4<R>*)d.acc)[k];
+    const R h = (R)hdt;
+    if (kind == K_FLUID) {
+        if constexpr (sizeof(R) == 8) {
+            p.x = wrap_coord(p.x + hdt * v.x, I, 0);
+            p.y = wrap_coord(p.y + hdt * v.y, I, 1);
+            p.z = DIM == 3 ? wrap_coord(p.z + hdt * v.z, I, 2) : p.z;
+        } else {
+            p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
+        }
+        v.x += h * a.x; v.y += h * a.y; v.z += h * a.z;
+    } else if (kind == K_MOVING) {
+        moving_state<R>(I, O.ref[k], O.key[k], d.run[b].t + hdt, p, v);
+    }
+    R r = ((const R*)S.rho)[k] + h * a.w;
+    derive_one<R>(I, info_phase(info), r, v, x);
+    ((R4<R>*)d.star.pos)[k] = p;
+    ((R4<R>*)d.star.vel)[k] = v;
+    ((R4<R>*)d.star.aux)[k] = x;
+    ((R*)d.star.rho)[k] = r;
+}
+
+// S^{n+1} = S^n + dt R(S*), in place
+template <class R, int DIM>
+__global__ void k_correct(Dev d, int cur)
+{
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= d.n) return;
+    const Sorted& O = d.O[cur];
+    const StateSet& S = d.S[cur];
+    const uint32_t info = O.info[k];
+    const uint32_t b = info_inst(info);
+    const InstDev& I = d.inst[b];
+    const double dt = d.run[b].dt;
+    const uint32_t kind = info_kind(info);
+    R4<R> p = ((const R4<R>*)S.pos)[k];
+    R4<R> v = ((const R4<R>*)S.vel)[k];
+    R4<R> x = ((const R4<R>*)S.aux)[k];
+    const R4<R> us = ((const R4<R>*)d.star.vel)[k];
+    const R4<R> a = ((const R4<R>*)d.acc)[k];
+    R r = ((const R*)S.rho)[k];
+    bool bad = false;
+    if constexpr (sizeof(R) == 8) {
+        if (kind == K_FLUID) {
+            p.x = wrap_coord(p.x + dt * us.x, I, 0);
+            p.y = wrap_coord(p.y + dt * us.y, I, 1);
+            p.z = DIM == 3 ? wrap_coord(p.z + dt * us.z, I, 2) : p.z;
+            v.x += dt * a.x; v.y += dt * a.y; v.z += dt * a.z;
+        } else if (kind == K_MOVING) {
+            moving_state<R>(I, O.ref[k], O.key[k], d.run[b].t_next, p, v);
+        }
+        r += dt * a.w;
+    } else {
+        const float fdt = (float)dt;
+        float4 pl = S.plo[k], vl = S.vlo[k];
+        if (kind == K_FLUID) {
+            kahan_add(p.x, pl.x, fdt * us.x);
+            kahan_add(p.y, pl.y, fdt * us.y);
+            if (DIM == 3) kahan_add(p.z, pl.z, fdt * us.z);
+            kahan_add(v.x, vl.x, fdt * a.x);
+            kahan_add(v.y, vl.y, fdt * a.y);
+            if (DIM == 3) kahan_add(v.z, vl.z, fdt * a.z);
+        } else if (kind == K_MOVING) {
+            moving_state<R>(I, O.ref[k], O.key[k], d.run[b].t_next, p, v);
+            pl.x = pl.y = pl.z = 0.0f;
+        }
+        kahan_add(r, pl.w, fdt * a.w);
+        S.plo[k] = pl;
+        S.vlo[k] = vl;
+    }
+    bad = !isfinite((double)p.x) || !isfinite((double)p.y) || !isfinite((double)p.z) ||
+          !isfinite((double)v.x) || !isfinite((double)v.y) || !isfinite((double)v.z) || !isfinite((double)r);
+    if (bad) atomicOr(d.status, ST_NONFINITE);
+    derive_one<R>(I, info_phase(info), r, v, x);
+    ((R4<R>*)S.pos)[k] = p;
+    ((R4<R>*)S.vel)[k] = v;
+    ((R4<R>*)S.aux)[k] = x;
+    ((R*)S.rho)[k] = r;
+}
+
+// ------------------------------------------------------- neighbour export
+
+template <class R, int DIM>
+__global__ void k_export(Dev d, int cur, int pass, const uint32_t* __restrict__ off, uint32_t* __restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= d.n) return;
+    const Sorted& O = d.O[cur];
+    const StateSet& S = d.S[cur];
+    const R4<R>* pos = (const R4<R>*)S.pos;
+    const InstDev& I = d.inst[info_inst(O.info[i])];
+    Lane<R> L;
+    L.load(I, pos[i], O.key[i]);
+    uint32_t c = 0;
+    const uint32_t base = pass ? off[i] : 0;
+    for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R*, R) {
+        if (pass) out[base + c] = O.id[k];
+        ++c;
+    });
+    if (!pass) out[i] = c;
+}
+
+// ================================================================ launchers
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <class R, int DIM>
+static void build_impl(const Dev& d, int cur, hipStream_t s)
+{
+    const int B = 256;
+    uint32_t* mask = d.cellmask + (size_t)cur * d.ncell;
+    uint32_t* mask_next = d.cellmask + (size_t)(1 - cur) * d.ncell;
+    hipLaunchKernelGGL((k_hash<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur, mask);
+    const uint32_t ntiles = (d.ncell + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(SCAN_THREADS), 0, s, d.cnt, d.ncell, d.scan_tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, d.scan_tmp, ntiles);
+    hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(SCAN_THREADS), 0, s, d.cnt, d.ncell, d.scan_tmp, d.cstart);
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur);
+    hipLaunchKernelGGL(k_rank, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
+    hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur, d.O[cur].ref ? 1 : 0);
+    hipLaunchKernelGGL((k_cellmix<DIM>), dim3(blocks_for(d.ncell, B)), dim3(B), 0, s, d, mask, mask_next);
+}
+
+#define SPHX_DISPATCH(PREC, DIM, CALL)                                  \
+    do {                                                                \
+        if ((PREC) == 0) {                                              \
+            if ((DIM) == 2) { using R = double; constexpr int D = 2; CALL; } \
+            else { using R = double; constexpr int D = 3; CALL; }       \
+        } else {                                                        \
+            if ((DIM) == 2) { using R = float; constexpr int D = 2; CALL; } \
+            else { using R = float; constexpr int D = 3; CALL; }        \
+        }                                                               \
+    } while (0)
+
+void launch_build(const Dev& d, int cur, const Launch&, hipStream_t s)
+{
+    SPHX_DISPATCH(d.precision, d.dim, (build_impl<R, D>(d, cur, s)));
+}
+
+void launch_renorm(const Dev& d, int cur, const Launch& L, hipStream_t s)
+{
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        hipLaunchKernelGGL((k_renorm<R, D>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, cur,
+                           L.xcd_remap);
+        hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur, 1);
+    }));
+}
+
+void launch_derive(const Dev& d, int cur, const Launch&, hipStream_t s)
+{
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur, 0);
+    }));
+}
+
+void launch_rates(const Dev& d, int cur, bool star, bool reduce_max, const Launch& L, hipStream_t s)
+{
+    const dim3 grid(blocks_for(d.n, L.block)), block(L.block);
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        hipLaunchKernelGGL((k_colour<R, D>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+        if (L.debug_terms) {
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, true>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, false, true>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+        } else {
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, false>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, false, false>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+        }
+    }));
+}
+
+void launch_begin_step(const Dev& d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_begin_step, dim3(blocks_for(d.ninst, 256)), dim3(256), 0, s, d);
+}
+
+void launch_dt(const Dev& d, double dt_override, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dt, dim3(blocks_for(d.ninst, 256)), dim3(256), 0, s, d, dt_override);
+}
+
+void launch_finish(const Dev& d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish, dim3(blocks_for(d.ninst, 256)), dim3(256), 0, s, d);
+}
+
+void launch_predict(const Dev& d, int cur, const Launch&, hipStream_t s)
+{
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        hipLaunchKernelGGL((k_predict<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur);
+    }));
+}
+
+void launch_correct(const Dev& d, int cur, const Launch&, hipStream_t s)
+{
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        hipLaunchKernelGGL((k_correct<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur);
+    }));
+}
+
+void launch_export(const Dev& d, int cur, int pass, const uint32_t* off, uint32_t* out, const Launch&,
+                   hipStream_t s)
+{
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        hipLaunchKernelGGL((k_export<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur, pass, off, out);
+    }));
+}
+
+} // namespace sphx

@@ -1,0 +1,241 @@
+"""GPU library against the FP64 oracle, through the C ABI.
+
+Bars: neighbour sets bit-exact in the FP64 form; rates and one full step
+within 1e-12 (FP64) and 1e-5 (FP32 cell-relative) in the E-norm of
+``tests/parity.py`` (positions in units of dx, density relative to rho0,
+velocity relative to the largest oracle speed).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1702_07760_amd import binding, inputs
+
+from parity import enorm, rel_to
+
+pytestmark = pytest.mark.gpu
+
+TOL = {binding.FP64: 1e-12, binding.FP32_CELLREL: 1e-5}
+PRECS = [binding.FP64, binding.FP32_CELLREL]
+
+
+def periodic_drop(dim, n=24, seed=11):
+    """Periodic two-phase box, jittered, with seeded velocities (no walls)."""
+    dx = 1e-3
+    c = (n * dx / 2,) * dim
+    s = inputs.lattice_box(dim, n, dx, periodic=True, oil=inputs.drop(dim, c, n * dx / 5),
+                           c0=5.0)
+    rng = np.random.default_rng(seed)
+    L = n * dx
+    s.x[:, :dim] = np.mod(s.x[:, :dim] + rng.uniform(-0.1 * dx, 0.1 * dx, (s.n, dim)), L)
+    s.u[:, :dim] = rng.uniform(-0.2, 0.2, (s.n, dim))
+    s.rho *= 1 + rng.uniform(-0.005, 0.005, s.n)
+    s.params[0]["alpha_s"] = 0.02
+    s.params[0]["gravity"] = [0.0, -9.81, 0.0] if dim == 2 else [0.0, 0.0, -9.81]
+    return s
+
+
+SCENES = {
+    "drop2d": lambda: inputs.drop2d(perturb=True),
+    "drop3d_small": lambda: inputs.drop3d(scale=0.3, perturb=True),
+    "periodic2d": lambda: periodic_drop(2),
+    "periodic3d": lambda: periodic_drop(3, 14),
+    "drop2d_eq11_eq5": lambda: inputs.drop2d(perturb=True).with_params(visc_form=1, cont_form=1),
+}
+
+
+@pytest.fixture(scope="module")
+def oracle_rates():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            s = SCENES[name]()
+            o = oracle.Oracle(s)
+            o.renormalize()
+            o.rates()
+            cache[name] = (s, {f: o.get(f) for f in (oracle.RHO, oracle.DRHO, oracle.A, oracle.AP,
+                                                      oracle.AV, oracle.AS, oracle.SDRHO,
+                                                      oracle.SAP, oracle.SAV, oracle.SAS,
+                                                      oracle.GRADC, oracle.P)}, o.neighbors())
+        return cache[name]
+    return get
+
+
+@pytest.mark.parametrize("name", ["drop2d", "drop3d_small", "periodic2d", "periodic3d"])
+def test_neighbour_sets_bit_exact_fp64(name, oracle_rates):
+    s, _, (off, ids) = oracle_rates(name)
+    print(f"case neighbours {name} n={s.n}", flush=True)
+    sim = binding.Sim(s, precision=binding.FP64)
+    goff, gids = sim.get_neighbors()
+    assert np.array_equal(goff, off)
+    assert np.array_equal(gids, ids)
+
+
+@pytest.mark.parametrize("name", ["drop2d", "drop3d_small", "periodic2d", "periodic3d"])
+def test_neighbour_sets_fp32_cell_relative(name, oracle_rates):
+    # FP32 offsets may move a pair across the cutoff only within rounding of 2h
+    s, _, (off, ids) = oracle_rates(name)
+    sim = binding.Sim(s, precision=binding.FP32_CELLREL)
+    goff, gids = sim.get_neighbors()
+    a = {(i, int(j)) for i in range(s.n) for j in ids[off[i]:off[i + 1]]}
+    b = {(i, int(j)) for i in range(s.n) for j in gids[goff[i]:goff[i + 1]]}
+    diff = a ^ b
+    x = s.x
+    h = s.params[0]["h"]
+    for i, j in diff:
+        r = np.linalg.norm(x[i] - x[j])
+        assert abs(r - 2 * h) < 1e-5 * h
+    assert len(diff) <= 1e-4 * len(a)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", list(SCENES))
+def test_rates_match_oracle(name, prec, oracle_rates):
+    s, ref, _ = oracle_rates(name)
+    print(f"case rates {name} precision={prec} n={s.n}", flush=True)
+    sim = binding.Sim(s, precision=prec)
+    sim.set_option(binding.OPT_DEBUG_TERMS, 1)
+    sim.renormalize_density()
+    sim.compute_forces()
+    sim.sync()
+    tol = TOL[prec]
+    rho0 = max(p[0] for p in s.phases[0])
+    assert rel_to(sim.get_field(binding.F_RHO), ref[oracle.RHO], rho0) < tol
+    assert enorm(sim.get_field(binding.F_DRHO), ref[oracle.DRHO], ref[oracle.SDRHO]) < tol
+    for f, g, sc in ((binding.F_AP, oracle.AP, oracle.SAP), (binding.F_AV, oracle.AV, oracle.SAV),
+                     (binding.F_AS, oracle.AS, oracle.SAS)):
+        if np.max(ref[sc]) > 0:
+            assert enorm(sim.get_field(f), ref[g], ref[sc]) < tol, f
+    total_scale = ref[oracle.SAP] + ref[oracle.SAV] + ref[oracle.SAS]
+    assert enorm(sim.get_field(binding.F_A), ref[oracle.A], total_scale) < tol
+    gref = ref[oracle.GRADC]
+    if np.abs(gref).max() > 0:
+        assert rel_to(sim.get_field(binding.F_GRADC), gref, np.abs(gref).max()) < 10 * tol
+    P = sim.get_field(binding.F_P)
+    assert rel_to(P, ref[oracle.P], np.abs(ref[oracle.P]).max()) < 10 * tol
+
+
+def _one_step(scene, prec, nsteps=1):
+    o = oracle.Oracle(scene)
+    o.step(nsteps)
+    sim = binding.Sim(scene, precision=prec)
+    sim.step(nsteps)
+    sim.sync()
+    return o, sim
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["drop2d", "drop3d_small", "periodic3d", "drop2d_eq11_eq5"])
+def test_one_step_matches_oracle(name, prec):
+    s = SCENES[name]()
+    print(f"case step {name} precision={prec} n={s.n}", flush=True)
+    o, sim = _one_step(s, prec)
+    dx = s.dx[0]
+    rho0 = max(p[0] for p in s.phases[0])
+    ur = np.abs(o.get(oracle.U)).max()
+    tol = TOL[prec]
+    assert abs(sim.stats()["t"] - o.t) <= 1e-6 * o.t if prec else abs(sim.stats()["t"] - o.t) <= 1e-13 * o.t
+    assert rel_to(sim.get_field(binding.F_X), o.get(oracle.X), dx) < tol
+    assert rel_to(sim.get_field(binding.F_U), o.get(oracle.U), ur) < tol
+    assert rel_to(sim.get_field(binding.F_RHO), o.get(oracle.RHO), rho0) < tol
+
+
+def test_neighbour_sets_stay_exact_after_gpu_steps():
+    # after GPU steps, the oracle rebuilt at the GPU's own positions finds the same sets
+    s = inputs.drop2d(perturb=True)
+    sim = binding.Sim(s, precision=binding.FP64)
+    sim.step(5)
+    s2 = inputs.drop2d(perturb=True)
+    s2.x[:] = sim.get_field(binding.F_X)
+    o = oracle.Oracle(s2)
+    off, ids = o.neighbors()
+    goff, gids = sim.get_neighbors()
+    assert np.array_equal(goff, off) and np.array_equal(gids, ids)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_steps_are_deterministic_and_graph_matches_eager(prec):
+    s = inputs.drop2d(perturb=True)
+    a = binding.Sim(s, precision=prec)
+    b = binding.Sim(s, precision=prec)
+    c = binding.Sim(s, precision=prec, graph=False)
+    for sim in (a, b, c):
+        sim.step(6)
+        sim.sync()
+    for f in (binding.F_X, binding.F_U, binding.F_RHO):
+        assert np.array_equal(a.get_field(f), b.get_field(f))
+        assert np.array_equal(a.get_field(f), c.get_field(f))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_checkpoint_round_trip_is_bit_identical(prec):
+    s = inputs.drop2d(perturb=True)
+    a = binding.Sim(s, precision=prec)
+    a.step(8)
+    b = binding.Sim(s, precision=prec)
+    b.step(4)
+    blob = b.get_state()
+    c = binding.Sim(s, precision=prec)
+    c.set_state(blob)
+    c.step(4)
+    for f in (binding.F_X, binding.F_U, binding.F_RHO):
+        assert np.array_equal(a.get_field(f), c.get_field(f))
+    assert a.stats()["steps"] == c.stats()["steps"] == 8
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_manual_calls_equal_one_step(prec):
+    # build / renormalise / forces / integrate through the separate entry points
+    s = inputs.drop2d(perturb=True)
+    a = binding.Sim(s, precision=prec)
+    a.step(1)
+    b = binding.Sim(s, precision=prec)
+    b.build_neighbors()
+    b.renormalize_density()
+    b.compute_forces()
+    b.integrate_step(0.0)
+    b.build_neighbors()
+    for f in (binding.F_X, binding.F_U, binding.F_RHO):
+        assert np.array_equal(a.get_field(f), b.get_field(f))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batched_instances_match_their_own_oracles(prec):
+    parts = [inputs.drop2d(perturb=True, dx=dx) for dx in (2.5e-3, 3.3e-3, 4e-3)]
+    parts[1].params[0]["alpha_s"] = 0.04
+    parts[2].phases[0][1] = (850.0, 1e-5, parts[2].phases[0][1][2])
+    scene = inputs.concat("batch", parts)
+    sim = binding.Sim(scene, precision=prec)
+    sim.step(2)
+    sim.sync()
+    x = sim.get_field(binding.F_X)
+    rho = sim.get_field(binding.F_RHO)
+    for b, part in enumerate(parts):
+        o = oracle.Oracle(part)
+        o.step(2)
+        a, e = scene.inst_offsets[b], scene.inst_offsets[b + 1]
+        assert rel_to(x[a:e], o.get(oracle.X), part.dx[0]) < TOL[prec]
+        assert rel_to(rho[a:e], o.get(oracle.RHO), 1000.0) < TOL[prec]
+
+
+def test_invalid_particles_are_rejected():
+    s = inputs.drop2d()
+    s.x[5, 0] = np.nan
+    with pytest.raises(binding.SphxError) as e:
+        binding.Sim(s)
+    assert e.value.code == 1
+    s = inputs.drop2d()
+    s.phase[s.kind == 1] = 1                       # walls must be water
+    with pytest.raises(binding.SphxError):
+        binding.Sim(s)
+
+
+def test_fixed_dt_violating_the_skin_is_reported():
+    s = inputs.drop2d(perturb=True).with_params(dt_fixed=1e-3)   # dt*max|u| >> skin
+    sim = binding.Sim(s, precision=binding.FP64)
+    sim.step(1)
+    with pytest.raises(binding.SphxError) as e:
+        sim.sync()
+    assert e.value.code == 8
+    sim.sync()                                      # sticky bits cleared by the report
