@@ -94,10 +94,21 @@ enum {
 /* Options for sphx_set_option. */
 enum {
     SPHX_OPT_DEBUG_TERMS = 1, /* 1: compute_forces also stores the three acceleration terms */
-    SPHX_OPT_BLOCK = 2,       /* threads per block of the neighbour passes: 64..1024, multiple of 64 */
+    SPHX_OPT_BLOCK = 2,       /* threads per block of the neighbour passes: 64, 128, 192 or 256 */
     SPHX_OPT_XCD_REMAP = 3,   /* 1: map consecutive particle tiles to one XCD (default 1) */
     SPHX_OPT_GRAPH = 4,       /* 1: sphx_step replays a captured hipGraph per step (default 1) */
-    SPHX_OPT_PERSISTENT = 5   /* >0: neighbour passes run as a persistent grid of this many blocks per CU */
+    SPHX_OPT_PROFILE = 6      /* 1: no graphs; every kernel group is bracketed by HIP events on the
+                                 context stream and its time is reported in sphx_stats */
+};
+
+/* Kernel groups timed under SPHX_OPT_PROFILE. */
+enum {
+    SPHX_PH_BUILD = 0,        /* hash, scan, sort, gather, cell flags */
+    SPHX_PH_RENORM = 1,       /* Eq. (7) and the state derivation after it */
+    SPHX_PH_COLOUR = 2,       /* Eq. (16) pass */
+    SPHX_PH_FORCE = 3,        /* Eqs. (6), (8), (10)/(11), (17) pass */
+    SPHX_PH_INTEGRATE = 4,    /* time step, predictor, corrector */
+    SPHX_NPH = 5
 };
 
 /* Run statistics, from the device after sphx_sync. */
@@ -108,6 +119,8 @@ typedef struct {
     int64_t interactions;     /* ordered pairs (i, j != i, r_ij < 2h) summed over every
                                  force evaluation since the last reset */
     int64_t ncells;           /* cells over all instances */
+    double phase_ms[5];       /* SPHX_OPT_PROFILE: summed event time per kernel group */
+    int64_t phase_launches[5];/* SPHX_OPT_PROFILE: timed launches per kernel group */
 } sphx_stats;
 
 /* Bytes of device workspace for ninst instances holding counts[b] particles. */

@@ -21,7 +21,8 @@ FP64, FP32_CELLREL = 0, 1
 MAX_PISTON = 16
 F_X, F_U, F_RHO, F_A, F_DRHO, F_AP, F_AV, F_AS, F_P, F_GRADC = 0, 1, 2, 3, 4, 5, 6, 7, 12, 13
 _VEC = {F_X, F_U, F_A, F_AP, F_AV, F_AS, F_GRADC}
-OPT_DEBUG_TERMS, OPT_BLOCK, OPT_XCD_REMAP, OPT_GRAPH = 1, 2, 3, 4
+OPT_DEBUG_TERMS, OPT_BLOCK, OPT_XCD_REMAP, OPT_GRAPH, OPT_PROFILE = 1, 2, 3, 4, 6
+PHASES = ("build", "renorm", "colour", "force", "integrate")
 STATUS = {0: "SPHX_OK", 1: "SPHX_E_ARG", 2: "SPHX_E_NODEV", 3: "SPHX_E_HIP", 4: "SPHX_E_WORKSPACE",
           5: "SPHX_E_STATE", 6: "SPHX_E_NONFINITE", 7: "SPHX_E_DOMAIN", 8: "SPHX_E_DT"}
 
@@ -48,7 +49,8 @@ class Phase(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("t", C.c_double), ("dt", C.c_double),
-                ("interactions", C.c_int64), ("ncells", C.c_int64)]
+                ("interactions", C.c_int64), ("ncells", C.c_int64),
+                ("phase_ms", C.c_double * 5), ("phase_launches", C.c_int64 * 5)]
 
 
 class SphxError(RuntimeError):
@@ -239,7 +241,9 @@ class Sim:
     def stats(self) -> dict:
         s = Stats()
         self._check(lib().sphx_get_stats(self.ctx, C.byref(s)), "sphx_get_stats")
-        return dict(steps=s.steps, t=s.t, dt=s.dt, interactions=s.interactions, ncells=s.ncells)
+        return dict(steps=s.steps, t=s.t, dt=s.dt, interactions=s.interactions, ncells=s.ncells,
+                    phase_ms={k: s.phase_ms[q] for q, k in enumerate(PHASES)},
+                    phase_launches={k: s.phase_launches[q] for q, k in enumerate(PHASES)})
 
     def reset_interactions(self):
         self._check(lib().sphx_reset_interactions(self.ctx), "sphx_reset_interactions")

@@ -35,6 +35,10 @@ struct sphx_ctx {
     int renorm_every = 1;
     bool use_graph = true;
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    bool profile = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;   // (group, start/stop)
+    double phase_ms[SPHX_NPH] = {0, 0, 0, 0, 0};
+    int64_t phase_launches[SPHX_NPH] = {0, 0, 0, 0, 0};
     std::string err;
 };
 
@@ -139,6 +143,11 @@ InstDev make_inst(const sphx_params& p, const sphx_phase* ph2, int nphase, uint3
     I.h = h;
     I.inv_h = 1.0 / h;
     I.cut2 = 4.0 * h * h;
+    // neighbour-list radius: 2h plus half the skin (the most two particles can close in
+    // on each other between the list build and the predicted state), with a margin far
+    // above FP32 rounding
+    const double rl = (2.0 + 0.5 * p.skin_coef) * h;
+    I.cutl2 = rl * rl * (1.0 + 2e-5);
     I.wcoef = alpha;
     I.fcoef = -5.0 * alpha / (h * h);
     const double delta = p.delta_coef * h;
@@ -187,6 +196,7 @@ InstDev make_inst(const sphx_params& p, const sphx_phase* ph2, int nphase, uint3
     }
     I.f_inv_h = (float)I.inv_h;
     I.f_cut2 = (float)I.cut2;
+    I.f_cutl2 = (float)I.cutl2;
     I.f_fcoef = (float)I.fcoef;
     I.f_wcoef = (float)I.wcoef;
     I.f_delta2 = (float)I.delta2;
@@ -212,7 +222,10 @@ struct Carver {
 };
 
 // Lays every device array out in the workspace (or only measures when base is null).
-size_t carve(Dev& d, void* base, int precision, int64_t n, uint32_t ncell, int ninst)
+// Neighbour-list capacity per particle (lattice: 20 / 80 neighbours within 2h in 2D / 3D).
+uint32_t list_cap(int dim) { return dim == 3 ? 128u : 48u; }
+
+size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t ncell, int ninst)
 {
     Carver c(base);
     const size_t R = precision == 0 ? 8 : 4;
@@ -224,8 +237,10 @@ size_t carve(Dev& d, void* base, int precision, int64_t n, uint32_t ncell, int n
     d.cnt = c.take<uint32_t>(ncell);
     d.cstart = c.take<uint32_t>((size_t)ncell + 1);
     d.scan_tmp = c.take<uint32_t>((ncell + 2047) / 2048 + 1);
-    d.cellmask = c.take<uint32_t>((size_t)ncell * 2);
-    d.cellmix = c.take<uint8_t>(ncell);
+    d.cap = list_cap(dim);
+    d.nbl = c.take<uint32_t>(un * d.cap);
+    d.nbc = c.take<uint32_t>(un);
+    d.nbx = c.take<uint8_t>(un);
     d.newkey = c.take<uint32_t>(un);
     d.slot = c.take<uint32_t>(un);
     d.tsrc = c.take<uint32_t>(un);
@@ -288,27 +303,88 @@ sphx_status status_of(sphx_ctx* c)
     return SPHX_OK;
 }
 
+// Brackets the launches of one kernel group with events when profiling.
+struct Timed {
+    sphx_ctx* c;
+    int group;
+    hipEvent_t a = nullptr, b = nullptr;
+    Timed(sphx_ctx* ctx, int g) : c(ctx), group(g)
+    {
+        if (c->profile && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, c->stream);
+    }
+    ~Timed()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->events.push_back({group, {a, b}});
+        }
+    }
+};
+
+void collect_events(sphx_ctx* c)
+{
+    for (auto& e : c->events) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e.second.first, e.second.second) == hipSuccess) {
+            c->phase_ms[e.first] += ms;
+            c->phase_launches[e.first] += 1;
+        }
+        (void)hipEventDestroy(e.second.first);
+        (void)hipEventDestroy(e.second.second);
+    }
+    c->events.clear();
+}
+
 void enqueue_build(sphx_ctx* c)
 {
-    launch_build(c->dev, c->cur, c->launch, c->stream);
+    {
+        Timed t(c, SPHX_PH_BUILD);
+        launch_build(c->dev, c->cur, c->launch, c->stream);
+    }
     c->cur = 1 - c->cur;
+}
+
+void enqueue_rates(sphx_ctx* c, bool star, bool reduce)
+{
+    {
+        Timed t(c, SPHX_PH_COLOUR);
+        launch_colour(c->dev, c->cur, star, c->launch, c->stream);
+    }
+    Timed t(c, SPHX_PH_FORCE);
+    launch_force(c->dev, c->cur, star, reduce, c->launch, c->stream);
 }
 
 void enqueue_integrate(sphx_ctx* c, double dt_override)
 {
-    launch_dt(c->dev, dt_override, c->stream);
-    launch_predict(c->dev, c->cur, c->launch, c->stream);
-    launch_rates(c->dev, c->cur, true, false, c->launch, c->stream);
+    {
+        Timed t(c, SPHX_PH_INTEGRATE);
+        launch_dt(c->dev, dt_override, c->stream);
+        launch_predict(c->dev, c->cur, c->launch, c->stream);
+    }
+    enqueue_rates(c, true, false);
+    Timed t(c, SPHX_PH_INTEGRATE);
     launch_correct(c->dev, c->cur, c->launch, c->stream);
     launch_finish(c->dev, c->stream);
+}
+
+void enqueue_renorm(sphx_ctx* c)
+{
+    Timed t(c, SPHX_PH_RENORM);
+    launch_renorm(c->dev, c->cur, c->launch, c->stream);
+}
+
+void enqueue_forces(sphx_ctx* c)
+{
+    launch_begin_step(c->dev, c->stream);
+    enqueue_rates(c, false, true);
 }
 
 // One full step from a valid neighbour structure; ends with a rebuilt one.
 void enqueue_step(sphx_ctx* c, bool renorm)
 {
-    if (renorm) launch_renorm(c->dev, c->cur, c->launch, c->stream);
-    launch_begin_step(c->dev, c->stream);
-    launch_rates(c->dev, c->cur, false, true, c->launch, c->stream);
+    if (renorm) enqueue_renorm(c);
+    enqueue_forces(c);
     enqueue_integrate(c, 0.0);
     enqueue_build(c);
 }
@@ -351,7 +427,6 @@ std::vector<Span> state_spans(sphx_ctx* c)
     std::vector<Span> v = {
         {d.S[s].pos, n * 4 * R}, {d.S[s].vel, n * 4 * R}, {d.S[s].aux, n * 4 * R}, {d.S[s].rho, n * R},
         {d.O[s].key, n * 4}, {d.O[s].id, n * 4}, {d.O[s].info, n * 4}, {d.cstart, ((size_t)c->ncell + 1) * 4},
-        {d.cellmix, c->ncell},
         {d.run, sizeof(InstRun) * c->ninst}, {d.acc, n * 4 * R}, {d.gc, n * 4 * R}};
     if (c->precision) {
         v.push_back({d.S[s].plo, n * 16});
@@ -379,7 +454,7 @@ size_t sphx_workspace_size(int32_t precision, const sphx_params* per_inst, int32
     std::string why;
     if (!setup_cells(per_inst, ninst, base, total, why)) return 0;
     Dev d{};
-    return carve(d, nullptr, precision, n, total, ninst);
+    return carve(d, nullptr, precision, per_inst[0].dim, n, total, ninst);
 }
 
 sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sphx_phase* phases, int32_t nphase,
@@ -396,7 +471,7 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
         if (counts[b] < 1) return SPHX_E_ARG;
         n += counts[b];
     }
-    if (n >= (1ll << 31)) return SPHX_E_ARG;
+    if (n >= (1ll << 26)) return SPHX_E_ARG;   // neighbour-list entries hold 26-bit indices
     std::string why;
     for (int b = 0; b < ninst; ++b) {
         if (!check_params(per_inst[b], per_inst[0].dim, why)) return SPHX_E_ARG;
@@ -447,6 +522,8 @@ void sphx_destroy(sphx_ctx* c)
 {
     if (!c) return;
     drop_graphs(c);
+    if (c->stream || c->bound) (void)hipStreamSynchronize(c->stream);
+    collect_events(c);
     delete c;
 }
 
@@ -457,11 +534,11 @@ sphx_status sphx_bind_workspace(sphx_ctx* c, void* dev_ptr, size_t bytes)
     if (!c) return SPHX_E_ARG;
     if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(c, SPHX_E_WORKSPACE, "workspace must be non-null and 256-byte aligned");
     Dev d{};
-    const size_t need = carve(d, nullptr, c->precision, c->n, c->ncell, c->ninst);
+    const size_t need = carve(d, nullptr, c->precision, c->dim, c->n, c->ncell, c->ninst);
     if (bytes < need) return fail(c, SPHX_E_WORKSPACE, "workspace too small: %zu < %zu bytes", bytes, need);
     drop_graphs(c);
     c->dev = Dev{};
-    carve(c->dev, dev_ptr, c->precision, c->n, c->ncell, c->ninst);
+    carve(c->dev, dev_ptr, c->precision, c->dim, c->n, c->ncell, c->ninst);
     c->dev.precision = c->precision;
     c->dev.dim = c->dim;
     c->dev.ninst = c->ninst;
@@ -527,7 +604,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
             key[i] = I.cell_base + (uint32_t)cc[0] + (uint32_t)I.nc[0] * ((uint32_t)cc[1] + (uint32_t)I.nc[1] * (uint32_t)cc[2]);
             const double r0 = I.rho0[phase[i]];
             if (!f32) {
-                ((double4*)pos.data())[i] = make_double4(xi[0], xi[1], xi[2], 0.0);
+                ((double4*)pos.data())[i] = make_double4(xi[0], xi[1], xi[2], (double)phase[i]);
                 ((double4*)vel.data())[i] = make_double4(u[3 * i], c->dim > 1 ? u[3 * i + 1] : 0.0, c->dim > 2 ? u[3 * i + 2] : 0.0, 0.0);
                 ((double4*)aux.data())[i] = make_double4(m[i], 0.0, 0.0, 0.0);
                 ((double*)rh.data())[i] = rho[i];
@@ -543,7 +620,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
                 }
                 const double dr = rho[i] - r0;
                 const float drf = (float)dr;
-                uint32_t kb = key[i];
+                uint32_t kb = key[i] | ((uint32_t)phase[i] << 31);
                 float kf;
                 std::memcpy(&kf, &kb, 4);
                 ((float4*)pos.data())[i] = make_float4(o[0], o[1], o[2], kf);
@@ -564,7 +641,6 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemsetAsync(d.status, 0, sizeof(uint32_t), s));
     HIP_OK(c, hipMemsetAsync(d.inter, 0, sizeof(unsigned long long), s));
     HIP_OK(c, hipMemsetAsync(d.cnt, 0, sizeof(uint32_t) * c->ncell, s));
-    HIP_OK(c, hipMemsetAsync(d.cellmask, 0, sizeof(uint32_t) * 2 * (size_t)c->ncell, s));
     HIP_OK(c, hipMemsetAsync(d.acc, 0, n * 4 * R, s));
     HIP_OK(c, hipMemsetAsync(d.gc, 0, n * 4 * R, s));
     HIP_OK(c, hipMemsetAsync(d.terms, 0, n * 12 * R, s));
@@ -586,7 +662,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
         d.O[1].ref = nullptr;
     } else {
         Dev tmp{};
-        carve(tmp, c->ws, c->precision, c->n, c->ncell, c->ninst);
+        carve(tmp, c->ws, c->precision, c->dim, c->n, c->ncell, c->ninst);
         d.O[0].ref = tmp.O[0].ref;
         d.O[1].ref = tmp.O[1].ref;
     }
@@ -618,7 +694,7 @@ sphx_status sphx_renormalize_density(sphx_ctx* c)
     if (!c) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
     if (!c->nb_valid) enqueue_build(c), c->nb_valid = true;
-    launch_renorm(c->dev, c->cur, c->launch, c->stream);
+    enqueue_renorm(c);
     c->rates_valid = false;
     HIP_OK(c, hipGetLastError());
     return SPHX_OK;
@@ -629,8 +705,7 @@ sphx_status sphx_compute_forces(sphx_ctx* c)
     if (!c) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
     if (!c->nb_valid) enqueue_build(c), c->nb_valid = true;
-    launch_begin_step(c->dev, c->stream);
-    launch_rates(c->dev, c->cur, false, true, c->launch, c->stream);
+    enqueue_forces(c);
     c->rates_valid = true;
     HIP_OK(c, hipGetLastError());
     return SPHX_OK;
@@ -662,7 +737,7 @@ sphx_status sphx_step(sphx_ctx* c, int32_t nsteps)
     for (int32_t k = 0; k < nsteps; ++k) {
         const bool due = renorm_due(c, c->step_host);
         const int cur = c->cur;
-        if (c->use_graph) {
+        if (c->use_graph && !c->profile) {
             hipGraphExec_t& g = c->graph[cur][due ? 1 : 0];
             if (!g) {
                 hipGraph_t graph = nullptr;
@@ -706,11 +781,18 @@ sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
     switch (option) {
     case SPHX_OPT_DEBUG_TERMS: c->launch.debug_terms = value != 0; break;
     case SPHX_OPT_BLOCK:
-        if (value < 64 || value > 1024 || value % 64) return fail(c, SPHX_E_ARG, "block must be a multiple of 64 in [64, 1024]");
+        if (value < 64 || value > 256 || value % 64) return fail(c, SPHX_E_ARG, "block must be 64, 128, 192 or 256");
         c->launch.block = (int)value;
         break;
     case SPHX_OPT_XCD_REMAP: c->launch.xcd_remap = value != 0; break;
     case SPHX_OPT_GRAPH: c->use_graph = value != 0 && c->stream != nullptr; break;
+    case SPHX_OPT_PROFILE:
+        c->profile = value != 0;
+        for (int q = 0; q < SPHX_NPH; ++q) {
+            c->phase_ms[q] = 0;
+            c->phase_launches[q] = 0;
+        }
+        break;
     default: return fail(c, SPHX_E_ARG, "unknown option %d", (int)option);
     }
     drop_graphs(c);
@@ -738,6 +820,11 @@ sphx_status sphx_get_stats(sphx_ctx* c, sphx_stats* out)
     out->dt = r.dt;
     out->interactions = (int64_t)inter;
     out->ncells = c->ncell;
+    collect_events(c);
+    for (int q = 0; q < SPHX_NPH; ++q) {
+        out->phase_ms[q] = c->phase_ms[q];
+        out->phase_launches[q] = c->phase_launches[q];
+    }
     return st;
 }
 
@@ -971,9 +1058,10 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
         HIP_OK(c, hipMemcpy(s.p, p, s.bytes, hipMemcpyHostToDevice));
         p += s.bytes;
     }
-    // the next build (from set cur) accumulates into the cell mask of parity cur
-    HIP_OK(c, hipMemset(c->dev.cellmask + (size_t)c->cur * c->ncell, 0, (size_t)c->ncell * 4));
     HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * 4));
+    // the neighbour list is a function of the restored positions and cell table
+    launch_nlist(c->dev, c->cur, c->launch, c->stream);
+    HIP_OK(c, hipStreamSynchronize(c->stream));
     c->step_host = h.step_host;
     c->nb_valid = h.nb_valid != 0;
     c->rates_valid = h.rates_valid != 0;

@@ -28,7 +28,7 @@ struct InstDev {
     int32_t periodic[3];
     uint32_t cell_base, ncell;
     int32_t dim, visc_form, cont_form, renorm_every;
-    double h, inv_h, cut2, wcoef, fcoef, delta2, alpha_s, skin;
+    double h, inv_h, cut2, cutl2, wcoef, fcoef, delta2, alpha_s, skin;
     double g[3];
     double rho0[2], beta[2], nu[2];
     double vpair[2][2];   // 2 nu_ij (Eq. (10)) or 2 mu_ij (Eq. (11)) by phase pair
@@ -37,7 +37,7 @@ struct InstDev {
     double piston_t_end;
     double pa[kMaxPiston], pw[kMaxPiston], pphi[kMaxPiston];
     // FP32 copies for the cell-relative kernels
-    float f_cs[3], f_inv_h, f_cut2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3];
+    float f_cs[3], f_inv_h, f_cut2, f_cutl2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3];
     float f_vpair[2][2], f_rho0[2];
 };
 
@@ -85,8 +85,11 @@ struct Dev {
     uint32_t* tsrc;      // n
     uint32_t* tid;       // n
     uint32_t* perm;      // n
-    uint32_t* cellmask;  // 2 x ncell: phases present (one mask per build parity)
-    uint8_t* cellmix;    // ncell: both phases within the 3^d cell neighbourhood
+    // neighbour list of the current sort order, column-major: entry q of i at q * n + i
+    uint32_t* nbl;       // n * cap entries (index | cell-offset code << 26)
+    uint32_t* nbc;       // n counts (> cap: overflowed, the passes walk the stencil)
+    uint8_t* nbx;        // n: an other-phase particle is in the list
+    uint32_t cap;
     // state
     StateSet S[2];       // double-buffered current state
     Sorted O[2];
@@ -95,7 +98,6 @@ struct Dev {
     void* acc;           // R4: (ax, ay, az, drho)
     void* gc;            // R4: (gx, gy, gz, |g|)
     void* terms;         // 3 x R4 per particle (debug)
-    double4* newref;     // unused placeholder
 };
 
 struct Launch {
@@ -107,9 +109,11 @@ struct Launch {
 };
 
 // --- launchers (sphx_kernels.hip); all asynchronous on the given stream ---
-void launch_build(const Dev& d, int cur, const Launch& L, hipStream_t s);   // S[cur] -> S[1-cur]
+void launch_build(const Dev& d, int cur, const Launch& L, hipStream_t s);   // S[cur] -> S[1-cur], + list
+void launch_nlist(const Dev& d, int cur, const Launch& L, hipStream_t s);
 void launch_renorm(const Dev& d, int cur, const Launch& L, hipStream_t s);
-void launch_rates(const Dev& d, int cur, bool star, bool reduce_max, const Launch& L, hipStream_t s);
+void launch_colour(const Dev& d, int cur, bool star, const Launch& L, hipStream_t s);
+void launch_force(const Dev& d, int cur, bool star, bool reduce_max, const Launch& L, hipStream_t s);
 void launch_dt(const Dev& d, double dt_fixed_override, hipStream_t s);
 void launch_predict(const Dev& d, int cur, const Launch& L, hipStream_t s);
 void launch_correct(const Dev& d, int cur, const Launch& L, hipStream_t s);

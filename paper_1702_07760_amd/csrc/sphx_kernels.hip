@@ -103,8 +103,16 @@ template <> struct Lane<float> {
     }
 };
 
-// Per-row constants (the y/z cell offsets of a stencil row are fixed).
-template <class R> struct Row { R y, z; uint32_t base; };
+// Per-row constants: the y/z cell offsets of a stencil row are fixed.
+template <class R> struct Row {
+    uint32_t base;   // key of the row's first cell
+    uint32_t code;   // (delta_y + 1) << 2 | (delta_z + 1) << 4, delta = c_i - c_j
+    float dy, dz;    // delta_y, delta_z as floats
+};
+
+// Neighbour-list entry: particle index in the low 26 bits, the cell offset
+// delta = c_i - c_j (each component in {-1, 0, 1}, stored + 1) in the top 6 bits.
+constexpr uint32_t kIdxBits = 26, kIdxMask = (1u << kIdxBits) - 1u;
 
 template <int DIM>
 __device__ __forceinline__ double dist2(double rx, double ry, double rz)
@@ -129,39 +137,77 @@ __device__ __forceinline__ double min_image(double v, const InstDev& I, int d)
     return v;
 }
 
-// r_ij for candidate record pj (FP64: absolute positions, minimal image).
+// Phase of a particle, carried in the w slot of its position record
+// (FP64: as a number; FP32: bit 31 above the cell key).
+__device__ __forceinline__ uint32_t pos_phase(const double4& p) { return (uint32_t)p.w; }
+__device__ __forceinline__ uint32_t pos_phase(const float4& p) { return __float_as_uint(p.w) >> 31; }
+
+// r_ij for a stencil candidate (FP64: absolute positions, minimal image).  Returns the
+// list-entry offset code (unused in FP64).
 template <int DIM>
-__device__ __forceinline__ void pair_r(const InstDev& I, const Lane<double>& L, const Row<double>&,
-                                       const double4& pj, double r[3])
+__device__ __forceinline__ uint32_t pair_r(const InstDev& I, const Lane<double>& L, const Row<double>&,
+                                           const double4& pj, double r[3])
+{
+    r[0] = min_image(L.x[0] - pj.x, I, 0);
+    r[1] = min_image(L.x[1] - pj.y, I, 1);
+    r[2] = DIM == 3 ? min_image(L.x[2] - pj.z, I, 2) : 0.0;
+    return 0u;
+}
+
+// r_ij for a stencil candidate (FP32: cell offsets; pj.w holds j's cell key).
+template <int DIM>
+__device__ __forceinline__ uint32_t pair_r(const InstDev& I, const Lane<float>& L, const Row<float>& row,
+                                           const float4& pj, float r[3])
+{
+    int dcx = L.c[0] - (int)((__float_as_uint(pj.w) & 0x7fffffffu) - row.base);
+    if (I.periodic[0]) dcx = dcx > 1 ? dcx - I.nc[0] : (dcx < -1 ? dcx + I.nc[0] : dcx);
+    r[0] = fmaf((float)dcx, I.f_cs[0], L.o[0] - pj.x);
+    r[1] = fmaf(row.dy, I.f_cs[1], L.o[1] - pj.y);
+    r[2] = DIM == 3 ? fmaf(row.dz, I.f_cs[2], L.o[2] - pj.z) : 0.0f;
+    return (uint32_t)(dcx + 1) | row.code;
+}
+
+// r_ij for a list entry e (same arithmetic as the stencil form above).
+template <int DIM>
+__device__ __forceinline__ void list_pair_r(const InstDev& I, const Lane<double>& L, const double4& pj,
+                                            uint32_t, double r[3])
 {
     r[0] = min_image(L.x[0] - pj.x, I, 0);
     r[1] = min_image(L.x[1] - pj.y, I, 1);
     r[2] = DIM == 3 ? min_image(L.x[2] - pj.z, I, 2) : 0.0;
 }
 
-// r_ij for candidate record pj (FP32: cell offsets; pj.w holds j's cell key).
 template <int DIM>
-__device__ __forceinline__ void pair_r(const InstDev& I, const Lane<float>& L, const Row<float>& row,
-                                       const float4& pj, float r[3])
+__device__ __forceinline__ void list_pair_r(const InstDev& I, const Lane<float>& L, const float4& pj,
+                                            uint32_t e, float r[3])
 {
-    int dcx = L.c[0] - (int)(__float_as_uint(pj.w) - row.base);
-    if (I.periodic[0]) dcx = dcx > 1 ? dcx - I.nc[0] : (dcx < -1 ? dcx + I.nc[0] : dcx);
-    r[0] = fmaf((float)dcx, I.f_cs[0], L.o[0] - pj.x);
-    r[1] = row.y - pj.y;
-    r[2] = DIM == 3 ? row.z - pj.z : 0.0f;
+    const float dx = (float)((int)((e >> 26) & 3u) - 1);
+    const float dy = (float)((int)((e >> 28) & 3u) - 1);
+    const float dz = (float)((int)(e >> 30) - 1);
+    r[0] = fmaf(dx, I.f_cs[0], L.o[0] - pj.x);
+    r[1] = fmaf(dy, I.f_cs[1], L.o[1] - pj.y);
+    r[2] = DIM == 3 ? fmaf(dz, I.f_cs[2], L.o[2] - pj.z) : 0.0f;
 }
 
 template <class R> __device__ __forceinline__ R cut2_of(const InstDev& I);
 template <> __device__ __forceinline__ double cut2_of<double>(const InstDev& I) { return I.cut2; }
 template <> __device__ __forceinline__ float cut2_of<float>(const InstDev& I) { return I.f_cut2; }
+template <class R> __device__ __forceinline__ R cutl2_of(const InstDev& I);
+template <> __device__ __forceinline__ double cutl2_of<double>(const InstDev& I) { return I.cutl2; }
+template <> __device__ __forceinline__ float cutl2_of<float>(const InstDev& I) { return I.f_cutl2; }
 
-// Visit every j != i with |r_ij|^2 < 4h^2 among the 3^d cells around i's cell.
+// Candidates loaded per batch in the stencil walk (independent loads in flight).
+template <class R> struct StencilBatch { static constexpr int U = 8; };
+template <> struct StencilBatch<double> { static constexpr int U = 4; };
+
+// Visit every j != i with |r_ij|^2 < cut2 among the 3^d cells around i's cell:
+// body(j, r_ij, |r_ij|^2, record of j, list code).
 template <class R, int DIM, class Body>
 __device__ __forceinline__ void for_neighbors(const InstDev& I, const uint32_t* __restrict__ cstart,
                                               const R4<R>* __restrict__ pos, uint32_t i,
-                                              const Lane<R>& L, Body&& body)
+                                              const Lane<R>& L, R cut2, Body&& body)
 {
-    const R cut2 = cut2_of<R>(I);
+    constexpr int U = StencilBatch<R>::U;
     const int nx = I.nc[0];
     const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
@@ -176,11 +222,9 @@ __device__ __forceinline__ void for_neighbors(const InstDev& I, const uint32_t* 
             else if (cy < 0 || cy >= I.nc[1]) continue;
             Row<R> row;
             row.base = I.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)I.nc[1] * (uint32_t)cz);
-            if constexpr (sizeof(R) == 4) {
-                const Lane<float>& Lf = reinterpret_cast<const Lane<float>&>(L);
-                row.y = Lf.o[1] - (float)dy * I.f_cs[1];
-                row.z = DIM == 3 ? Lf.o[2] - (float)dz * I.f_cs[2] : 0.0f;
-            }
+            row.code = (uint32_t)(1 - dy) << 2 | (uint32_t)(1 - dz) << 4;
+            row.dy = (float)(-dy);
+            row.dz = (float)(-dz);
             uint32_t a0, b0, a1 = 0, b1 = 0;
             const int x0 = L.c[0] - 1, x1 = L.c[0] + 1;
             if (!I.periodic[0]) {
@@ -202,15 +246,77 @@ __device__ __forceinline__ void for_neighbors(const InstDev& I, const uint32_t* 
             }
             for (int seg = 0; seg < 2; ++seg) {
                 const uint32_t a = seg ? a1 : a0, b = seg ? b1 : b0;
-                for (uint32_t k = a; k < b; ++k) {
-                    const R4<R> pj = pos[k];
-                    R r[3];
-                    pair_r<DIM>(I, L, row, pj, r);
-                    const R r2 = dist2<DIM>(r[0], r[1], r[2]);
-                    if (r2 < cut2 && k != i) body(k, r, r2);
+                for (uint32_t k0 = a; k0 < b; k0 += U) {
+                    R4<R> pj[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) pj[u] = pos[min(k0 + (uint32_t)u, b - 1)];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const uint32_t k = k0 + (uint32_t)u;
+                        if (k < b && k != i) {
+                            R r[3];
+                            const uint32_t code = pair_r<DIM>(I, L, row, pj[u], r);
+                            const R r2 = dist2<DIM>(r[0], r[1], r[2]);
+                            if (r2 < cut2) body(k, r, r2, pj[u], code);
+                        }
+                    }
                 }
             }
         }
+    }
+}
+
+struct NoExtra {};
+
+// Visit the entries of i's neighbour list with |r_ij|^2 < 4h^2 at the positions `pos`:
+// body(j, r_ij, |r_ij|^2, record of j, load(j)).  U entries are fetched per batch so
+// that their loads are in flight together; entries are stored column-major (entry q of
+// particle i at q * n + i), so a wave reads each batch coalesced.
+template <class R, int DIM, int U, class Load, class Body>
+__device__ __forceinline__ void for_list(const Dev& d, const InstDev& I, const R4<R>* __restrict__ pos,
+                                         uint32_t i, const Lane<R>& L, uint32_t cnt, Load&& load, Body&& body)
+{
+    using X = decltype(load(0u));
+    const uint32_t* __restrict__ nb = d.nbl + i;
+    const size_t n = (size_t)d.n;
+    const R cut2 = cut2_of<R>(I);
+    for (uint32_t q0 = 0; q0 < cnt; q0 += U) {
+        uint32_t e[U];
+        R4<R> pj[U];
+        X x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) e[u] = nb[(size_t)min(q0 + (uint32_t)u, cnt - 1) * n];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t k = e[u] & kIdxMask;
+            pj[u] = pos[k];
+            x[u] = load(k);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (q0 + (uint32_t)u < cnt) {
+                R r[3];
+                list_pair_r<DIM>(I, L, pj[u], e[u], r);
+                const R r2 = dist2<DIM>(r[0], r[1], r[2]);
+                if (r2 < cut2) body(e[u] & kIdxMask, r, r2, pj[u], x[u]);
+            }
+        }
+    }
+}
+
+// Either the list (normal case) or, for a particle whose list overflowed, the stencil.
+template <class R, int DIM, int U, class Load, class Body>
+__device__ __forceinline__ void for_each_neighbor(const Dev& d, const InstDev& I, const R4<R>* __restrict__ pos,
+                                                  uint32_t i, const Lane<R>& L, Load&& load, Body&& body)
+{
+    const uint32_t cnt = d.nbc[i];
+    if (cnt <= d.cap) {
+        for_list<R, DIM, U>(d, I, pos, i, L, cnt, load, body);
+    } else {
+        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, cut2_of<R>(I),
+                              [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t) {
+                                  body(k, r, r2, pj, load(k));
+                              });
     }
 }
 
@@ -221,7 +327,7 @@ __device__ __forceinline__ void for_neighbors(const InstDev& I, const uint32_t* 
 // the compensation term.  Each particle bumps its cell counter (the returned
 // value is its provisional slot) and marks its phase in the cell mask.
 template <class R, int DIM>
-__global__ void k_hash(Dev d, int cur, uint32_t* __restrict__ cellmask)
+__global__ void k_hash(Dev d, int cur)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n) return;
@@ -283,7 +389,6 @@ __global__ void k_hash(Dev d, int cur, uint32_t* __restrict__ cellmask)
                          (uint32_t)I.nc[0] * ((uint32_t)c[1] + (uint32_t)I.nc[1] * (uint32_t)c[2]);
     d.newkey[k] = key;
     d.slot[k] = atomicAdd(&d.cnt[key], 1u);
-    atomicOr(&cellmask[key], 1u << info_phase(info));
 }
 
 // a4 (cell start table): exclusive scan of the per-cell counts in three passes.
@@ -405,7 +510,7 @@ __global__ void k_gather(Dev d, int cur, int with_ref)
     const StateSet& SA = d.S[cur];
     const StateSet& SB = d.S[nxt];
     R4<R> p = ((const R4<R>*)SA.pos)[src];
-    if constexpr (sizeof(R) == 4) p.w = __uint_as_float(key);
+    if constexpr (sizeof(R) == 4) p.w = __uint_as_float(key | (info_phase(A.info[src]) << 31));
     ((R4<R>*)SB.pos)[k] = p;
     ((R4<R>*)SB.vel)[k] = ((const R4<R>*)SA.vel)[src];
     ((R4<R>*)SB.aux)[k] = ((const R4<R>*)SA.aux)[src];
@@ -416,37 +521,35 @@ __global__ void k_gather(Dev d, int cur, int with_ref)
     }
 }
 
-// Per cell: do both phases occur among the 3^d surrounding cells?  Also clears the
-// other parity's mask for the next build.
-template <int DIM>
-__global__ void k_cellmix(Dev d, const uint32_t* __restrict__ mask, uint32_t* __restrict__ mask_next)
+// Neighbour list at the positions of S[cur]: every j within the list radius
+// (2h plus half the skin, with a rounding margin), so that the same list holds every
+// pair within 2h at the predicted positions of the step as well.  Also flags
+// particles with an other-phase particle in their list (interface candidates).
+template <class R, int DIM>
+__global__ void __launch_bounds__(256) k_nlist(Dev d, int cur, int remap)
 {
-    const uint32_t cidx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cidx >= d.ncell) return;
-    int lo = 0, hi = d.ninst - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (d.inst[mid].cell_base <= cidx) lo = mid;
-        else hi = mid - 1;
-    }
-    const InstDev& I = d.inst[lo];
-    int c[3];
-    cell_of_key(I, cidx, c);
-    uint32_t m = 0;
-    for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                int q[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-                bool skip = false;
-                for (int a = 0; a < DIM; ++a) {
-                    if (I.periodic[a]) q[a] = wrapi(q[a], I.nc[a]);
-                    else if (q[a] < 0 || q[a] >= I.nc[a]) skip = true;
-                }
-                if (skip) continue;
-                m |= mask[I.cell_base + (uint32_t)q[0] + (uint32_t)I.nc[0] * ((uint32_t)q[1] + (uint32_t)I.nc[1] * (uint32_t)q[2])];
-            }
-    d.cellmix[cidx] = m == 3u ? 1 : 0;
-    mask_next[cidx] = 0u;
+    const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
+    if (i >= d.n) return;
+    const Sorted& O = d.O[cur];
+    const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
+    const R4<R> pi = pos[i];
+    const InstDev& I = d.inst[info_inst(O.info[i])];
+    Lane<R> L;
+    L.load(I, pi, O.key[i]);
+    const uint32_t ph = pos_phase(pi);
+    uint32_t* nb = d.nbl + i;
+    const size_t n = (size_t)d.n;
+    const uint32_t cap = d.cap;
+    uint32_t cnt = 0;
+    bool other = false;
+    for_neighbors<R, DIM>(I, d.cstart, pos, i, L, cutl2_of<R>(I),
+                          [&](uint32_t k, const R*, R, const R4<R>& pj, uint32_t code) {
+                              if (cnt < cap) nb[(size_t)cnt * n] = k | (code << kIdxBits);
+                              ++cnt;
+                              other |= pos_phase(pj) != ph;
+                          });
+    d.nbc[i] = cnt;
+    d.nbx[i] = other ? 1 : 0;
 }
 
 // ------------------------------------------------------ per-particle state
@@ -527,41 +630,45 @@ __device__ __forceinline__ void renorm_one(const Dev& d, int cur, uint32_t i)
     const R4<R>* vel = (const R4<R>*)S.vel;
     const R4<R>* aux = (const R4<R>*)S.aux;
     const R* rho = (const R*)S.rho;
-    const uint32_t info = O.info[i];
-    const InstDev& I = d.inst[info_inst(info)];
-    const uint32_t ph = info_phase(info);
+    const R4<R> pi = pos[i];
+    const InstDev& I = d.inst[info_inst(O.info[i])];
+    const uint32_t ph = pos_phase(pi);
     Lane<R> L;
-    L.load(I, pos[i], O.key[i]);
+    L.load(I, pi, O.key[i]);
     const R w0 = kernel_w<R>(I, (R)0);
+    struct Pair { R a, b; };
     R num, den;
     if constexpr (sizeof(R) == 8) {
         // Eq. (7) as written: sum m_j W_ij / sum (m_j / rho_j) W_ij, self included
         num = aux[i].x * w0;
         den = vel[i].w * w0;
-        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R*, R r2) {
-            if (info_phase(O.info[k]) != ph) return;
-            const R w = kernel_w<R>(I, r2);
-            num += aux[k].x * w;
-            den += vel[k].w * w;
-        });
-        ((R*)d.rho_tmp)[i] = num / den;
+        for_each_neighbor<R, DIM, 2>(d, I, pos, i, L,
+            [&](uint32_t k) { return Pair{aux[k].x, vel[k].w}; },
+            [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
+                if (pos_phase(pj) != ph) return;
+                const R w = kernel_w<R>(I, r2);
+                num += x.a * w;
+                den += x.b * w;
+            });
     } else {
         // the same quotient minus rho0, as a V_j W_ij-weighted mean of (rho_j - rho0):
         // m_j - rho0 V_j = V_j (rho_j - rho0), so nothing cancels in FP32
         num = vel[i].w * w0 * rho[i];
         den = vel[i].w * w0;
-        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R*, R r2) {
-            if (info_phase(O.info[k]) != ph) return;
-            const R vw = vel[k].w * kernel_w<R>(I, r2);
-            num += vw * rho[k];
-            den += vw;
-        });
-        ((R*)d.rho_tmp)[i] = num / den;
+        for_each_neighbor<R, DIM, 4>(d, I, pos, i, L,
+            [&](uint32_t k) { return Pair{vel[k].w, rho[k]}; },
+            [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
+                if (pos_phase(pj) != ph) return;
+                const R vw = x.a * kernel_w<R>(I, r2);
+                num += vw * x.b;
+                den += vw;
+            });
     }
+    ((R*)d.rho_tmp)[i] = num / den;
 }
 
 template <class R, int DIM>
-__global__ void k_renorm(Dev d, int cur, int remap)
+__global__ void __launch_bounds__(256) k_renorm(Dev d, int cur, int remap)
 {
     const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
     if (i >= d.n) return;
@@ -571,36 +678,35 @@ __global__ void k_renorm(Dev d, int cur, int remap)
 // ----------------------------------------------- Eq. (16) colour gradient (pass A)
 
 template <class R, int DIM>
-__global__ void k_colour(Dev d, int cur, int star, int remap)
+__global__ void __launch_bounds__(256) k_colour(Dev d, int cur, int star, int remap)
 {
     const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
-    const bool valid = i < d.n;
+    if (i >= d.n) return;
     const Sorted& O = d.O[cur];
     const StateSet& S = star ? d.star : d.S[cur];
     R4<R>* gc = (R4<R>*)d.gc;
     R4<R>* aux = (R4<R>*)S.aux;
-    const bool mixed = valid && d.cellmix[O.key[i]] != 0;
-    if (!valid) return;
     R g[3] = {0, 0, 0};
     R gn = 0;
-    if (mixed) {
+    if (d.nbx[i]) {   // only particles with an other-phase particle in their list
         const R4<R>* pos = (const R4<R>*)S.pos;
         const R4<R>* vel = (const R4<R>*)S.vel;
-        const uint32_t info = O.info[i];
-        const InstDev& I = d.inst[info_inst(info)];
-        const uint32_t ph = info_phase(info);
+        const R4<R> pi = pos[i];
+        const InstDev& I = d.inst[info_inst(O.info[i])];
+        const uint32_t ph = pos_phase(pi);
         Lane<R> L;
-        L.load(I, pos[i], O.key[i]);
+        L.load(I, pi, O.key[i]);
         R s[3] = {0, 0, 0};
-        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R* r, R r2) {
-            if (info_phase(O.info[k]) == ph) return;       // C_j^y = 1 only for the other phase
-            const R vk = vel[k].w;                          // 1 / sigma_k
-            const R f = kernel_f<R>(I, r2) * (vk * vk);
-            s[0] += f * r[0];
-            s[1] += f * r[1];
-            s[2] += f * r[2];
-        });
-        const R vi = vel[i].w;                              // sigma_i = 1 / V_i
+        for_each_neighbor<R, DIM, 4>(d, I, pos, i, L, [](uint32_t) { return NoExtra{}; },
+            [&](uint32_t k, const R* r, R r2, const R4<R>& pj, NoExtra) {
+                if (pos_phase(pj) == ph) return;             // C_j^y = 1 only for the other phase
+                const R vk = vel[k].w;                       // 1 / sigma_k
+                const R f = kernel_f<R>(I, r2) * (vk * vk);
+                s[0] += f * r[0];
+                s[1] += f * r[1];
+                s[2] += f * r[2];
+            });
+        const R vi = vel[i].w;                               // sigma_i = 1 / V_i
         g[0] = s[0] / vi;
         g[1] = s[1] / vi;
         g[2] = s[2] / vi;
@@ -623,8 +729,11 @@ __device__ __forceinline__ void tension_dot(R c, const R g[3], R gn2, const R w[
     for (int a = 0; a < 3; ++a) out[a] = c * (iso * w[a] - g[a] * gw);
 }
 
+template <class R> struct ForceBatch { static constexpr int U = 4; };
+template <> struct ForceBatch<double> { static constexpr int U = 2; };
+
 template <class R, int DIM, bool REDUCE, bool TERMS>
-__global__ void k_force(Dev d, int cur, int star, int remap)
+__global__ void __launch_bounds__(256) k_force(Dev d, int cur, int star, int remap)
 {
     const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
     const bool valid = i < d.n;
@@ -643,19 +752,21 @@ __global__ void k_force(Dev d, int cur, int star, int remap)
         const InstDev& I = d.inst[inst];
         const uint32_t ph = info_phase(info);
         const bool fluid = info_kind(info) == K_FLUID;
+        const R4<R> pi = pos[i];
         Lane<R> L;
-        L.load(I, pos[i], O.key[i]);
+        L.load(I, pi, O.key[i]);
         const R4<R> vi = vel[i];
         const R4<R> xi = aux[i];                 // (m, m A, flag)
         const R mi = xi.x;
         const R Ai = xi.y / mi;                  // P_i / rho_i^2
         const bool fli = xi.z != (R)0;
         R gi[3] = {0, 0, 0}, ci = 0, gi2 = 0;
+        const R alpha = sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s;
         if (fli) {
             const R4<R> g4 = gc[i];
             gi[0] = g4.x; gi[1] = g4.y; gi[2] = g4.z;
             gi2 = g4.w * g4.w;
-            ci = (sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s) * (vi.w * vi.w) / g4.w;
+            ci = alpha * (vi.w * vi.w) / g4.w;
         }
         R vp0, vp1, delta2;
         if constexpr (sizeof(R) == 8) { vp0 = I.vpair[ph][0]; vp1 = I.vpair[ph][1]; delta2 = I.delta2; }
@@ -663,38 +774,40 @@ __global__ void k_force(Dev d, int cur, int star, int remap)
         const bool massform = I.cont_form == 1;
         R cont = 0, ap[3] = {0, 0, 0}, av[3] = {0, 0, 0}, as[3] = {0, 0, 0};
         uint32_t cnt = 0;
-        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R* r, R r2) {
-            ++cnt;
-            const R F = kernel_f<R>(I, r2);
-            const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
-            const R4<R> vk = vel[k];
-            const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
-            const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
-            const R4<R> xk = aux[k];
-            cont += (massform ? xk.x : vk.w) * udw;                   // Eq. (6) / (5)
-            if (!fluid) return;
-            const R pc = xk.x * Ai + xk.y;                            // m_j (A_i + A_j)
-            ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
-            const uint32_t pk = info_phase(O.info[k]);
-            const R lap = (F * r2) / (r2 + delta2);                   // r.gradW / (r^2 + delta^2)
-            const R cv = vk.w * (pk ? vp1 : vp0) * lap;
-            av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
-            const bool flk = xk.z != (R)0;
-            if (fli || flk) {
-                R t[3];
-                if (fli) {
-                    tension_dot<R, DIM>(ci, gi, gi2, w, t);
-                    as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+        struct VA { R4<R> v, a; };
+        for_each_neighbor<R, DIM, ForceBatch<R>::U>(d, I, pos, i, L,
+            [&](uint32_t k) { return VA{vel[k], aux[k]}; },
+            [&](uint32_t k, const R* r, R r2, const R4<R>& pj, const VA& x) {
+                ++cnt;
+                const R F = kernel_f<R>(I, r2);
+                const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
+                const R4<R>& vk = x.v;
+                const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
+                const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+                const R4<R>& xk = x.a;
+                cont += (massform ? xk.x : vk.w) * udw;                   // Eq. (6) / (5)
+                if (!fluid) return;
+                const R pc = xk.x * Ai + xk.y;                            // m_j (A_i + A_j)
+                ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
+                const R lap = (F * r2) / (r2 + delta2);                   // r.gradW / (r^2 + delta^2)
+                const R cv = vk.w * (pos_phase(pj) ? vp1 : vp0) * lap;
+                av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
+                const bool flk = xk.z != (R)0;
+                if (fli || flk) {
+                    R t[3];
+                    if (fli) {
+                        tension_dot<R, DIM>(ci, gi, gi2, w, t);
+                        as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+                    }
+                    if (flk) {
+                        const R4<R> g4 = gc[k];
+                        const R gk[3] = {g4.x, g4.y, g4.z};
+                        const R ck = alpha * (vk.w * vk.w) / g4.w;
+                        tension_dot<R, DIM>(ck, gk, g4.w * g4.w, w, t);
+                        as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+                    }
                 }
-                if (flk) {
-                    const R4<R> g4 = gc[k];
-                    const R gk[3] = {g4.x, g4.y, g4.z};
-                    const R ck = (sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s) * (vk.w * vk.w) / g4.w;
-                    tension_dot<R, DIM>(ck, gk, g4.w * g4.w, w, t);
-                    as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
-                }
-            }
-        });
+            });
         nint = cnt;
         const double rho_i = rho_of<R>(I, ph, ((const R*)S.rho)[i]);
         R4<R> out;
@@ -940,17 +1053,19 @@ __global__ void k_export(Dev d, int cur, int pass, const uint32_t* __restrict__ 
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.n) return;
     const Sorted& O = d.O[cur];
-    const StateSet& S = d.S[cur];
-    const R4<R>* pos = (const R4<R>*)S.pos;
+    const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
+    const R4<R> pi = pos[i];
     const InstDev& I = d.inst[info_inst(O.info[i])];
     Lane<R> L;
-    L.load(I, pos[i], O.key[i]);
+    L.load(I, pi, O.key[i]);
     uint32_t c = 0;
     const uint32_t base = pass ? off[i] : 0;
-    for_neighbors<R, DIM>(I, d.cstart, pos, i, L, [&](uint32_t k, const R*, R) {
-        if (pass) out[base + c] = O.id[k];
-        ++c;
-    });
+    // the same neighbour walk as the physics passes
+    for_each_neighbor<R, DIM, 4>(d, I, pos, i, L, [](uint32_t) { return NoExtra{}; },
+        [&](uint32_t k, const R*, R, const R4<R>&, NoExtra) {
+            if (pass) out[base + c] = O.id[k];
+            ++c;
+        });
     if (!pass) out[i] = c;
 }
 
@@ -959,12 +1074,10 @@ __global__ void k_export(Dev d, int cur, int pass, const uint32_t* __restrict__ 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <class R, int DIM>
-static void build_impl(const Dev& d, int cur, hipStream_t s)
+static void build_impl(const Dev& d, int cur, const Launch& L, hipStream_t s)
 {
     const int B = 256;
-    uint32_t* mask = d.cellmask + (size_t)cur * d.ncell;
-    uint32_t* mask_next = d.cellmask + (size_t)(1 - cur) * d.ncell;
-    hipLaunchKernelGGL((k_hash<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur, mask);
+    hipLaunchKernelGGL((k_hash<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur);
     const uint32_t ntiles = (d.ncell + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(SCAN_THREADS), 0, s, d.cnt, d.ncell, d.scan_tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, d.scan_tmp, ntiles);
@@ -972,7 +1085,8 @@ static void build_impl(const Dev& d, int cur, hipStream_t s)
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur);
     hipLaunchKernelGGL(k_rank, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
     hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur, d.O[cur].ref ? 1 : 0);
-    hipLaunchKernelGGL((k_cellmix<DIM>), dim3(blocks_for(d.ncell, B)), dim3(B), 0, s, d, mask, mask_next);
+    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, 1 - cur,
+                       L.xcd_remap);
 }
 
 #define SPHX_DISPATCH(PREC, DIM, CALL)                                  \
@@ -986,9 +1100,17 @@ static void build_impl(const Dev& d, int cur, hipStream_t s)
         }                                                               \
     } while (0)
 
-void launch_build(const Dev& d, int cur, const Launch&, hipStream_t s)
+void launch_build(const Dev& d, int cur, const Launch& L, hipStream_t s)
 {
-    SPHX_DISPATCH(d.precision, d.dim, (build_impl<R, D>(d, cur, s)));
+    SPHX_DISPATCH(d.precision, d.dim, (build_impl<R, D>(d, cur, L, s)));
+}
+
+void launch_nlist(const Dev& d, int cur, const Launch& L, hipStream_t s)
+{
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, cur,
+                           L.xcd_remap);
+    }));
 }
 
 void launch_renorm(const Dev& d, int cur, const Launch& L, hipStream_t s)
@@ -1007,17 +1129,25 @@ void launch_derive(const Dev& d, int cur, const Launch&, hipStream_t s)
     }));
 }
 
-void launch_rates(const Dev& d, int cur, bool star, bool reduce_max, const Launch& L, hipStream_t s)
+void launch_colour(const Dev& d, int cur, bool star, const Launch& L, hipStream_t s)
 {
     const dim3 grid(blocks_for(d.n, L.block)), block(L.block);
     SPHX_DISPATCH(d.precision, d.dim, ({
         hipLaunchKernelGGL((k_colour<R, D>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+    }));
+}
+
+void launch_force(const Dev& d, int cur, bool star, bool reduce_max, const Launch& L, hipStream_t s)
+{
+    const dim3 grid(blocks_for(d.n, L.block)), block(L.block);
+    const int st = star ? 1 : 0;
+    SPHX_DISPATCH(d.precision, d.dim, ({
         if (L.debug_terms) {
-            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, true>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
-            else hipLaunchKernelGGL((k_force<R, D, false, true>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, true>), grid, block, 0, s, d, cur, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, false, true>), grid, block, 0, s, d, cur, st, L.xcd_remap);
         } else {
-            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, false>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
-            else hipLaunchKernelGGL((k_force<R, D, false, false>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, false>), grid, block, 0, s, d, cur, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, false, false>), grid, block, 0, s, d, cur, st, L.xcd_remap);
         }
     }));
 }

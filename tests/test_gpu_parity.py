@@ -239,3 +239,43 @@ def test_fixed_dt_violating_the_skin_is_reported():
         sim.sync()
     assert e.value.code == 8
     sim.sync()                                      # sticky bits cleared by the report
+
+
+def clumped2d(extra=40, seed=3):
+    """Periodic 2D box with a tight clump of extra particles: the particles around the
+    clump overflow the neighbour-list capacity and take the stencil path."""
+    s = periodic_drop(2, 20)
+    rng = np.random.default_rng(seed)
+    c = np.array([0.01, 0.01])
+    xc = np.zeros((extra, 3))
+    xc[:, :2] = c + rng.uniform(-0.4e-3, 0.4e-3, (extra, 2))
+    uc = np.zeros((extra, 3))
+    uc[:, :2] = rng.uniform(-0.1, 0.1, (extra, 2))
+    s.x = np.concatenate([s.x, xc])
+    s.u = np.concatenate([s.u, uc])
+    s.rho = np.concatenate([s.rho, np.full(extra, 1001.0)])
+    s.m = np.concatenate([s.m, np.full(extra, 1e-3)])
+    s.phase = np.concatenate([s.phase, np.zeros(extra, np.uint8)])
+    s.kind = np.concatenate([s.kind, np.zeros(extra, np.uint8)])
+    s.inst_offsets = np.array([0, s.x.shape[0]], np.int64)
+    return s
+
+
+SCENES["clumped2d"] = clumped2d
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_list_overflow_falls_back_to_the_stencil(prec, oracle_rates):
+    s, ref, (off, ids) = oracle_rates("clumped2d")
+    assert np.diff(off).max() > 48                  # beyond the 2D list capacity
+    sim = binding.Sim(s, precision=prec)
+    if prec == binding.FP64:
+        goff, gids = sim.get_neighbors()
+        assert np.array_equal(goff, off) and np.array_equal(gids, ids)
+    sim.renormalize_density()
+    sim.compute_forces()
+    tol = TOL[prec]
+    assert rel_to(sim.get_field(binding.F_RHO), ref[oracle.RHO], 1000.0) < tol
+    total_scale = ref[oracle.SAP] + ref[oracle.SAV] + ref[oracle.SAS]
+    assert enorm(sim.get_field(binding.F_A), ref[oracle.A], total_scale) < tol
+    assert enorm(sim.get_field(binding.F_DRHO), ref[oracle.DRHO], ref[oracle.SDRHO]) < tol
