@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsphx_oracle.so")
+LIB_PATH = os.environ.get("SPHX_ORACLE_LIB", os.path.join(HERE, "libsphx_oracle.so"))
 
 MAX_PISTON = 16
 X, U, RHO, A, DRHO, AP, AV, AS, SDRHO, SAP, SAV, SAS, P, GRADC, TENSOR = range(15)

@@ -285,3 +285,174 @@ def isolated_particles(dim=3, n=1, *, spacing=1.0, h=0.01, u0=(0.3, -0.2, 0.5)) 
     return Scene("isolated", dim, [p], [phases], x, u, np.full(n, 1000.0), np.full(n, 1e-3),
                  np.zeros(n, np.uint8), np.zeros(n, np.uint8), np.array([0, n], np.int64),
                  [h / 1.3], None)
+
+
+# ----------------------------------------------------------------- flumes
+
+def _dispersion_k(omega, depth):
+    """Wavenumber of linear gravity waves, omega^2 = g k tanh(k depth) (Newton)."""
+    k = omega * omega / G
+    for _ in range(60):
+        f = G * k * math.tanh(k * depth) - omega * omega
+        df = G * math.tanh(k * depth) + G * k * depth / math.cosh(k * depth) ** 2
+        k -= f / df
+    return k
+
+
+def focused_piston(seed: int, depth: float, x_focus: float, amplitude=0.08, ncomp=8,
+                   periods=(0.7, 1.2)):
+    """Piston displacement d(t) = sum a_k (cos(w_k t + phi_k) - cos phi_k) whose
+    components reach x_focus in phase.  Component wave amplitudes are equal and sum to
+    ``amplitude``; each paddle amplitude follows the linear piston transfer function
+    H/S = 2 (cosh 2kh - 1) / (sinh 2kh + 2kh).  The focus time is the arrival of the
+    slowest group.  Returns the piston entries of a parameter dictionary."""
+    rng = np.random.default_rng(seed)
+    T = np.sort(rng.uniform(periods[0], periods[1], ncomp))
+    w = 2 * math.pi / T
+    ks = np.array([_dispersion_k(wi, depth) for wi in w])
+    kh = ks * depth
+    transfer = 2 * (np.cosh(2 * kh) - 1) / (np.sinh(2 * kh) + 2 * kh)
+    A = amplitude / ncomp
+    ap = A / transfer                       # paddle amplitude = (H/2) / (H/S)
+    cg = 0.5 * (w / ks) * (1 + 2 * kh / np.sinh(2 * kh))
+    t_f = x_focus / cg.min()
+    theta = w * t_f - ks * x_focus          # crest phase at the paddle
+    # paddle x(t) = ap sin(w t - theta) = ap cos(w t - theta - pi/2)
+    phi = -theta - math.pi / 2
+    return dict(piston_a=list(ap), piston_w=list(w), piston_phi=list(phi),
+                piston_t_end=1e30), dict(t_focus=t_f, periods=list(T), paddle=list(ap))
+
+
+def flume(dim: int, length: float, depth: float, dx: float, *, seed: int, width=None,
+          slick=None, rho_o=850.0, mu_o=0.01, alpha_s=0.02, piston=None, nlayers=3,
+          wall_top=1.2, headroom=1.6, back=0.1, jitter=0.05, name="flume") -> Scene:
+    """Wave flume: piston (MOVING) at x = 0, end wall at x = length, bottom wall, open
+    top; in 3D the width is periodic.  ``slick(points) -> mask`` marks oil lattice
+    points.  ``back`` is room behind the piston for its backward stroke."""
+    rng = np.random.default_rng(seed)
+    nx = int(round(length / dx))
+    nz = int(round(depth / dx))
+    H = nz * dx
+    c0 = 10.0 * math.sqrt(G * H)
+    h = 1.3 * dx
+    ny = int(round(width / dx)) if dim == 3 else 1
+    if dim == 2:
+        fl = _grid([(0, nx), (0, nz)]).astype(np.float64)
+    else:
+        fl = _grid([(0, nx), (0, ny), (0, nz)]).astype(np.float64)
+    xf = (fl + 0.5) * dx
+    nwz = int(round(wall_top * depth / dx))
+    zax = dim - 1
+    # bottom: under the whole flume and under the piston/end wall columns
+    if dim == 2:
+        bot = _grid([(-nlayers, nx + nlayers), (-nlayers, 0)])
+        end = _grid([(nx, nx + nlayers), (0, nwz)])
+        pis = _grid([(-nlayers, 0), (0, nwz)])
+    else:
+        bot = _grid([(-nlayers, nx + nlayers), (0, ny), (-nlayers, 0)])
+        end = _grid([(nx, nx + nlayers), (0, ny), (0, nwz)])
+        pis = _grid([(-nlayers, 0), (0, ny), (0, nwz)])
+    xw = (np.concatenate([bot, end]).astype(np.float64) + 0.5) * dx
+    xp = (pis.astype(np.float64) + 0.5) * dx
+    ph_f = np.zeros(len(xf), np.uint8)
+    if slick is not None:
+        ph_f[slick(xf)] = OIL
+    xf = xf + rng.uniform(-jitter * dx, jitter * dx, size=xf.shape)
+    if dim == 3:
+        xf[:, 1] = np.mod(xf[:, 1], ny * dx)
+    n = len(xf) + len(xw) + len(xp)
+    x = np.zeros((n, 3))
+    x[:len(xf), :dim] = xf
+    x[len(xf):len(xf) + len(xw), :dim] = xw
+    x[len(xf) + len(xw):, :dim] = xp
+    phase = np.concatenate([ph_f, np.zeros(len(xw) + len(xp), np.uint8)])
+    kind = np.concatenate([np.full(len(xf), FLUID, np.uint8), np.full(len(xw), WALL, np.uint8),
+                           np.full(len(xp), MOVING, np.uint8)])
+    rho0 = np.where(phase == OIL, rho_o, 1000.0)
+    rho = _hydrostatic_rho(x[:, zax], H, rho0, 1000.0, c0, G)
+    m = rho0 * dx ** dim
+    p = default_params(dim, h)
+    p["alpha_s"] = alpha_s if slick is not None else 0.0
+    grav = [0.0, 0.0, 0.0]
+    grav[zax] = -G
+    p["gravity"] = grav
+    lo, hi, per = [0.0] * 3, [0.0] * 3, [0, 0, 0]
+    lo[0], hi[0] = -nlayers * dx - back, (nx + nlayers) * dx
+    if dim == 3:
+        lo[1], hi[1], per[1] = 0.0, ny * dx, 1
+    lo[zax], hi[zax] = -nlayers * dx, headroom * H
+    p["lo"], p["hi"], p["periodic"] = lo, hi, per
+    if piston:
+        p.update(piston)
+    phases = [(1000.0, 1e-3 / 1000.0, c0), (rho_o, mu_o / rho_o, c0)]
+    return Scene(name, dim, [p], [phases], x, np.zeros((n, 3)), rho, m, phase, kind,
+                 np.array([0, n], np.int64), [dx], seed)
+
+
+def flume2d(k_seed: int = 2, *, dx=5e-3, length=8.0, depth=0.5, x_focus=5.0) -> Scene:
+    """2D breaking-wave flume: 8 m, depth 0.5 m, focused piston wave at x = 5 m; oil
+    layer 4 particles thick, 0.5 m long, centred at x_focus (rho 850, mu 0.01, sigma 0.02)."""
+    seed = SEED_BASE + k_seed
+    piston, _ = focused_piston(seed, depth, x_focus)
+    H = int(round(depth / dx)) * dx
+
+    def slick(pts):
+        return (np.abs(pts[:, 0] - x_focus) < 0.25) & (pts[:, 1] > H - 4 * dx)
+    return flume(2, length, depth, dx, seed=seed, slick=slick, piston=piston, name="flume2d")
+
+
+def flume3d(k_seed: int = 3, *, dx=4e-3, length=4.0, width=0.1, depth=0.5,
+            x_focus=2.5) -> Scene:
+    """3D flume section: 4 m x 0.1 m (periodic in y), depth 0.5 m, focused piston wave
+    (focus inside the section, x = 2.5 m); oil slick 3 particles thick over
+    0.3 x 0.1 m centred at the focus."""
+    seed = SEED_BASE + k_seed
+    piston, _ = focused_piston(seed, depth, x_focus)
+    H = int(round(depth / dx)) * dx
+
+    def slick(pts):
+        return (np.abs(pts[:, 0] - x_focus) < 0.15) & (pts[:, 2] > H - 3 * dx)
+    return flume(3, length, depth, dx, seed=seed, width=width, slick=slick, piston=piston,
+                 name="flume3d")
+
+
+def lab_flume(dim: int = 2, *, dx=5e-3, width=0.05, seed=SEED_BASE + 10) -> Scene:
+    """The paper's laboratory flume (Sec. IV): 6 m long, water depth 0.25 m, piston at
+    x = 0.55 m driven by Eq. (18) (stroke 45.72 cm at 0.75 Hz, t <= 2/3 s), oil slick
+    25.4 cm long and 0.5 mm thick (one particle layer at this resolution) centred at
+    x = 1.5 m, interfacial tension 0.019 N/m; in 3D a narrowed periodic width."""
+    stroke = 0.4572
+    piston = dict(piston_a=[-stroke / 2], piston_w=[2 * math.pi * 0.75], piston_phi=[0.0],
+                  piston_t_end=2.0 / 3.0)
+    length = 6.0 - 0.55
+    depth = 0.25
+    H = int(round(depth / dx)) * dx
+    xs = 1.5 - 0.55                         # slick centre in flume coordinates
+
+    def slick(pts):
+        top = pts[:, dim - 1] > H - max(5e-4, dx)
+        return (np.abs(pts[:, 0] - xs) < 0.127) & top
+    return flume(dim, length, depth, dx, seed=seed, width=width if dim == 3 else None,
+                 slick=slick, piston=piston, rho_o=900.0, mu_o=5e-3, alpha_s=0.019,
+                 back=0.05, name="lab_flume")
+
+
+def batched_drops(k_seed: int = 4, ninst: int = 256, nmin=2000, nmax=40000) -> Scene:
+    """Independent 2D drop tanks of uneven sizes: each 0.1 x 0.1 m with
+    dx = 0.1 / round(sqrt(n_fluid)), n_fluid ~ U[nmin, nmax]; drop radius U[5, 15] mm at
+    (0.05, 0.03); oil density U[800, 950], viscosity U[1e-3, 2e-2], tension U[0.01, 0.05]."""
+    ss = np.random.SeedSequence(SEED_BASE + k_seed)
+    parts = []
+    for b, child in enumerate(ss.spawn(ninst)):
+        rng = np.random.default_rng(child)
+        nf = int(rng.integers(nmin, nmax + 1))
+        side = max(int(round(math.sqrt(nf))), 8)
+        dx = 0.1 / side
+        R = float(rng.uniform(5e-3, 15e-3))
+        rho_o = float(rng.uniform(800.0, 950.0))
+        mu_o = float(rng.uniform(1e-3, 2e-2))
+        alpha = float(rng.uniform(0.01, 0.05))
+        seed = int(rng.integers(0, 2 ** 31))
+        parts.append(tank(2, 0.1, 0.1, dx, seed=seed, oil=drop(2, (0.05, 0.03), R),
+                          rho_o=rho_o, mu_o=mu_o, alpha_s=alpha, name=f"tank{b}"))
+    return concat("batched_drops", parts)

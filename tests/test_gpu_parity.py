@@ -279,3 +279,88 @@ def test_list_overflow_falls_back_to_the_stencil(prec, oracle_rates):
     total_scale = ref[oracle.SAP] + ref[oracle.SAV] + ref[oracle.SAS]
     assert enorm(sim.get_field(binding.F_A), ref[oracle.A], total_scale) < tol
     assert enorm(sim.get_field(binding.F_DRHO), ref[oracle.DRHO], ref[oracle.SDRHO]) < tol
+
+
+# ---- flumes: piston (MOVING) particles, periodic width in 3D, oil slick at the surface
+
+def small_flume2d():
+    return inputs.flume2d(dx=0.02, length=2.0, depth=0.3, x_focus=1.0)
+
+
+def small_flume3d():
+    return inputs.flume3d(dx=0.02, length=1.0, width=0.2, depth=0.2, x_focus=0.5)
+
+
+def small_lab_flume():
+    return inputs.lab_flume(2, dx=0.02)
+
+
+FLUMES = {"flume2d": small_flume2d, "flume3d": small_flume3d, "lab_flume": small_lab_flume}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", list(FLUMES))
+def test_flume_steps_match_oracle(name, prec):
+    s = FLUMES[name]()
+    print(f"case flume {name} precision={prec} n={s.n}", flush=True)
+    nsteps = 3
+    o, sim = _one_step(s, prec, nsteps)
+    dx = s.dx[0]
+    tol = TOL[prec]
+    x, xo = sim.get_field(binding.F_X), o.get(oracle.X)
+    assert rel_to(x, xo, dx) < tol
+    assert rel_to(sim.get_field(binding.F_RHO), o.get(oracle.RHO), 1000.0) < tol
+    ur = np.abs(o.get(oracle.U)).max()
+    assert rel_to(sim.get_field(binding.F_U), o.get(oracle.U), ur) < tol
+    piston = s.kind == inputs.MOVING
+    d, _ = oracle.piston(s.params[0], o.t)
+    assert np.allclose(xo[piston, 0], s.x[piston, 0] + d, rtol=0, atol=1e-12)
+    assert np.abs(x[piston, 0] - xo[piston, 0]).max() < (1e-12 if prec == 0 else 1e-6) + 0.0
+
+
+def test_flume3d_neighbours_bit_exact_across_the_periodic_width():
+    s = small_flume3d()
+    o = oracle.Oracle(s)
+    off, ids = o.neighbors()
+    sim = binding.Sim(s, precision=binding.FP64)
+    goff, gids = sim.get_neighbors()
+    assert np.array_equal(goff, off) and np.array_equal(gids, ids)
+    # pairs across the periodic faces exist
+    y = s.x[:, 1]
+    L = s.params[0]["hi"][1] - s.params[0]["lo"][1]
+    wrapped = 0
+    for i in range(0, s.n, 17):
+        js = ids[off[i]:off[i + 1]]
+        wrapped += int(np.sum(np.abs(y[js] - y[i]) > 0.5 * L))
+    assert wrapped > 0
+
+
+def test_drift_over_1000_steps_is_reported(tmp_path):
+    """Drift of both GPU forms against the oracle over 1000 steps of the 2D drop
+    (reported, loose bounds: particle trajectories separate chaotically)."""
+    import json
+    import os
+    s = inputs.drop2d()
+    o = oracle.Oracle(s)
+    o.set_neighbor_method(2)
+    sims = {p: binding.Sim(s, precision=p) for p in PRECS}
+    dx = s.dx[0]
+    rows = []
+    for k in range(10):
+        o.step(100)
+        xo, uo, ro = o.get(oracle.X), o.get(oracle.U), o.get(oracle.RHO)
+        row = {"steps": 100 * (k + 1), "t": o.t}
+        for p, sim in sims.items():
+            sim.step(100)
+            tag = "fp64" if p == 0 else "fp32"
+            row[f"{tag}_x_over_dx"] = rel_to(sim.get_field(binding.F_X), xo, dx)
+            row[f"{tag}_u_rel"] = rel_to(sim.get_field(binding.F_U), uo, np.abs(uo).max())
+            row[f"{tag}_rho_rel"] = rel_to(sim.get_field(binding.F_RHO), ro, 1000.0)
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "drift_drop2d_1000.json"), "w") as fh:
+        json.dump(rows, fh, indent=1)
+    assert rows[0]["fp64_x_over_dx"] < 1e-9
+    assert rows[-1]["fp32_x_over_dx"] < 0.5
