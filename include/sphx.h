@@ -119,6 +119,7 @@ typedef struct {
     int64_t interactions;     /* ordered pairs (i, j != i, r_ij < 2h) summed over every
                                  force evaluation since the last reset */
     int64_t ncells;           /* cells over all instances */
+    int64_t builds;           /* neighbour builds (sort + list) so far, instance 0 */
     double phase_ms[5];       /* SPHX_OPT_PROFILE: summed event time per kernel group */
     int64_t phase_launches[5];/* SPHX_OPT_PROFILE: timed launches per kernel group */
 } sphx_stats;
@@ -148,7 +149,9 @@ sphx_status sphx_init_particles(sphx_ctx* ctx, const double* x, const double* u,
                                 const double* m, const uint8_t* phase, const uint8_t* kind);
 
 /* Neighbour search at the current positions: cell hash, stable sort by cell (ties by
- * original index), reorder of the state, cell start table. */
+ * original index), reorder of the state, cell start table, neighbour list.  The other
+ * calls rebuild by themselves whenever a particle has moved more than a quarter of the
+ * skin since the last build; this call forces a rebuild. */
 sphx_status sphx_build_neighbors(sphx_ctx* ctx);
 
 /* Eq. (7): rho_i = sum m_j W_ij / sum (m_j/rho_j) W_ij over i and its same-phase
@@ -162,12 +165,12 @@ sphx_status sphx_compute_forces(sphx_ctx* ctx);
 
 /* One midpoint predictor-corrector step from the rates of the last compute_forces:
  * time step (dt > 0 fixes it, dt <= 0 takes the adaptive one on the device),
- * predictor, rates at the predicted state, corrector.  The neighbour structure is
- * rebuilt by the next build_neighbors. */
+ * predictor, rates at the predicted state, corrector. */
 sphx_status sphx_integrate_step(sphx_ctx* ctx, double dt);
 
-/* nsteps full steps: build, renormalise when due, rates, integrate.  Each step is one
- * replay of a captured hipGraph when SPHX_OPT_GRAPH is on and the stream allows it. */
+/* nsteps full steps: neighbour rebuild when due, Eq. (7) when due, rates, integrate.
+ * Each step is one replay of a captured hipGraph when SPHX_OPT_GRAPH is on and the
+ * stream allows it (both decisions are taken on the device). */
 sphx_status sphx_step(sphx_ctx* ctx, int32_t nsteps);
 
 sphx_status sphx_set_option(sphx_ctx* ctx, int32_t option, int64_t value);

@@ -49,7 +49,7 @@ class Phase(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("t", C.c_double), ("dt", C.c_double),
-                ("interactions", C.c_int64), ("ncells", C.c_int64),
+                ("interactions", C.c_int64), ("ncells", C.c_int64), ("builds", C.c_int64),
                 ("phase_ms", C.c_double * 5), ("phase_launches", C.c_int64 * 5)]
 
 
@@ -242,6 +242,7 @@ class Sim:
         s = Stats()
         self._check(lib().sphx_get_stats(self.ctx, C.byref(s)), "sphx_get_stats")
         return dict(steps=s.steps, t=s.t, dt=s.dt, interactions=s.interactions, ncells=s.ncells,
+                    builds=s.builds,
                     phase_ms={k: s.phase_ms[q] for q, k in enumerate(PHASES)},
                     phase_launches={k: s.phase_launches[q] for q, k in enumerate(PHASES)})
 

@@ -28,13 +28,10 @@ struct sphx_ctx {
     size_t ws_bytes = 0;
     Dev dev{};
     Launch launch{};
-    int cur = 0;
-    bool bound = false, inited = false, nb_valid = false, rates_valid = false;
+    bool bound = false, inited = false, rates_valid = false;
     bool has_moving = false;
-    int64_t step_host = 0;
-    int renorm_every = 1;
     bool use_graph = true;
-    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+    hipGraphExec_t graph = nullptr;   // one step; the state parity lives on the device
     bool profile = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;   // (group, start/stop)
     double phase_ms[SPHX_NPH] = {0, 0, 0, 0, 0};
@@ -143,11 +140,14 @@ InstDev make_inst(const sphx_params& p, const sphx_phase* ph2, int nphase, uint3
     I.h = h;
     I.inv_h = 1.0 / h;
     I.cut2 = 4.0 * h * h;
-    // neighbour-list radius: 2h plus half the skin (the most two particles can close in
-    // on each other between the list build and the predicted state), with a margin far
-    // above FP32 rounding
-    const double rl = (2.0 + 0.5 * p.skin_coef) * h;
+    // neighbour-list radius: the cell size (2 + skin) h, with a margin far above FP32 rounding
+    const double rl = (2.0 + p.skin_coef) * h;
     I.cutl2 = rl * rl * (1.0 + 2e-5);
+    // the list (and the cells) stay valid while no particle moved more than skin/4 since
+    // the build: a predictor half step adds at most skin/4 more (dt <= skin h / (2 max|u|)),
+    // so any pair within 2h at a predicted state was within (2 + skin) h at the build
+    const double q = 0.25 * p.skin_coef * h;
+    I.rebuild_d2 = q * q;
     I.wcoef = alpha;
     I.fcoef = -5.0 * alpha / (h * h);
     const double delta = p.delta_coef * h;
@@ -234,6 +234,8 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.run = c.take<InstRun>(ninst);
     d.status = c.take<uint32_t>(1);
     d.inter = c.take<unsigned long long>(1);
+    d.curp = c.take<int>(1);
+    d.flags = c.take<uint32_t>(2);
     d.cnt = c.take<uint32_t>(ncell);
     d.cstart = c.take<uint32_t>((size_t)ncell + 1);
     d.scan_tmp = c.take<uint32_t>((ncell + 2047) / 2048 + 1);
@@ -241,6 +243,7 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.nbl = c.take<uint32_t>(un * d.cap);
     d.nbc = c.take<uint32_t>(un);
     d.nbx = c.take<uint8_t>(un);
+    d.xb = c.take<char>(un * 4 * R);
     d.newkey = c.take<uint32_t>(un);
     d.slot = c.take<uint32_t>(un);
     d.tsrc = c.take<uint32_t>(un);
@@ -338,21 +341,18 @@ void collect_events(sphx_ctx* c)
 
 void enqueue_build(sphx_ctx* c)
 {
-    {
-        Timed t(c, SPHX_PH_BUILD);
-        launch_build(c->dev, c->cur, c->launch, c->stream);
-    }
-    c->cur = 1 - c->cur;
+    Timed t(c, SPHX_PH_BUILD);
+    launch_build(c->dev, c->launch, c->stream);
 }
 
 void enqueue_rates(sphx_ctx* c, bool star, bool reduce)
 {
     {
         Timed t(c, SPHX_PH_COLOUR);
-        launch_colour(c->dev, c->cur, star, c->launch, c->stream);
+        launch_colour(c->dev, star, c->launch, c->stream);
     }
     Timed t(c, SPHX_PH_FORCE);
-    launch_force(c->dev, c->cur, star, reduce, c->launch, c->stream);
+    launch_force(c->dev, star, reduce, c->launch, c->stream);
 }
 
 void enqueue_integrate(sphx_ctx* c, double dt_override)
@@ -360,48 +360,52 @@ void enqueue_integrate(sphx_ctx* c, double dt_override)
     {
         Timed t(c, SPHX_PH_INTEGRATE);
         launch_dt(c->dev, dt_override, c->stream);
-        launch_predict(c->dev, c->cur, c->launch, c->stream);
+        launch_predict(c->dev, c->launch, c->stream);
     }
     enqueue_rates(c, true, false);
     Timed t(c, SPHX_PH_INTEGRATE);
-    launch_correct(c->dev, c->cur, c->launch, c->stream);
+    launch_correct(c->dev, c->launch, c->stream);
     launch_finish(c->dev, c->stream);
 }
 
-void enqueue_renorm(sphx_ctx* c)
+void enqueue_renorm(sphx_ctx* c, bool force)
 {
     Timed t(c, SPHX_PH_RENORM);
-    launch_renorm(c->dev, c->cur, c->launch, c->stream);
+    launch_renorm(c->dev, force, c->launch, c->stream);
 }
 
-void enqueue_forces(sphx_ctx* c)
+// One full step: neighbour structure (rebuilt only when due), Eq. (7) when due, rates
+// at S^n, time step, predictor, rates at S*, corrector.
+void enqueue_step(sphx_ctx* c)
 {
-    launch_begin_step(c->dev, c->stream);
-    enqueue_rates(c, false, true);
-}
-
-// One full step from a valid neighbour structure; ends with a rebuilt one.
-void enqueue_step(sphx_ctx* c, bool renorm)
-{
-    if (renorm) enqueue_renorm(c);
-    enqueue_forces(c);
-    enqueue_integrate(c, 0.0);
     enqueue_build(c);
+    enqueue_renorm(c, false);
+    enqueue_rates(c, false, true);
+    enqueue_integrate(c, 0.0);
+}
+
+sphx_status request_rebuild(sphx_ctx* c)
+{
+    const uint32_t one = 1;
+    HIP_OK(c, hipMemcpyAsync(c->dev.flags + 1, &one, sizeof one, hipMemcpyHostToDevice, c->stream));
+    return SPHX_OK;
+}
+
+// Current state set (synchronises the stream).
+int device_cur(sphx_ctx* c)
+{
+    int cur = 0;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return 0;
+    if (hipMemcpy(&cur, c->dev.curp, sizeof cur, hipMemcpyDeviceToHost) != hipSuccess) return 0;
+    return cur & 1;
 }
 
 void drop_graphs(sphx_ctx* c)
 {
-    for (auto& row : c->graph)
-        for (auto& g : row)
-            if (g) {
-                (void)hipGraphExecDestroy(g);
-                g = nullptr;
-            }
-}
-
-bool renorm_due(const sphx_ctx* c, int64_t step)
-{
-    return c->renorm_every > 0 && step % c->renorm_every == 0;
+    if (c->graph) {
+        (void)hipGraphExecDestroy(c->graph);
+        c->graph = nullptr;
+    }
 }
 
 } // namespace
@@ -412,22 +416,25 @@ namespace {
 struct BlobHeader {
     uint64_t magic;
     int32_t precision, dim, ninst, cur;
-    int64_t n, step_host;
-    uint32_t ncell, nb_valid, rates_valid, pad;
+    int64_t n;
+    uint32_t ncell, rates_valid, cap, pad;
 };
-constexpr uint64_t kMagic = 0x5350485853543031ull;   // "SPHXST01"
+constexpr uint64_t kMagic = 0x5350485853543032ull;   // "SPHXST02"
 
 struct Span { void* p; size_t bytes; };
 
-std::vector<Span> state_spans(sphx_ctx* c)
+// Everything a continuation depends on, in the sorted order of state set `s`: the state,
+// the cell table, the neighbour list and its build positions, the per-instance run
+// variables and the last rates.
+std::vector<Span> state_spans(sphx_ctx* c, int s)
 {
     const size_t n = (size_t)c->n, R = c->precision ? 4 : 8;
     Dev& d = c->dev;
-    const int s = c->cur;
     std::vector<Span> v = {
         {d.S[s].pos, n * 4 * R}, {d.S[s].vel, n * 4 * R}, {d.S[s].aux, n * 4 * R}, {d.S[s].rho, n * R},
         {d.O[s].key, n * 4}, {d.O[s].id, n * 4}, {d.O[s].info, n * 4}, {d.cstart, ((size_t)c->ncell + 1) * 4},
-        {d.run, sizeof(InstRun) * c->ninst}, {d.acc, n * 4 * R}, {d.gc, n * 4 * R}};
+        {d.run, sizeof(InstRun) * c->ninst}, {d.acc, n * 4 * R}, {d.gc, n * 4 * R},
+        {d.nbl, n * d.cap * 4}, {d.nbc, n * 4}, {d.nbx, n}, {d.xb, n * 4 * R}};
     if (c->precision) {
         v.push_back({d.S[s].plo, n * 16});
         v.push_back({d.S[s].vlo, n * 16});
@@ -512,7 +519,6 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
     c->stream = (hipStream_t)stream;
     c->num_cu = prop.multiProcessorCount;
     c->launch.num_cu = c->num_cu;
-    c->renorm_every = per_inst[0].renorm_every;
     c->use_graph = stream != nullptr;
     *out = c;
     return SPHX_OK;
@@ -666,12 +672,13 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
         d.O[0].ref = tmp.O[0].ref;
         d.O[1].ref = tmp.O[1].ref;
     }
-    c->cur = 0;
-    launch_derive(d, 0, c->launch, s);
+    const int zero = 0;
+    const uint32_t flags[2] = {0u, 1u};          // the first build is requested
+    HIP_OK(c, hipMemcpyAsync(d.curp, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+    HIP_OK(c, hipMemcpyAsync(d.flags, flags, sizeof flags, hipMemcpyHostToDevice, s));
+    launch_derive(d, c->launch, s);
     enqueue_build(c);
-    c->step_host = 0;
     c->inited = true;
-    c->nb_valid = true;
     c->rates_valid = false;
     HIP_OK(c, hipGetLastError());
     HIP_OK(c, hipStreamSynchronize(s));
@@ -682,8 +689,9 @@ sphx_status sphx_build_neighbors(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    sphx_status st = request_rebuild(c);
+    if (st) return st;
     enqueue_build(c);
-    c->nb_valid = true;
     c->rates_valid = false;
     HIP_OK(c, hipGetLastError());
     return SPHX_OK;
@@ -693,8 +701,8 @@ sphx_status sphx_renormalize_density(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
-    if (!c->nb_valid) enqueue_build(c), c->nb_valid = true;
-    enqueue_renorm(c);
+    enqueue_build(c);
+    enqueue_renorm(c, true);
     c->rates_valid = false;
     HIP_OK(c, hipGetLastError());
     return SPHX_OK;
@@ -704,8 +712,8 @@ sphx_status sphx_compute_forces(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
-    if (!c->nb_valid) enqueue_build(c), c->nb_valid = true;
-    enqueue_forces(c);
+    enqueue_build(c);
+    enqueue_rates(c, false, true);
     c->rates_valid = true;
     HIP_OK(c, hipGetLastError());
     return SPHX_OK;
@@ -719,8 +727,6 @@ sphx_status sphx_integrate_step(sphx_ctx* c, double dt)
     if (!std::isfinite(dt)) return fail(c, SPHX_E_ARG, "dt must be finite");
     enqueue_integrate(c, dt > 0 ? dt : 0.0);
     c->rates_valid = false;
-    c->nb_valid = false;
-    c->step_host += 1;
     HIP_OK(c, hipGetLastError());
     return SPHX_OK;
 }
@@ -730,47 +736,26 @@ sphx_status sphx_step(sphx_ctx* c, int32_t nsteps)
     if (!c) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
     if (nsteps < 0) return fail(c, SPHX_E_ARG, "nsteps must be >= 0");
-    if (!c->nb_valid) {
-        enqueue_build(c);
-        c->nb_valid = true;
-    }
     for (int32_t k = 0; k < nsteps; ++k) {
-        const bool due = renorm_due(c, c->step_host);
-        const int cur = c->cur;
-        if (c->use_graph && !c->profile) {
-            hipGraphExec_t& g = c->graph[cur][due ? 1 : 0];
-            if (!g) {
-                hipGraph_t graph = nullptr;
-                if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-                    enqueue_step(c, due);
-                    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
-                    c->cur = cur;   // capture only recorded the launches
-                    if (e == hipSuccess && graph && hipGraphInstantiate(&g, graph, nullptr, nullptr, 0) == hipSuccess) {
-                        (void)hipGraphDestroy(graph);
-                    } else {
-                        if (graph) (void)hipGraphDestroy(graph);
-                        g = nullptr;
-                        c->use_graph = false;
-                        (void)hipGetLastError();
-                    }
-                } else {
-                    c->use_graph = false;
-                    (void)hipGetLastError();
-                }
+        if (c->use_graph && !c->profile && !c->graph) {
+            hipGraph_t graph = nullptr;
+            bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                enqueue_step(c);
+                ok = hipStreamEndCapture(c->stream, &graph) == hipSuccess && graph &&
+                     hipGraphInstantiate(&c->graph, graph, nullptr, nullptr, 0) == hipSuccess;
+                if (graph) (void)hipGraphDestroy(graph);
             }
-            if (g) {
-                HIP_OK(c, hipGraphLaunch(g, c->stream));
-                c->cur = 1 - cur;
-            } else {
-                enqueue_step(c, due);
+            if (!ok) {
+                c->graph = nullptr;
+                c->use_graph = false;
+                (void)hipGetLastError();
             }
-        } else {
-            enqueue_step(c, due);
         }
-        c->step_host += 1;
+        if (c->use_graph && !c->profile && c->graph) HIP_OK(c, hipGraphLaunch(c->graph, c->stream));
+        else enqueue_step(c);
     }
     c->rates_valid = false;
-    c->nb_valid = true;
     HIP_OK(c, hipGetLastError());
     return SPHX_OK;
 }
@@ -820,6 +805,7 @@ sphx_status sphx_get_stats(sphx_ctx* c, sphx_stats* out)
     out->dt = r.dt;
     out->interactions = (int64_t)inter;
     out->ncells = c->ncell;
+    out->builds = r.builds;
     collect_events(c);
     for (int q = 0; q < SPHX_NPH; ++q) {
         out->phase_ms[q] = c->phase_ms[q];
@@ -845,8 +831,9 @@ sphx_status sphx_get_field(sphx_ctx* c, int32_t field, double* out)
     const bool f32 = c->precision == 1;
     const size_t R = f32 ? 4 : 8;
     const Dev& d = c->dev;
-    const StateSet& S = d.S[c->cur];
-    const Sorted& O = d.O[c->cur];
+    const int cur = device_cur(c);
+    const StateSet& S = d.S[cur];
+    const Sorted& O = d.O[cur];
     std::vector<uint32_t> id(n), info(n), key(n);
     HIP_OK(c, hipMemcpy(id.data(), O.id, n * 4, hipMemcpyDeviceToHost));
     HIP_OK(c, hipMemcpy(info.data(), O.info, n * 4, hipMemcpyDeviceToHost));
@@ -967,14 +954,15 @@ sphx_status sphx_get_neighbors(sphx_ctx* c, int64_t* off, int32_t* ids, int64_t 
 {
     if (!c || !off || !need) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
-    if (!c->nb_valid) enqueue_build(c), c->nb_valid = true;
+    enqueue_build(c);
+    const int cur = device_cur(c);
     const int64_t n = c->n;
     uint32_t *dcnt = nullptr, *doff = nullptr, *dids = nullptr;
     HIP_OK(c, hipMalloc(&dcnt, n * 4));
-    launch_export(c->dev, c->cur, 0, nullptr, dcnt, c->launch, c->stream);
+    launch_export(c->dev, 0, nullptr, dcnt, c->launch, c->stream);
     std::vector<uint32_t> cnt(n), id(n);
     hipError_t e = hipMemcpyAsync(cnt.data(), dcnt, n * 4, hipMemcpyDeviceToHost, c->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(id.data(), c->dev.O[c->cur].id, n * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(id.data(), c->dev.O[cur].id, n * 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
         (void)hipFree(dcnt);
@@ -998,7 +986,7 @@ sphx_status sphx_get_neighbors(sphx_ctx* c, int64_t* off, int32_t* ids, int64_t 
     if (e == hipSuccess) e = hipMalloc(&dids, (total > 0 ? total : 1) * 4);
     if (e == hipSuccess) e = hipMemcpyAsync(doff, soff.data(), (n + 1) * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) {
-        launch_export(c->dev, c->cur, 1, doff, dids, c->launch, c->stream);
+        launch_export(c->dev, 1, doff, dids, c->launch, c->stream);
         e = hipMemcpyAsync(sids.data(), dids, total * 4, hipMemcpyDeviceToHost, c->stream);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1019,14 +1007,15 @@ sphx_status sphx_get_state(sphx_ctx* c, void* blob, size_t cap, size_t* need)
 {
     if (!c || !need) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
-    auto spans = state_spans(c);
+    const int cur = device_cur(c);
+    auto spans = state_spans(c, cur);
     size_t total = sizeof(BlobHeader);
     for (auto& s : spans) total += s.bytes;
     *need = total;
     if (!blob || cap < total) return SPHX_OK;
     const sphx_status st = status_of(c);
-    BlobHeader h{kMagic, c->precision, c->dim, c->ninst, c->cur, c->n, c->step_host, c->ncell,
-                 (uint32_t)c->nb_valid, (uint32_t)c->rates_valid, 0};
+    BlobHeader h{kMagic, c->precision, c->dim, c->ninst, cur, c->n, c->ncell, (uint32_t)c->rates_valid,
+                 c->dev.cap, 0};
     char* p = (char*)blob;
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
@@ -1045,27 +1034,24 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
     if (bytes < sizeof h) return fail(c, SPHX_E_ARG, "blob too small");
     std::memcpy(&h, blob, sizeof h);
     if (h.magic != kMagic || h.precision != c->precision || h.dim != c->dim || h.ninst != c->ninst || h.n != c->n ||
-        h.ncell != c->ncell)
+        h.ncell != c->ncell || h.cap != c->dev.cap || (h.cur != 0 && h.cur != 1))
         return fail(c, SPHX_E_ARG, "blob does not match this context");
-    HIP_OK(c, hipStreamSynchronize(c->stream));
-    c->cur = h.cur;
-    auto spans = state_spans(c);
+    auto spans = state_spans(c, h.cur);
     size_t total = sizeof h;
     for (auto& s : spans) total += s.bytes;
     if (bytes != total) return fail(c, SPHX_E_ARG, "blob size mismatch");
+    HIP_OK(c, hipStreamSynchronize(c->stream));
     const char* p = (const char*)blob + sizeof h;
     for (auto& s : spans) {
         HIP_OK(c, hipMemcpy(s.p, p, s.bytes, hipMemcpyHostToDevice));
         p += s.bytes;
     }
+    const int cur = h.cur;
+    const uint32_t flags[2] = {0u, 0u};
+    HIP_OK(c, hipMemcpy(c->dev.curp, &cur, sizeof cur, hipMemcpyHostToDevice));
+    HIP_OK(c, hipMemcpy(c->dev.flags, flags, sizeof flags, hipMemcpyHostToDevice));
     HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * 4));
-    // the neighbour list is a function of the restored positions and cell table
-    launch_nlist(c->dev, c->cur, c->launch, c->stream);
-    HIP_OK(c, hipStreamSynchronize(c->stream));
-    c->step_host = h.step_host;
-    c->nb_valid = h.nb_valid != 0;
     c->rates_valid = h.rates_valid != 0;
-    drop_graphs(c);
     return SPHX_OK;
 }
 

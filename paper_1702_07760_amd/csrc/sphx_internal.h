@@ -29,6 +29,7 @@ struct InstDev {
     uint32_t cell_base, ncell;
     int32_t dim, visc_form, cont_form, renorm_every;
     double h, inv_h, cut2, cutl2, wcoef, fcoef, delta2, alpha_s, skin;
+    double rebuild_d2;    // rebuild once some particle moved more than skin/4 since the build
     double g[3];
     double rho0[2], beta[2], nu[2];
     double vpair[2][2];   // 2 nu_ij (Eq. (10)) or 2 mu_ij (Eq. (11)) by phase pair
@@ -45,8 +46,10 @@ struct InstDev {
 struct InstRun {
     unsigned long long umax2;  // bit pattern of max |u|^2 (FP64, non-negative)
     unsigned long long amax2;  // bit pattern of max |a|^2
+    unsigned long long disp2;  // bit pattern of max |x - x_build|^2 since the last build
     double dt, t, t_next;
     long long step;
+    long long builds;          // neighbour builds so far
 };
 
 // One copy of the cell-sorted particle state.
@@ -76,6 +79,8 @@ struct Dev {
     InstRun* run;        // device
     uint32_t* status;
     unsigned long long* inter;
+    int* curp;           // which state set (0/1) holds the current sorted state
+    uint32_t* flags;     // [0] rebuild in this step, [1] rebuild requested by the host
     // build scratch
     uint32_t* cnt;       // ncell
     uint32_t* cstart;    // ncell + 1
@@ -90,6 +95,7 @@ struct Dev {
     uint32_t* nbc;       // n counts (> cap: overflowed, the passes walk the stencil)
     uint8_t* nbx;        // n: an other-phase particle is in the list
     uint32_t cap;
+    void* xb;            // R4: positions at the last build (FP32: cell offsets)
     // state
     StateSet S[2];       // double-buffered current state
     Sorted O[2];
@@ -108,20 +114,21 @@ struct Launch {
     bool debug_terms = false;
 };
 
-// --- launchers (sphx_kernels.hip); all asynchronous on the given stream ---
-void launch_build(const Dev& d, int cur, const Launch& L, hipStream_t s);   // S[cur] -> S[1-cur], + list
-void launch_nlist(const Dev& d, int cur, const Launch& L, hipStream_t s);
-void launch_renorm(const Dev& d, int cur, const Launch& L, hipStream_t s);
-void launch_colour(const Dev& d, int cur, bool star, const Launch& L, hipStream_t s);
-void launch_force(const Dev& d, int cur, bool star, bool reduce_max, const Launch& L, hipStream_t s);
+// --- launchers (sphx_kernels.hip); all asynchronous on the given stream.  The current
+// state set and the rebuild decision live on the device, so one captured graph serves
+// every step.
+void launch_build(const Dev& d, const Launch& L, hipStream_t s);     // decide, then sort + list if due
+void launch_nlist(const Dev& d, const Launch& L, hipStream_t s);     // list of the current order
+void launch_renorm(const Dev& d, bool force, const Launch& L, hipStream_t s);
+void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s);
+void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hipStream_t s);
 void launch_dt(const Dev& d, double dt_fixed_override, hipStream_t s);
-void launch_predict(const Dev& d, int cur, const Launch& L, hipStream_t s);
-void launch_correct(const Dev& d, int cur, const Launch& L, hipStream_t s);
+void launch_predict(const Dev& d, const Launch& L, hipStream_t s);
+void launch_correct(const Dev& d, const Launch& L, hipStream_t s);
 void launch_finish(const Dev& d, hipStream_t s);
-void launch_begin_step(const Dev& d, hipStream_t s);
-void launch_derive(const Dev& d, int cur, const Launch& L, hipStream_t s);
+void launch_derive(const Dev& d, const Launch& L, hipStream_t s);
 // neighbour export: counts (pass 0) or ids (pass 1) in sorted order
-void launch_export(const Dev& d, int cur, int pass, const uint32_t* off, uint32_t* out,
+void launch_export(const Dev& d, int pass, const uint32_t* off, uint32_t* out,
                    const Launch& L, hipStream_t s);
 
 } // namespace sphx

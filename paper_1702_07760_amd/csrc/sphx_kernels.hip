@@ -53,6 +53,15 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Running maximum of a non-negative double kept as its bit pattern.  The plain read
+// first skips the atomic when it cannot raise the value (values only grow, so a stale
+// read can only cost an extra atomic, never lose an update).
+__device__ __forceinline__ void max_update(unsigned long long* slot, double v)
+{
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(v);
+    if (bits > *(volatile unsigned long long*)slot) atomicMax(slot, bits);
+}
+
 __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -326,11 +335,10 @@ __device__ __forceinline__ void for_each_neighbor(const Dev& d, const InstDev& I
 // its cell into the neighbouring cell, folding the rounding of the shift into
 // the compensation term.  Each particle bumps its cell counter (the returned
 // value is its provisional slot) and marks its phase in the cell mask.
+// a1 for one particle: its new cell key (and, in FP32, its offset moved into that cell).
 template <class R, int DIM>
-__global__ void k_hash(Dev d, int cur)
+__device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
 {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d.n) return;
     const Sorted& O = d.O[cur];
     const uint32_t info = O.info[k];
     const InstDev& I = d.inst[info_inst(info)];
@@ -385,10 +393,37 @@ __global__ void k_hash(Dev d, int cur)
         d.S[cur].plo[k] = make_float4(e[0], e[1], e[2], lo.w);
     }
     if (out) atomicOr(d.status, ST_DOMAIN);
-    const uint32_t key = I.cell_base + (uint32_t)c[0] +
-                         (uint32_t)I.nc[0] * ((uint32_t)c[1] + (uint32_t)I.nc[1] * (uint32_t)c[2]);
-    d.newkey[k] = key;
-    d.slot[k] = atomicAdd(&d.cnt[key], 1u);
+    return I.cell_base + (uint32_t)c[0] + (uint32_t)I.nc[0] * ((uint32_t)c[1] + (uint32_t)I.nc[1] * (uint32_t)c[2]);
+}
+
+
+template <class R, int DIM>
+__global__ void k_hash(Dev d)
+{
+    if (!d.flags[0]) return;
+    const int cur = *d.curp;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = k < d.n;
+    uint32_t key = 0;
+    if (valid) key = hash_one<R, DIM>(d, cur, k);
+    // lanes of one wave mostly share a cell: one counter update per distinct key
+    const int lane = threadIdx.x & 63;
+    unsigned long long todo = __ballot(valid);
+    uint32_t slot = 0;
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t kl = __shfl(key, leader, 64);
+        const unsigned long long same = __ballot(valid && key == kl) & todo;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&d.cnt[kl], (uint32_t)__popcll(same));
+        base = __shfl(base, leader, 64);
+        if ((same >> lane) & 1ull) slot = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        todo &= ~same;
+    }
+    if (valid) {
+        d.newkey[k] = key;
+        d.slot[k] = slot;
+    }
 }
 
 // a4 (cell start table): exclusive scan of the per-cell counts in three passes.
@@ -415,8 +450,10 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& t
     return base + incl - v;
 }
 
-__global__ void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n, uint32_t* __restrict__ sums)
+__global__ void k_scan_reduce(const uint32_t* __restrict__ gate, const uint32_t* __restrict__ in, uint32_t n,
+                              uint32_t* __restrict__ sums)
 {
+    if (!*gate) return;
     const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     uint32_t s = 0;
     for (int j = 0; j < SCAN_ITEMS; ++j)
@@ -426,8 +463,9 @@ __global__ void k_scan_reduce(const uint32_t* __restrict__ in, uint32_t n, uint3
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ void k_scan_top(uint32_t* __restrict__ sums, uint32_t ntiles)
+__global__ void k_scan_top(const uint32_t* __restrict__ gate, uint32_t* __restrict__ sums, uint32_t ntiles)
 {
+    if (!*gate) return;
     // one block; each thread owns a run of ceil(ntiles / 256) tile sums
     const uint32_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint32_t a = threadIdx.x * per;
@@ -445,9 +483,10 @@ __global__ void k_scan_top(uint32_t* __restrict__ sums, uint32_t ntiles)
 }
 
 // Writes cstart[0..n] and clears the counters for the next build.
-__global__ void k_scan_down(uint32_t* __restrict__ cnt, uint32_t n, const uint32_t* __restrict__ sums,
-                            uint32_t* __restrict__ out)
+__global__ void k_scan_down(const uint32_t* __restrict__ gate, uint32_t* __restrict__ cnt, uint32_t n,
+                            const uint32_t* __restrict__ sums, uint32_t* __restrict__ out)
 {
+    if (!*gate) return;
     const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
     uint32_t s = 0;
@@ -469,8 +508,10 @@ __global__ void k_scan_down(uint32_t* __restrict__ cnt, uint32_t n, const uint32
 }
 
 // Provisional scatter into the cell's segment.
-__global__ void k_scatter(Dev d, int cur)
+__global__ void k_scatter(Dev d)
 {
+    if (!d.flags[0]) return;
+    const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n) return;
     const uint32_t p = d.cstart[d.newkey[k]] + d.slot[k];
@@ -481,6 +522,7 @@ __global__ void k_scatter(Dev d, int cur)
 // a2 made unique: within a cell, order by original id (rank = number of smaller ids).
 __global__ void k_rank(Dev d)
 {
+    if (!d.flags[0]) return;
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.n) return;
     const uint32_t src = d.tsrc[s];
@@ -494,8 +536,10 @@ __global__ void k_rank(Dev d)
 
 // a3: permute the state into the new order (S[cur] -> S[1-cur]).
 template <class R>
-__global__ void k_gather(Dev d, int cur, int with_ref)
+__global__ void k_gather(Dev d, int with_ref)
 {
+    if (!d.flags[0]) return;
+    const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n) return;
     const uint32_t src = d.perm[k];
@@ -521,18 +565,53 @@ __global__ void k_gather(Dev d, int cur, int with_ref)
     }
 }
 
+// After a rebuild the gathered copy becomes the current state set.
+__global__ void k_flip(Dev d)
+{
+    if (d.flags[0] && threadIdx.x == 0 && blockIdx.x == 0) *d.curp = 1 - *d.curp;
+}
+
+// Start of a step (or of a rate evaluation): rebuild the sort and the list when the
+// host asked for it or some particle moved more than a quarter of the skin since the
+// last build; reset the per-instance maxima of the time step.  One block.
+__global__ void k_decide(Dev d)
+{
+    __shared__ int any;
+    if (threadIdx.x == 0) any = d.flags[1] ? 1 : 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x)
+        if (__longlong_as_double((long long)d.run[b].disp2) > d.inst[b].rebuild_d2) atomicOr(&any, 1);
+    __syncthreads();
+    const int rebuild = any;
+    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) {
+        d.run[b].umax2 = 0ull;
+        d.run[b].amax2 = 0ull;
+        if (rebuild) {
+            d.run[b].disp2 = 0ull;
+            d.run[b].builds += 1;
+        }
+    }
+    if (threadIdx.x == 0) {
+        d.flags[0] = (uint32_t)rebuild;
+        d.flags[1] = 0u;
+    }
+}
+
 // Neighbour list at the positions of S[cur]: every j within the list radius
 // (2h plus half the skin, with a rounding margin), so that the same list holds every
 // pair within 2h at the predicted positions of the step as well.  Also flags
 // particles with an other-phase particle in their list (interface candidates).
 template <class R, int DIM>
-__global__ void __launch_bounds__(256) k_nlist(Dev d, int cur, int remap)
+__global__ void __launch_bounds__(256) k_nlist(Dev d, int remap)
 {
+    if (!d.flags[0]) return;
+    const int cur = *d.curp;
     const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
     if (i >= d.n) return;
     const Sorted& O = d.O[cur];
     const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
     const R4<R> pi = pos[i];
+    ((R4<R>*)d.xb)[i] = pi;
     const InstDev& I = d.inst[info_inst(O.info[i])];
     Lane<R> L;
     L.load(I, pi, O.key[i]);
@@ -575,9 +654,18 @@ __device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R s
 }
 
 // After Eq. (7): move the renormalised density into the state and re-derive.
-template <class R>
-__global__ void k_derive(Dev d, int cur, int from_tmp)
+// Eq. (7) runs at steps with step % renorm_every == 0 (or when the host asks for it).
+__device__ __forceinline__ bool renorm_due(const Dev& d)
 {
+    const int e = d.inst[0].renorm_every;
+    return e > 0 && d.run[0].step % e == 0;
+}
+
+template <class R>
+__global__ void k_derive(Dev d, int from_tmp, int force)
+{
+    if (from_tmp && !force && !renorm_due(d)) return;
+    const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n) return;
     const uint32_t info = d.O[cur].info[k];
@@ -668,18 +756,20 @@ __device__ __forceinline__ void renorm_one(const Dev& d, int cur, uint32_t i)
 }
 
 template <class R, int DIM>
-__global__ void __launch_bounds__(256) k_renorm(Dev d, int cur, int remap)
+__global__ void __launch_bounds__(256) k_renorm(Dev d, int remap, int force)
 {
+    if (!force && !renorm_due(d)) return;
     const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
     if (i >= d.n) return;
-    renorm_one<R, DIM>(d, cur, i);
+    renorm_one<R, DIM>(d, *d.curp, i);
 }
 
 // ----------------------------------------------- Eq. (16) colour gradient (pass A)
 
 template <class R, int DIM>
-__global__ void __launch_bounds__(256) k_colour(Dev d, int cur, int star, int remap)
+__global__ void __launch_bounds__(256) k_colour(Dev d, int star, int remap)
 {
+    const int cur = *d.curp;
     const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
     if (i >= d.n) return;
     const Sorted& O = d.O[cur];
@@ -733,8 +823,9 @@ template <class R> struct ForceBatch { static constexpr int U = 4; };
 template <> struct ForceBatch<double> { static constexpr int U = 2; };
 
 template <class R, int DIM, bool REDUCE, bool TERMS>
-__global__ void __launch_bounds__(256) k_force(Dev d, int cur, int star, int remap)
+__global__ void __launch_bounds__(256) k_force(Dev d, int star, int remap)
 {
+    const int cur = *d.curp;
     const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
     const bool valid = i < d.n;
     const Sorted& O = d.O[cur];
@@ -856,25 +947,17 @@ __global__ void __launch_bounds__(256) k_force(Dev d, int cur, int star, int rem
         if (uniform) {
             const double um = wave_max(umag2), am = wave_max(amag2);
             if ((threadIdx.x & 63) == 0) {
-                atomicMax(&d.run[inst0].umax2, (unsigned long long)__double_as_longlong(um));
-                atomicMax(&d.run[inst0].amax2, (unsigned long long)__double_as_longlong(am));
+                max_update(&d.run[inst0].umax2, um);
+                max_update(&d.run[inst0].amax2, am);
             }
         } else if (valid) {
-            atomicMax(&d.run[inst].umax2, (unsigned long long)__double_as_longlong(umag2));
-            atomicMax(&d.run[inst].amax2, (unsigned long long)__double_as_longlong(amag2));
+            max_update(&d.run[inst].umax2, umag2);
+            max_update(&d.run[inst].amax2, amag2);
         }
     }
 }
 
 // ----------------------------------------------------------- time step (a9)
-
-__global__ void k_begin_step(Dev d)
-{
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= d.ninst) return;
-    d.run[b].umax2 = 0ull;
-    d.run[b].amax2 = 0ull;
-}
 
 __global__ void k_dt(Dev d, double dt_override)
 {
@@ -951,8 +1034,9 @@ __device__ __forceinline__ void kahan_add(float& s, float& e, float y)
 
 // S* = S^n + dt/2 R(S^n)
 template <class R, int DIM>
-__global__ void k_predict(Dev d, int cur)
+__global__ void k_predict(Dev d)
 {
+    const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n) return;
     const Sorted& O = d.O[cur];
@@ -988,15 +1072,15 @@ __global__ void k_predict(Dev d, int cur)
 }
 
 // S^{n+1} = S^n + dt R(S*), in place
+// Corrector for one particle; returns |x - x_build|^2 and its instance.
 template <class R, int DIM>
-__global__ void k_correct(Dev d, int cur)
+__device__ __forceinline__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst)
 {
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d.n) return;
     const Sorted& O = d.O[cur];
     const StateSet& S = d.S[cur];
     const uint32_t info = O.info[k];
     const uint32_t b = info_inst(info);
+    inst = b;
     const InstDev& I = d.inst[b];
     const double dt = d.run[b].dt;
     const uint32_t kind = info_kind(info);
@@ -1043,13 +1127,38 @@ __global__ void k_correct(Dev d, int cur)
     ((R4<R>*)S.vel)[k] = v;
     ((R4<R>*)S.aux)[k] = x;
     ((R*)S.rho)[k] = r;
+    const R4<R> xb = ((const R4<R>*)d.xb)[k];
+    const double ex = (double)p.x - (double)xb.x, ey = (double)p.y - (double)xb.y;
+    const double ez = DIM == 3 ? (double)p.z - (double)xb.z : 0.0;
+    return ex * ex + ey * ey + ez * ez;
+}
+
+
+template <class R, int DIM>
+__global__ void k_correct(Dev d)
+{
+    const int cur = *d.curp;
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = k < d.n;
+    double moved2 = 0.0;
+    uint32_t b = 0;
+    if (valid) moved2 = correct_one<R, DIM>(d, cur, k, b);
+    // running maximum of the displacement since the last build, per instance
+    const uint32_t b0 = __shfl(b, 0, 64);
+    if (__all(!valid || b == b0)) {
+        const double m = wave_max(moved2);
+        if ((threadIdx.x & 63) == 0) max_update(&d.run[b0].disp2, m);
+    } else if (valid) {
+        max_update(&d.run[b].disp2, moved2);
+    }
 }
 
 // ------------------------------------------------------- neighbour export
 
 template <class R, int DIM>
-__global__ void k_export(Dev d, int cur, int pass, const uint32_t* __restrict__ off, uint32_t* __restrict__ out)
+__global__ void k_export(Dev d, int pass, const uint32_t* __restrict__ off, uint32_t* __restrict__ out)
 {
+    const int cur = *d.curp;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= d.n) return;
     const Sorted& O = d.O[cur];
@@ -1074,19 +1183,21 @@ __global__ void k_export(Dev d, int cur, int pass, const uint32_t* __restrict__ 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 template <class R, int DIM>
-static void build_impl(const Dev& d, int cur, const Launch& L, hipStream_t s)
+static void build_impl(const Dev& d, const Launch& L, hipStream_t s)
 {
     const int B = 256;
-    hipLaunchKernelGGL((k_hash<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur);
+    const uint32_t* gate = d.flags;
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, d);
+    hipLaunchKernelGGL((k_hash<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
     const uint32_t ntiles = (d.ncell + SCAN_TILE - 1) / SCAN_TILE;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(SCAN_THREADS), 0, s, d.cnt, d.ncell, d.scan_tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, d.scan_tmp, ntiles);
-    hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(SCAN_THREADS), 0, s, d.cnt, d.ncell, d.scan_tmp, d.cstart);
-    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(SCAN_THREADS), 0, s, gate, d.cnt, d.ncell, d.scan_tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, gate, d.scan_tmp, ntiles);
+    hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(SCAN_THREADS), 0, s, gate, d.cnt, d.ncell, d.scan_tmp, d.cstart);
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
     hipLaunchKernelGGL(k_rank, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
-    hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, cur, d.O[cur].ref ? 1 : 0);
-    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, 1 - cur,
-                       L.xcd_remap);
+    hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, d.O[0].ref ? 1 : 0);
+    hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, L.xcd_remap);
 }
 
 #define SPHX_DISPATCH(PREC, DIM, CALL)                                  \
@@ -1100,61 +1211,56 @@ static void build_impl(const Dev& d, int cur, const Launch& L, hipStream_t s)
         }                                                               \
     } while (0)
 
-void launch_build(const Dev& d, int cur, const Launch& L, hipStream_t s)
+void launch_build(const Dev& d, const Launch& L, hipStream_t s)
 {
-    SPHX_DISPATCH(d.precision, d.dim, (build_impl<R, D>(d, cur, L, s)));
+    SPHX_DISPATCH(d.precision, d.dim, (build_impl<R, D>(d, L, s)));
 }
 
-void launch_nlist(const Dev& d, int cur, const Launch& L, hipStream_t s)
+void launch_nlist(const Dev& d, const Launch& L, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, cur,
-                           L.xcd_remap);
+        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, L.xcd_remap);
     }));
 }
 
-void launch_renorm(const Dev& d, int cur, const Launch& L, hipStream_t s)
+void launch_renorm(const Dev& d, bool force, const Launch& L, hipStream_t s)
 {
+    const int f = force ? 1 : 0;
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_renorm<R, D>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, cur,
-                           L.xcd_remap);
-        hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur, 1);
+        hipLaunchKernelGGL((k_renorm<R, D>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d,
+                           L.xcd_remap, f);
+        hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, 1, f);
     }));
 }
 
-void launch_derive(const Dev& d, int cur, const Launch&, hipStream_t s)
+void launch_derive(const Dev& d, const Launch&, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur, 0);
+        hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, 0, 0);
     }));
 }
 
-void launch_colour(const Dev& d, int cur, bool star, const Launch& L, hipStream_t s)
+void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s)
 {
     const dim3 grid(blocks_for(d.n, L.block)), block(L.block);
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_colour<R, D>), grid, block, 0, s, d, cur, star ? 1 : 0, L.xcd_remap);
+        hipLaunchKernelGGL((k_colour<R, D>), grid, block, 0, s, d, star ? 1 : 0, L.xcd_remap);
     }));
 }
 
-void launch_force(const Dev& d, int cur, bool star, bool reduce_max, const Launch& L, hipStream_t s)
+void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hipStream_t s)
 {
     const dim3 grid(blocks_for(d.n, L.block)), block(L.block);
     const int st = star ? 1 : 0;
     SPHX_DISPATCH(d.precision, d.dim, ({
         if (L.debug_terms) {
-            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, true>), grid, block, 0, s, d, cur, st, L.xcd_remap);
-            else hipLaunchKernelGGL((k_force<R, D, false, true>), grid, block, 0, s, d, cur, st, L.xcd_remap);
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, true>), grid, block, 0, s, d, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, false, true>), grid, block, 0, s, d, st, L.xcd_remap);
         } else {
-            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, false>), grid, block, 0, s, d, cur, st, L.xcd_remap);
-            else hipLaunchKernelGGL((k_force<R, D, false, false>), grid, block, 0, s, d, cur, st, L.xcd_remap);
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, false>), grid, block, 0, s, d, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, false, false>), grid, block, 0, s, d, st, L.xcd_remap);
         }
     }));
-}
-
-void launch_begin_step(const Dev& d, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_begin_step, dim3(blocks_for(d.ninst, 256)), dim3(256), 0, s, d);
 }
 
 void launch_dt(const Dev& d, double dt_override, hipStream_t s)
@@ -1167,25 +1273,24 @@ void launch_finish(const Dev& d, hipStream_t s)
     hipLaunchKernelGGL(k_finish, dim3(blocks_for(d.ninst, 256)), dim3(256), 0, s, d);
 }
 
-void launch_predict(const Dev& d, int cur, const Launch&, hipStream_t s)
+void launch_predict(const Dev& d, const Launch&, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_predict<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur);
+        hipLaunchKernelGGL((k_predict<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d);
     }));
 }
 
-void launch_correct(const Dev& d, int cur, const Launch&, hipStream_t s)
+void launch_correct(const Dev& d, const Launch&, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_correct<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur);
+        hipLaunchKernelGGL((k_correct<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d);
     }));
 }
 
-void launch_export(const Dev& d, int cur, int pass, const uint32_t* off, uint32_t* out, const Launch&,
-                   hipStream_t s)
+void launch_export(const Dev& d, int pass, const uint32_t* off, uint32_t* out, const Launch&, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_export<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, cur, pass, off, out);
+        hipLaunchKernelGGL((k_export<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, pass, off, out);
     }));
 }
 

@@ -195,7 +195,6 @@ def test_manual_calls_equal_one_step(prec):
     b.renormalize_density()
     b.compute_forces()
     b.integrate_step(0.0)
-    b.build_neighbors()
     for f in (binding.F_X, binding.F_U, binding.F_RHO):
         assert np.array_equal(a.get_field(f), b.get_field(f))
 
@@ -364,3 +363,31 @@ def test_drift_over_1000_steps_is_reported(tmp_path):
         json.dump(rows, fh, indent=1)
     assert rows[0]["fp64_x_over_dx"] < 1e-9
     assert rows[-1]["fp32_x_over_dx"] < 0.5
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lists_stay_exact_between_conditional_rebuilds(prec):
+    """The sort and the neighbour list are rebuilt only once a particle has moved a
+    quarter of the skin; between rebuilds the sets filtered from the list must equal
+    the oracle's sets at the current positions (FP64), every few steps."""
+    s = inputs.drop2d(perturb=True)
+    sim = binding.Sim(s, precision=prec)
+    builds = [sim.stats()["builds"]]
+    for k in range(6):
+        sim.step(7)
+        builds.append(sim.stats()["builds"])
+        if prec == binding.FP64:
+            s2 = inputs.drop2d(perturb=True)
+            s2.x[:] = sim.get_field(binding.F_X)
+            off, ids = oracle.Oracle(s2).neighbors()
+            goff, gids = sim.get_neighbors()
+            assert np.array_equal(goff, off) and np.array_equal(gids, ids)
+    assert builds[-1] - builds[0] < 42          # not every step
+    assert builds[-1] - builds[0] >= 5          # this fast scene does need rebuilds
+
+
+def test_still_tank_rebuilds_rarely():
+    sim = binding.Sim(inputs.drop2d(), precision=binding.FP32_CELLREL)
+    b0 = sim.stats()["builds"]
+    sim.step(40)
+    assert sim.stats()["builds"] - b0 <= 4
