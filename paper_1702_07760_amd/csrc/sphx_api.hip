@@ -223,7 +223,12 @@ struct Carver {
 
 // Lays every device array out in the workspace (or only measures when base is null).
 // Neighbour-list capacity per particle (lattice: 20 / 80 neighbours within 2h in 2D / 3D).
-uint32_t list_cap(int dim) { return dim == 3 ? 128u : 48u; }
+// Neighbour-list capacity per particle.  The list walk reads whole batches of
+// (entries per batch) x (lanes per particle) <= 16 entries, so the capacity must be a
+// multiple of 16 for those reads to stay inside the list.
+constexpr uint32_t kListCap2 = 48u, kListCap3 = 128u;
+static_assert(kListCap2 % 16u == 0 && kListCap3 % 16u == 0, "list capacity must be a multiple of 16");
+uint32_t list_cap(int dim) { return dim == 3 ? kListCap3 : kListCap2; }
 
 size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t ncell, int ninst)
 {
@@ -501,6 +506,7 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
 
     sphx_ctx* c = new sphx_ctx();
     c->precision = precision;
+    c->launch.force_lanes = precision == 0 ? 2 : 1;   // measured best on the 3D drop
     c->dim = per_inst[0].dim;
     c->ninst = ninst;
     c->nphase = nphase;
@@ -518,7 +524,6 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
     for (int b = 0; b < ninst; ++b) c->inst[b] = make_inst(per_inst[b], &c->phases[(size_t)b * 2], nphase, base[b]);
     c->stream = (hipStream_t)stream;
     c->num_cu = prop.multiProcessorCount;
-    c->launch.num_cu = c->num_cu;
     c->use_graph = stream != nullptr;
     *out = c;
     return SPHX_OK;
@@ -770,6 +775,11 @@ sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
         c->launch.block = (int)value;
         break;
     case SPHX_OPT_XCD_REMAP: c->launch.xcd_remap = value != 0; break;
+    case SPHX_OPT_LANES:
+    case SPHX_OPT_FORCE_LANES:
+        if (value != 1 && value != 2 && value != 4) return fail(c, SPHX_E_ARG, "lanes must be 1, 2 or 4");
+        (option == SPHX_OPT_LANES ? c->launch.lanes : c->launch.force_lanes) = (int)value;
+        break;
     case SPHX_OPT_GRAPH: c->use_graph = value != 0 && c->stream != nullptr; break;
     case SPHX_OPT_PROFILE:
         c->profile = value != 0;

@@ -109,8 +109,8 @@ struct Dev {
 struct Launch {
     int block = 256;
     int xcd_remap = 1;
-    int persistent = 0;  // blocks per CU when > 0
-    int num_cu = 256;
+    int lanes = 4;       // lanes per particle in the renormalisation and colour passes (1, 2, 4)
+    int force_lanes = 1; // lanes per particle in the force pass (1, 2, 4)
     bool debug_terms = false;
 };
 

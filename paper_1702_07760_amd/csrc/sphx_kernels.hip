@@ -1,11 +1,13 @@
 // gfx950 kernels of the two-phase WCSPH step (arXiv 1702.07760, Sec. II).
 //
 // Layout: particles live in cell-sorted order, structure-of-arrays of 16/32-byte
-// records so that a wave reads them coalesced.  One lane owns one particle i and
-// gathers over its neighbours j (no atomics on floating-point data; the only
-// atomics are integer counters, cell masks and the max-reductions of the time
-// step, all order-independent).  Neighbour candidates are the particles of the
-// 3^d cells around i, read as contiguous x-rows of the sorted arrays.
+// records so that a wave reads them coalesced.  In the neighbour passes one lane, or a
+// group of 2 or 4 consecutive lanes, owns particle i and gathers over its neighbours j
+// from a column-major neighbour list; a group splits the list and adds its partial sums
+// with in-wave shuffles.  There are no atomics on floating-point data: the only atomics
+// are integer counters and the order-independent max-reductions of the time step, so
+// every result is deterministic.  Per-instance constants of a neighbour loop are held
+// in scalar registers, one pass per distinct instance in a wave.
 //
 // Two precision forms share every kernel through the template parameter R:
 //   double : absolute FP64 positions, FP64 everything;
@@ -38,7 +40,8 @@ __device__ __forceinline__ uint32_t tile_index(int remap)
 
 __device__ __forceinline__ int wrapi(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-__device__ __forceinline__ void cell_of_key(const InstDev& I, uint32_t key, int c[3])
+template <class IC>
+__device__ __forceinline__ void cell_of_key(const IC& I, uint32_t key, int c[3])
 {
     uint32_t l = key - I.cell_base;
     c[0] = (int)(l % (uint32_t)I.nc[0]);
@@ -87,6 +90,87 @@ __device__ inline void piston(const InstDev& I, double t, double& d, double& v)
     }
 }
 
+// ------------------------------------------- per-instance constants in SGPRs
+
+__device__ __forceinline__ uint32_t ufirst(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int32_t ufirst(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float ufirst(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ double ufirst(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = ufirst((uint32_t)b), hi = ufirst((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// The per-instance constants that the neighbour loops read, held in scalar registers
+// (loaded once per wave instead of once per neighbour).  Built only where every
+// active lane of the wave belongs to one instance; unused fields cost nothing.
+struct InstU {
+    uint32_t cell_base;
+    int32_t nc[3], periodic[3], cont_form, visc_form;
+    double span[3], cut2, cutl2, inv_h, wcoef, fcoef, delta2, alpha_s, g[3], rho0[2], vpair[2][2];
+    float f_cs[3], f_inv_h, f_cut2, f_cutl2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3], f_vpair[2][2];
+};
+
+__device__ __forceinline__ InstU uniform_inst(const InstDev& I)
+{
+    InstU u;
+    u.cell_base = ufirst(I.cell_base);
+    for (int q = 0; q < 3; ++q) {
+        u.nc[q] = ufirst(I.nc[q]);
+        u.periodic[q] = ufirst(I.periodic[q]);
+        u.span[q] = ufirst(I.span[q]);
+        u.g[q] = ufirst(I.g[q]);
+        u.f_cs[q] = ufirst(I.f_cs[q]);
+        u.f_g[q] = ufirst(I.f_g[q]);
+    }
+    u.cont_form = ufirst(I.cont_form);
+    u.visc_form = ufirst(I.visc_form);
+    u.cut2 = ufirst(I.cut2);
+    u.cutl2 = ufirst(I.cutl2);
+    u.inv_h = ufirst(I.inv_h);
+    u.wcoef = ufirst(I.wcoef);
+    u.fcoef = ufirst(I.fcoef);
+    u.delta2 = ufirst(I.delta2);
+    u.alpha_s = ufirst(I.alpha_s);
+    u.f_inv_h = ufirst(I.f_inv_h);
+    u.f_cut2 = ufirst(I.f_cut2);
+    u.f_cutl2 = ufirst(I.f_cutl2);
+    u.f_fcoef = ufirst(I.f_fcoef);
+    u.f_wcoef = ufirst(I.f_wcoef);
+    u.f_delta2 = ufirst(I.f_delta2);
+    u.f_alpha_s = ufirst(I.f_alpha_s);
+    for (int a = 0; a < 2; ++a) {
+        u.rho0[a] = ufirst(I.rho0[a]);
+        for (int b = 0; b < 2; ++b) {
+            u.vpair[a][b] = ufirst(I.vpair[a][b]);
+            u.f_vpair[a][b] = ufirst(I.f_vpair[a][b]);
+        }
+    }
+    return u;
+}
+
+// Runs f(instance constants) for the active lanes, one distinct instance at a time
+// (a single pass when the wave lies inside one instance, the usual case).  The loop is
+// driven by the ballot mask of lanes still to do, a value that changes every pass: a
+// loop keyed on readfirstlane alone looks invariant to the optimiser, which may then
+// assume its first pass covers every lane.
+template <class F>
+__device__ __forceinline__ void per_instance(const Dev& d, uint32_t inst, F&& f)
+{
+    unsigned long long todo = __ballot(1);
+    while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const uint32_t u = ufirst((uint32_t)__shfl((int)inst, leader, 64));
+        const bool mine = inst == u;
+        todo &= ~__ballot(mine);
+        if (mine) {
+            const InstU I = uniform_inst(d.inst[u]);
+            f(I);
+        }
+    }
+}
+
 // --------------------------------------------------------- lane geometry
 
 // What lane i needs to turn a candidate record into r_ij = x_i - x_j.
@@ -95,7 +179,7 @@ template <class R> struct Lane;
 template <> struct Lane<double> {
     double x[3];
     int c[3];
-    __device__ void load(const InstDev& I, const double4& p, uint32_t key)
+    template <class IC> __device__ void load(const IC& I, const double4& p, uint32_t key)
     {
         x[0] = p.x; x[1] = p.y; x[2] = p.z;
         cell_of_key(I, key, c);
@@ -105,7 +189,7 @@ template <> struct Lane<double> {
 template <> struct Lane<float> {
     float o[3];
     int c[3];
-    __device__ void load(const InstDev& I, const float4& p, uint32_t key)
+    template <class IC> __device__ void load(const IC& I, const float4& p, uint32_t key)
     {
         o[0] = p.x; o[1] = p.y; o[2] = p.z;
         cell_of_key(I, key, c);
@@ -136,7 +220,8 @@ __device__ __forceinline__ float dist2(float rx, float ry, float rz)
     return DIM == 3 ? fmaf(rz, rz, fmaf(ry, ry, rx * rx)) : fmaf(ry, ry, rx * rx);
 }
 
-__device__ __forceinline__ double min_image(double v, const InstDev& I, int d)
+template <class IC>
+__device__ __forceinline__ double min_image(double v, const IC& I, int d)
 {
     if (I.periodic[d]) {
         const double L = I.span[d];
@@ -153,8 +238,8 @@ __device__ __forceinline__ uint32_t pos_phase(const float4& p) { return __float_
 
 // r_ij for a stencil candidate (FP64: absolute positions, minimal image).  Returns the
 // list-entry offset code (unused in FP64).
-template <int DIM>
-__device__ __forceinline__ uint32_t pair_r(const InstDev& I, const Lane<double>& L, const Row<double>&,
+template <int DIM, class IC>
+__device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<double>& L, const Row<double>&,
                                            const double4& pj, double r[3])
 {
     r[0] = min_image(L.x[0] - pj.x, I, 0);
@@ -164,8 +249,8 @@ __device__ __forceinline__ uint32_t pair_r(const InstDev& I, const Lane<double>&
 }
 
 // r_ij for a stencil candidate (FP32: cell offsets; pj.w holds j's cell key).
-template <int DIM>
-__device__ __forceinline__ uint32_t pair_r(const InstDev& I, const Lane<float>& L, const Row<float>& row,
+template <int DIM, class IC>
+__device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<float>& L, const Row<float>& row,
                                            const float4& pj, float r[3])
 {
     int dcx = L.c[0] - (int)((__float_as_uint(pj.w) & 0x7fffffffu) - row.base);
@@ -177,8 +262,8 @@ __device__ __forceinline__ uint32_t pair_r(const InstDev& I, const Lane<float>& 
 }
 
 // r_ij for a list entry e (same arithmetic as the stencil form above).
-template <int DIM>
-__device__ __forceinline__ void list_pair_r(const InstDev& I, const Lane<double>& L, const double4& pj,
+template <int DIM, class IC>
+__device__ __forceinline__ void list_pair_r(const IC& I, const Lane<double>& L, const double4& pj,
                                             uint32_t, double r[3])
 {
     r[0] = min_image(L.x[0] - pj.x, I, 0);
@@ -186,8 +271,8 @@ __device__ __forceinline__ void list_pair_r(const InstDev& I, const Lane<double>
     r[2] = DIM == 3 ? min_image(L.x[2] - pj.z, I, 2) : 0.0;
 }
 
-template <int DIM>
-__device__ __forceinline__ void list_pair_r(const InstDev& I, const Lane<float>& L, const float4& pj,
+template <int DIM, class IC>
+__device__ __forceinline__ void list_pair_r(const IC& I, const Lane<float>& L, const float4& pj,
                                             uint32_t e, float r[3])
 {
     const float dx = (float)((int)((e >> 26) & 3u) - 1);
@@ -198,23 +283,28 @@ __device__ __forceinline__ void list_pair_r(const InstDev& I, const Lane<float>&
     r[2] = DIM == 3 ? fmaf(dz, I.f_cs[2], L.o[2] - pj.z) : 0.0f;
 }
 
-template <class R> __device__ __forceinline__ R cut2_of(const InstDev& I);
-template <> __device__ __forceinline__ double cut2_of<double>(const InstDev& I) { return I.cut2; }
-template <> __device__ __forceinline__ float cut2_of<float>(const InstDev& I) { return I.f_cut2; }
-template <class R> __device__ __forceinline__ R cutl2_of(const InstDev& I);
-template <> __device__ __forceinline__ double cutl2_of<double>(const InstDev& I) { return I.cutl2; }
-template <> __device__ __forceinline__ float cutl2_of<float>(const InstDev& I) { return I.f_cutl2; }
+template <class R, class IC> __device__ __forceinline__ R cut2_of(const IC& I)
+{
+    if constexpr (sizeof(R) == 8) return I.cut2;
+    else return I.f_cut2;
+}
+template <class R, class IC> __device__ __forceinline__ R cutl2_of(const IC& I)
+{
+    if constexpr (sizeof(R) == 8) return I.cutl2;
+    else return I.f_cutl2;
+}
 
 // Candidates loaded per batch in the stencil walk (independent loads in flight).
 template <class R> struct StencilBatch { static constexpr int U = 8; };
 template <> struct StencilBatch<double> { static constexpr int U = 4; };
 
 // Visit every j != i with |r_ij|^2 < cut2 among the 3^d cells around i's cell:
-// body(j, r_ij, |r_ij|^2, record of j, list code).
-template <class R, int DIM, class Body>
-__device__ __forceinline__ void for_neighbors(const InstDev& I, const uint32_t* __restrict__ cstart,
+// body(j, r_ij, |r_ij|^2, record of j, list code).  When P lanes share particle i,
+// lane `sub` takes every P-th candidate of each cell run.
+template <class R, int DIM, int P = 1, class IC, class Body>
+__device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __restrict__ cstart,
                                               const R4<R>* __restrict__ pos, uint32_t i,
-                                              const Lane<R>& L, R cut2, Body&& body)
+                                              const Lane<R>& L, R cut2, uint32_t sub, Body&& body)
 {
     constexpr int U = StencilBatch<R>::U;
     const int nx = I.nc[0];
@@ -255,13 +345,13 @@ __device__ __forceinline__ void for_neighbors(const InstDev& I, const uint32_t* 
             }
             for (int seg = 0; seg < 2; ++seg) {
                 const uint32_t a = seg ? a1 : a0, b = seg ? b1 : b0;
-                for (uint32_t k0 = a; k0 < b; k0 += U) {
+                for (uint32_t k0 = a + sub; k0 < b; k0 += U * P) {
                     R4<R> pj[U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) pj[u] = pos[min(k0 + (uint32_t)u, b - 1)];
+                    for (int u = 0; u < U; ++u) pj[u] = pos[min(k0 + (uint32_t)(u * P), b - 1)];
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const uint32_t k = k0 + (uint32_t)u;
+                        const uint32_t k = k0 + (uint32_t)(u * P);
                         if (k < b && k != i) {
                             R r[3];
                             const uint32_t code = pair_r<DIM>(I, L, row, pj[u], r);
@@ -278,23 +368,33 @@ __device__ __forceinline__ void for_neighbors(const InstDev& I, const uint32_t* 
 struct NoExtra {};
 
 // Visit the entries of i's neighbour list with |r_ij|^2 < 4h^2 at the positions `pos`:
-// body(j, r_ij, |r_ij|^2, record of j, load(j)).  U entries are fetched per batch so
-// that their loads are in flight together; entries are stored column-major (entry q of
-// particle i at q * n + i), so a wave reads each batch coalesced.
-template <class R, int DIM, int U, class Load, class Body>
-__device__ __forceinline__ void for_list(const Dev& d, const InstDev& I, const R4<R>* __restrict__ pos,
-                                         uint32_t i, const Lane<R>& L, uint32_t cnt, Load&& load, Body&& body)
+// body(j, r_ij, |r_ij|^2, record of j, load(j)).  Entries are stored column-major
+// (entry q of particle i at q * n + i), so a wave reads them coalesced; U entries are
+// fetched per batch so that their loads are in flight together.  With P lanes per
+// particle, lane `sub` takes the entries q = t P + sub: the row offset t P n is the
+// same for all lanes and the lane part sub n + i is fixed.  A batch may read entries
+// past cnt (never past the capacity, a multiple of U P); they are replaced by a valid
+// index and skipped.
+template <class R, int DIM, int U, int P, class IC, class Load, class Body>
+__device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>* __restrict__ pos,
+                                         uint32_t i, const Lane<R>& L, uint32_t cnt, uint32_t sub,
+                                         Load&& load, Body&& body)
 {
     using X = decltype(load(0u));
-    const uint32_t* __restrict__ nb = d.nbl + i;
-    const size_t n = (size_t)d.n;
+    const uint32_t n = (uint32_t)d.n;
+    const char* __restrict__ base = (const char*)d.nbl;
+    const uint32_t lane_off = (sub * n + i) * 4u;   // < 2^30: n < 2^26, sub < 4
+    const size_t step = (size_t)P * n * 4u;
     const R cut2 = cut2_of<R>(I);
-    for (uint32_t q0 = 0; q0 < cnt; q0 += U) {
+    for (uint32_t t0 = 0; t0 * P + sub < cnt; t0 += U) {
         uint32_t e[U];
         R4<R> pj[U];
         X x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) e[u] = nb[(size_t)min(q0 + (uint32_t)u, cnt - 1) * n];
+        for (int u = 0; u < U; ++u) {
+            const uint32_t raw = *(const uint32_t*)(base + (size_t)(t0 + (uint32_t)u) * step + lane_off);
+            e[u] = (t0 + (uint32_t)u) * P + sub < cnt ? raw : 0u;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t k = e[u] & kIdxMask;
@@ -303,7 +403,7 @@ __device__ __forceinline__ void for_list(const Dev& d, const InstDev& I, const R
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (q0 + (uint32_t)u < cnt) {
+            if ((t0 + (uint32_t)u) * P + sub < cnt) {
                 R r[3];
                 list_pair_r<DIM>(I, L, pj[u], e[u], r);
                 const R r2 = dist2<DIM>(r[0], r[1], r[2]);
@@ -314,19 +414,39 @@ __device__ __forceinline__ void for_list(const Dev& d, const InstDev& I, const R
 }
 
 // Either the list (normal case) or, for a particle whose list overflowed, the stencil.
-template <class R, int DIM, int U, class Load, class Body>
-__device__ __forceinline__ void for_each_neighbor(const Dev& d, const InstDev& I, const R4<R>* __restrict__ pos,
-                                                  uint32_t i, const Lane<R>& L, Load&& load, Body&& body)
+template <class R, int DIM, int U, int P, class IC, class Load, class Body>
+__device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, const R4<R>* __restrict__ pos,
+                                                  uint32_t i, const Lane<R>& L, uint32_t sub, Load&& load,
+                                                  Body&& body)
 {
     const uint32_t cnt = d.nbc[i];
     if (cnt <= d.cap) {
-        for_list<R, DIM, U>(d, I, pos, i, L, cnt, load, body);
+        for_list<R, DIM, U, P>(d, I, pos, i, L, cnt, sub, load, body);
     } else {
-        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, cut2_of<R>(I),
-                              [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t) {
-                                  body(k, r, r2, pj, load(k));
-                              });
+        for_neighbors<R, DIM, P>(I, d.cstart, pos, i, L, cut2_of<R>(I), sub,
+                                 [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t) {
+                                     body(k, r, r2, pj, load(k));
+                                 });
     }
+}
+
+// Sum over the P consecutive lanes that share one particle (P = 1, 2 or 4; the
+// lanes of a group are all active or all inactive).
+template <int P, class T>
+__device__ __forceinline__ T group_sum(T v)
+{
+    if (P >= 2) v += __shfl_xor(v, 1, 64);
+    if (P >= 4) v += __shfl_xor(v, 2, 64);
+    return v;
+}
+
+// Particle and sub-lane of this thread in a neighbour pass with P lanes per particle.
+template <int P>
+__device__ __forceinline__ void lane_split(int remap, uint32_t& i, uint32_t& sub)
+{
+    const uint32_t t = tile_index(remap) * blockDim.x + threadIdx.x;
+    i = t / P;
+    sub = t % P;
 }
 
 // ---------------------------------------------------------- neighbour build
@@ -612,33 +732,34 @@ __global__ void __launch_bounds__(256) k_nlist(Dev d, int remap)
     const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
     const R4<R> pi = pos[i];
     ((R4<R>*)d.xb)[i] = pi;
-    const InstDev& I = d.inst[info_inst(O.info[i])];
-    Lane<R> L;
-    L.load(I, pi, O.key[i]);
-    const uint32_t ph = pos_phase(pi);
-    uint32_t* nb = d.nbl + i;
-    const size_t n = (size_t)d.n;
-    const uint32_t cap = d.cap;
-    uint32_t cnt = 0;
-    bool other = false;
-    for_neighbors<R, DIM>(I, d.cstart, pos, i, L, cutl2_of<R>(I),
-                          [&](uint32_t k, const R*, R, const R4<R>& pj, uint32_t code) {
-                              if (cnt < cap) nb[(size_t)cnt * n] = k | (code << kIdxBits);
-                              ++cnt;
-                              other |= pos_phase(pj) != ph;
-                          });
-    d.nbc[i] = cnt;
-    d.nbx[i] = other ? 1 : 0;
+    per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
+        Lane<R> L;
+        L.load(I, pi, O.key[i]);
+        const uint32_t ph = pos_phase(pi);
+        uint32_t* nb = d.nbl + i;
+        const size_t n = (size_t)d.n;
+        const uint32_t cap = d.cap;
+        uint32_t cnt = 0;
+        bool other = false;
+        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, cutl2_of<R>(I), 0u,
+                              [&](uint32_t k, const R*, R, const R4<R>& pj, uint32_t code) {
+                                  if (cnt < cap) nb[(size_t)cnt * n] = k | (code << kIdxBits);
+                                  ++cnt;
+                                  other |= pos_phase(pj) != ph;
+                              });
+        d.nbc[i] = cnt;
+        d.nbx[i] = other ? 1 : 0;
+    });
 }
 
 // ------------------------------------------------------ per-particle state
 
 // Density of particle k as FP64 (FP32 form stores rho - rho0).
-template <class R>
-__device__ __forceinline__ double rho_of(const InstDev& I, uint32_t phase, R stored)
+template <class R, class IC>
+__device__ __forceinline__ double rho_of(const IC& I, uint32_t phase, R stored)
 {
     if constexpr (sizeof(R) == 8) return stored;
-    else return I.rho0[phase] + (double)stored;
+    else return (phase ? I.rho0[1] : I.rho0[0]) + (double)stored;   // no dynamic index: I may live in SGPRs
 }
 
 // Derived quantities of one particle: V = m / rho into vel.w, m P / rho^2 into aux.y.
@@ -685,33 +806,48 @@ __global__ void k_derive(Dev d, int from_tmp, int force)
 
 // -------------------------------------------------------- Eq. (7) renormalise
 
-template <class R> __device__ __forceinline__ R kernel_w(const InstDev& I, R r2);
-template <> __device__ __forceinline__ double kernel_w<double>(const InstDev& I, double r2)
+// Square root and reciprocal: IEEE in FP64; the single-instruction hardware forms
+// (about 1 ulp) in the FP32 path, whose error budget is set by the cell-relative
+// position encoding.
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+// Wendland C2: W = alpha (1 - q/2)^4 (2q + 1); grad_i W_ij = F r_ij with
+// F = -5 alpha / h^2 (1 - q/2)^3, q = |r| / h.
+template <class R, class IC> __device__ __forceinline__ R kernel_w(const IC& I, R r2)
 {
-    const double q = sqrt(r2) * I.inv_h, t = 1.0 - 0.5 * q, t2 = t * t;
-    return I.wcoef * (t2 * t2) * (2.0 * q + 1.0);
-}
-template <> __device__ __forceinline__ float kernel_w<float>(const InstDev& I, float r2)
-{
-    const float q = sqrtf(r2) * I.f_inv_h, t = 1.0f - 0.5f * q, t2 = t * t;
-    return I.f_wcoef * (t2 * t2) * (2.0f * q + 1.0f);
+    if constexpr (sizeof(R) == 8) {
+        const double q = sqrt(r2) * I.inv_h, t = 1.0 - 0.5 * q, t2 = t * t;
+        return I.wcoef * (t2 * t2) * (2.0 * q + 1.0);
+    } else {
+        const float q = fsqrt(r2) * I.f_inv_h, t = 1.0f - 0.5f * q, t2 = t * t;
+        return I.f_wcoef * (t2 * t2) * (2.0f * q + 1.0f);
+    }
 }
 
-template <class R> __device__ __forceinline__ R kernel_f(const InstDev& I, R r2);
-template <> __device__ __forceinline__ double kernel_f<double>(const InstDev& I, double r2)
+template <class R, class IC> __device__ __forceinline__ R kernel_f(const IC& I, R r2)
 {
-    const double t = 1.0 - 0.5 * (sqrt(r2) * I.inv_h);
-    return I.fcoef * (t * t * t);
-}
-template <> __device__ __forceinline__ float kernel_f<float>(const InstDev& I, float r2)
-{
-    const float t = 1.0f - 0.5f * (sqrtf(r2) * I.f_inv_h);
-    return I.f_fcoef * (t * t * t);
+    if constexpr (sizeof(R) == 8) {
+        const double t = 1.0 - 0.5 * (sqrt(r2) * I.inv_h);
+        return I.fcoef * (t * t * t);
+    } else {
+        const float t = 1.0f - 0.5f * (fsqrt(r2) * I.f_inv_h);
+        return I.f_fcoef * (t * t * t);
+    }
 }
 
-template <class R, int DIM>
-__device__ __forceinline__ void renorm_one(const Dev& d, int cur, uint32_t i)
+template <class R, int DIM, int P>
+__global__ void __launch_bounds__(256) k_renorm(Dev d, int remap, int force)
 {
+    if (!force && !renorm_due(d)) return;
+    uint32_t i, sub;
+    lane_split<P>(remap, i, sub);
+    if (i >= d.n) return;
+    const int cur = *d.curp;
     const Sorted& O = d.O[cur];
     const StateSet& S = d.S[cur];
     const R4<R>* pos = (const R4<R>*)S.pos;
@@ -719,59 +855,55 @@ __device__ __forceinline__ void renorm_one(const Dev& d, int cur, uint32_t i)
     const R4<R>* aux = (const R4<R>*)S.aux;
     const R* rho = (const R*)S.rho;
     const R4<R> pi = pos[i];
-    const InstDev& I = d.inst[info_inst(O.info[i])];
     const uint32_t ph = pos_phase(pi);
-    Lane<R> L;
-    L.load(I, pi, O.key[i]);
-    const R w0 = kernel_w<R>(I, (R)0);
-    struct Pair { R a, b; };
-    R num, den;
-    if constexpr (sizeof(R) == 8) {
-        // Eq. (7) as written: sum m_j W_ij / sum (m_j / rho_j) W_ij, self included
-        num = aux[i].x * w0;
-        den = vel[i].w * w0;
-        for_each_neighbor<R, DIM, 2>(d, I, pos, i, L,
-            [&](uint32_t k) { return Pair{aux[k].x, vel[k].w}; },
-            [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
-                if (pos_phase(pj) != ph) return;
-                const R w = kernel_w<R>(I, r2);
-                num += x.a * w;
-                den += x.b * w;
-            });
-    } else {
-        // the same quotient minus rho0, as a V_j W_ij-weighted mean of (rho_j - rho0):
-        // m_j - rho0 V_j = V_j (rho_j - rho0), so nothing cancels in FP32
-        num = vel[i].w * w0 * rho[i];
-        den = vel[i].w * w0;
-        for_each_neighbor<R, DIM, 4>(d, I, pos, i, L,
-            [&](uint32_t k) { return Pair{vel[k].w, rho[k]}; },
-            [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
-                if (pos_phase(pj) != ph) return;
-                const R vw = x.a * kernel_w<R>(I, r2);
-                num += vw * x.b;
-                den += vw;
-            });
-    }
-    ((R*)d.rho_tmp)[i] = num / den;
-}
-
-template <class R, int DIM>
-__global__ void __launch_bounds__(256) k_renorm(Dev d, int remap, int force)
-{
-    if (!force && !renorm_due(d)) return;
-    const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
-    if (i >= d.n) return;
-    renorm_one<R, DIM>(d, *d.curp, i);
+    per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
+        Lane<R> L;
+        L.load(I, pi, O.key[i]);
+        // the self term once per particle, on its first lane
+        const R w0 = sub == 0 ? kernel_w<R>(I, (R)0) : (R)0;
+        struct Pair { R a, b; };
+        R num, den;
+        if constexpr (sizeof(R) == 8) {
+            // Eq. (7) as written: sum m_j W_ij / sum (m_j / rho_j) W_ij, self included
+            num = aux[i].x * w0;
+            den = vel[i].w * w0;
+            for_each_neighbor<R, DIM, 2, P>(d, I, pos, i, L, sub,
+                [&](uint32_t k) { return Pair{aux[k].x, vel[k].w}; },
+                [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
+                    if (pos_phase(pj) != ph) return;
+                    const R w = kernel_w<R>(I, r2);
+                    num += x.a * w;
+                    den += x.b * w;
+                });
+        } else {
+            // the same quotient minus rho0, as a V_j W_ij-weighted mean of (rho_j - rho0):
+            // m_j - rho0 V_j = V_j (rho_j - rho0), so nothing cancels in FP32
+            num = vel[i].w * w0 * rho[i];
+            den = vel[i].w * w0;
+            for_each_neighbor<R, DIM, 4, P>(d, I, pos, i, L, sub,
+                [&](uint32_t k) { return Pair{vel[k].w, rho[k]}; },
+                [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
+                    if (pos_phase(pj) != ph) return;
+                    const R vw = x.a * kernel_w<R>(I, r2);
+                    num += vw * x.b;
+                    den += vw;
+                });
+        }
+        num = group_sum<P>(num);
+        den = group_sum<P>(den);
+        if (sub == 0) ((R*)d.rho_tmp)[i] = num / den;
+    });
 }
 
 // ----------------------------------------------- Eq. (16) colour gradient (pass A)
 
-template <class R, int DIM>
+template <class R, int DIM, int P>
 __global__ void __launch_bounds__(256) k_colour(Dev d, int star, int remap)
 {
-    const int cur = *d.curp;
-    const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
+    uint32_t i, sub;
+    lane_split<P>(remap, i, sub);
     if (i >= d.n) return;
+    const int cur = *d.curp;
     const Sorted& O = d.O[cur];
     const StateSet& S = star ? d.star : d.S[cur];
     R4<R>* gc = (R4<R>*)d.gc;
@@ -782,30 +914,33 @@ __global__ void __launch_bounds__(256) k_colour(Dev d, int star, int remap)
         const R4<R>* pos = (const R4<R>*)S.pos;
         const R4<R>* vel = (const R4<R>*)S.vel;
         const R4<R> pi = pos[i];
-        const InstDev& I = d.inst[info_inst(O.info[i])];
         const uint32_t ph = pos_phase(pi);
-        Lane<R> L;
-        L.load(I, pi, O.key[i]);
         R s[3] = {0, 0, 0};
-        for_each_neighbor<R, DIM, 4>(d, I, pos, i, L, [](uint32_t) { return NoExtra{}; },
-            [&](uint32_t k, const R* r, R r2, const R4<R>& pj, NoExtra) {
-                if (pos_phase(pj) == ph) return;             // C_j^y = 1 only for the other phase
-                const R vk = vel[k].w;                       // 1 / sigma_k
-                const R f = kernel_f<R>(I, r2) * (vk * vk);
-                s[0] += f * r[0];
-                s[1] += f * r[1];
-                s[2] += f * r[2];
-            });
+        per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
+            Lane<R> L;
+            L.load(I, pi, O.key[i]);
+            for_each_neighbor<R, DIM, 4, P>(d, I, pos, i, L, sub, [](uint32_t) { return NoExtra{}; },
+                [&](uint32_t k, const R* r, R r2, const R4<R>& pj, NoExtra) {
+                    if (pos_phase(pj) == ph) return;             // C_j^y = 1 only for the other phase
+                    const R vk = vel[k].w;                       // 1 / sigma_k
+                    const R f = kernel_f<R>(I, r2) * (vk * vk);
+                    s[0] += f * r[0];
+                    s[1] += f * r[1];
+                    s[2] += f * r[2];
+                });
+        });
         const R vi = vel[i].w;                               // sigma_i = 1 / V_i
-        g[0] = s[0] / vi;
-        g[1] = s[1] / vi;
-        g[2] = s[2] / vi;
+        g[0] = group_sum<P>(s[0]) / vi;
+        g[1] = group_sum<P>(s[1]) / vi;
+        g[2] = group_sum<P>(s[2]) / vi;
         gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
     }
-    R4<R> out;
-    out.x = g[0]; out.y = g[1]; out.z = g[2]; out.w = gn;
-    gc[i] = out;
-    aux[i].z = gn > 0 ? (R)1 : (R)0;
+    if (sub == 0) {
+        R4<R> out;
+        out.x = g[0]; out.y = g[1]; out.z = g[2]; out.w = gn;
+        gc[i] = out;
+        aux[i].z = gn > 0 ? (R)1 : (R)0;
+    }
 }
 
 // ------------------------------------------ Eqs. (6), (8), (10)/(11), (17) (pass B)
@@ -815,18 +950,24 @@ template <class R, int DIM>
 __device__ __forceinline__ void tension_dot(R c, const R g[3], R gn2, const R w[3], R out[3])
 {
     const R gw = g[0] * w[0] + g[1] * w[1] + g[2] * w[2];
-    const R iso = gn2 / (R)DIM;
+    const R iso = gn2 * (R)(1.0 / DIM);
     for (int a = 0; a < 3; ++a) out[a] = c * (iso * w[a] - g[a] * gw);
 }
 
-template <class R> struct ForceBatch { static constexpr int U = 4; };
+// List entries per batch in the force pass: more loads in flight per wave against
+// more registers (fewer waves per SIMD).  U * lanes must divide the list capacity.
+#ifndef SPHX_FORCE_BATCH
+#define SPHX_FORCE_BATCH 4
+#endif
+template <class R> struct ForceBatch { static constexpr int U = SPHX_FORCE_BATCH; };
 template <> struct ForceBatch<double> { static constexpr int U = 2; };
 
-template <class R, int DIM, bool REDUCE, bool TERMS>
+template <class R, int DIM, int P, bool REDUCE, bool TERMS>
 __global__ void __launch_bounds__(256) k_force(Dev d, int star, int remap)
 {
     const int cur = *d.curp;
-    const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
+    uint32_t i, sub;
+    lane_split<P>(remap, i, sub);
     const bool valid = i < d.n;
     const Sorted& O = d.O[cur];
     const StateSet& S = star ? d.star : d.S[cur];
@@ -840,103 +981,118 @@ __global__ void __launch_bounds__(256) k_force(Dev d, int star, int remap)
     if (valid) {
         const uint32_t info = O.info[i];
         inst = info_inst(info);
-        const InstDev& I = d.inst[inst];
-        const uint32_t ph = info_phase(info);
-        const bool fluid = info_kind(info) == K_FLUID;
-        const R4<R> pi = pos[i];
-        Lane<R> L;
-        L.load(I, pi, O.key[i]);
-        const R4<R> vi = vel[i];
-        const R4<R> xi = aux[i];                 // (m, m A, flag)
-        const R mi = xi.x;
-        const R Ai = xi.y / mi;                  // P_i / rho_i^2
-        const bool fli = xi.z != (R)0;
-        R gi[3] = {0, 0, 0}, ci = 0, gi2 = 0;
-        const R alpha = sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s;
-        if (fli) {
-            const R4<R> g4 = gc[i];
-            gi[0] = g4.x; gi[1] = g4.y; gi[2] = g4.z;
-            gi2 = g4.w * g4.w;
-            ci = alpha * (vi.w * vi.w) / g4.w;
-        }
-        R vp0, vp1, delta2;
-        if constexpr (sizeof(R) == 8) { vp0 = I.vpair[ph][0]; vp1 = I.vpair[ph][1]; delta2 = I.delta2; }
-        else { vp0 = I.f_vpair[ph][0]; vp1 = I.f_vpair[ph][1]; delta2 = I.f_delta2; }
-        const bool massform = I.cont_form == 1;
-        R cont = 0, ap[3] = {0, 0, 0}, av[3] = {0, 0, 0}, as[3] = {0, 0, 0};
-        uint32_t cnt = 0;
-        struct VA { R4<R> v, a; };
-        for_each_neighbor<R, DIM, ForceBatch<R>::U>(d, I, pos, i, L,
-            [&](uint32_t k) { return VA{vel[k], aux[k]}; },
-            [&](uint32_t k, const R* r, R r2, const R4<R>& pj, const VA& x) {
-                ++cnt;
-                const R F = kernel_f<R>(I, r2);
-                const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
-                const R4<R>& vk = x.v;
-                const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
-                const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
-                const R4<R>& xk = x.a;
-                cont += (massform ? xk.x : vk.w) * udw;                   // Eq. (6) / (5)
-                if (!fluid) return;
-                const R pc = xk.x * Ai + xk.y;                            // m_j (A_i + A_j)
-                ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
-                const R lap = (F * r2) / (r2 + delta2);                   // r.gradW / (r^2 + delta^2)
-                const R cv = vk.w * (pos_phase(pj) ? vp1 : vp0) * lap;
-                av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
-                const bool flk = xk.z != (R)0;
-                if (fli || flk) {
-                    R t[3];
-                    if (fli) {
-                        tension_dot<R, DIM>(ci, gi, gi2, w, t);
-                        as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+        per_instance(d, inst, [&](const InstU& I) {
+            const uint32_t ph = info_phase(info);
+            const bool fluid = info_kind(info) == K_FLUID;
+            const R4<R> pi = pos[i];
+            Lane<R> L;
+            L.load(I, pi, O.key[i]);
+            const R4<R> vi = vel[i];
+            const R4<R> xi = aux[i];                 // (m, m A, flag)
+            const R mi = xi.x;
+            const R Ai = xi.y / mi;                  // P_i / rho_i^2
+            const bool fli = xi.z != (R)0;
+            R gi[3] = {0, 0, 0}, ci = 0, gi2 = 0;
+            const R alpha = sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s;
+            if (fli) {
+                const R4<R> g4 = gc[i];
+                gi[0] = g4.x; gi[1] = g4.y; gi[2] = g4.z;
+                gi2 = g4.w * g4.w;
+                ci = alpha * (vi.w * vi.w) / g4.w;
+            }
+            R vp0, vp1, delta2;
+            // selects, not a dynamic index, keep the table in scalar registers
+            if constexpr (sizeof(R) == 8) {
+                vp0 = ph ? I.vpair[1][0] : I.vpair[0][0];
+                vp1 = ph ? I.vpair[1][1] : I.vpair[0][1];
+                delta2 = I.delta2;
+            } else {
+                vp0 = ph ? I.f_vpair[1][0] : I.f_vpair[0][0];
+                vp1 = ph ? I.f_vpair[1][1] : I.f_vpair[0][1];
+                delta2 = I.f_delta2;
+            }
+            const bool massform = I.cont_form == 1;
+            R cont = 0, ap[3] = {0, 0, 0}, av[3] = {0, 0, 0}, as[3] = {0, 0, 0};
+            uint32_t cnt = 0;
+            struct VA { R4<R> v, a; };
+            for_each_neighbor<R, DIM, ForceBatch<R>::U, P>(d, I, pos, i, L, sub,
+                [&](uint32_t k) { return VA{vel[k], aux[k]}; },
+                [&](uint32_t k, const R* r, R r2, const R4<R>& pj, const VA& x) {
+                    ++cnt;
+                    const R F = kernel_f<R>(I, r2);
+                    const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
+                    const R4<R>& vk = x.v;
+                    const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
+                    const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+                    const R4<R>& xk = x.a;
+                    cont += (massform ? xk.x : vk.w) * udw;                   // Eq. (6) / (5)
+                    if (!fluid) return;
+                    const R pc = xk.x * Ai + xk.y;                            // m_j (A_i + A_j)
+                    ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
+                    const R lap = (F * r2) * frcp(r2 + delta2);               // r.gradW / (r^2 + delta^2)
+                    const R cv = vk.w * (pos_phase(pj) ? vp1 : vp0) * lap;
+                    av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
+                    const bool flk = xk.z != (R)0;
+                    if (fli || flk) {
+                        R t[3];
+                        if (fli) {
+                            tension_dot<R, DIM>(ci, gi, gi2, w, t);
+                            as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+                        }
+                        if (flk) {
+                            const R4<R> g4 = gc[k];
+                            const R gk[3] = {g4.x, g4.y, g4.z};
+                            const R ck = fdiv(alpha * (vk.w * vk.w), g4.w);
+                            tension_dot<R, DIM>(ck, gk, g4.w * g4.w, w, t);
+                            as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+                        }
                     }
-                    if (flk) {
-                        const R4<R> g4 = gc[k];
-                        const R gk[3] = {g4.x, g4.y, g4.z};
-                        const R ck = alpha * (vk.w * vk.w) / g4.w;
-                        tension_dot<R, DIM>(ck, gk, g4.w * g4.w, w, t);
-                        as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
-                    }
-                }
-            });
-        nint = cnt;
-        const double rho_i = rho_of<R>(I, ph, ((const R*)S.rho)[i]);
-        R4<R> out;
-        out.w = massform ? cont : (R)rho_i * cont;
-        R a[3] = {0, 0, 0};
-        if (fluid) {
-            const R vfac = I.visc_form == 1 ? (R)(1.0 / rho_i) : (R)1;
+                });
+            nint = cnt;
+            cont = group_sum<P>(cont);
             for (int q = 0; q < 3; ++q) {
-                av[q] *= vfac;
-                as[q] /= mi;
-                const R gq = sizeof(R) == 8 ? (R)I.g[q] : (R)I.f_g[q];
-                a[q] = ap[q] + av[q] + as[q] + gq;
+                ap[q] = group_sum<P>(ap[q]);
+                av[q] = group_sum<P>(av[q]);
+                as[q] = group_sum<P>(as[q]);
             }
-        }
-        out.x = a[0]; out.y = a[1]; out.z = a[2];
-        ((R4<R>*)d.acc)[i] = out;
-        if (TERMS) {
-            R4<R>* T = (R4<R>*)d.terms;
-            R4<R> t;
-            t.w = 0;
-            t.x = fluid ? ap[0] : 0; t.y = fluid ? ap[1] : 0; t.z = fluid ? ap[2] : 0;
-            T[3 * (size_t)i + 0] = t;
-            t.x = av[0]; t.y = av[1]; t.z = av[2];
-            T[3 * (size_t)i + 1] = t;
-            t.x = as[0]; t.y = as[1]; t.z = as[2];
-            T[3 * (size_t)i + 2] = t;
-        }
-        if (!isfinite((double)out.x) || !isfinite((double)out.y) || !isfinite((double)out.z) ||
-            !isfinite((double)out.w))
-            atomicOr(d.status, ST_NONFINITE);
-        if (REDUCE) {
-            const uint32_t kind = info_kind(info);
-            if (kind != K_WALL) {
-                const double ux = vi.x, uy = vi.y, uz = vi.z;
-                umag2 = ux * ux + uy * uy + uz * uz;
+            const double rho_i = rho_of<R>(I, ph, ((const R*)S.rho)[i]);
+            R4<R> out;
+            out.w = massform ? cont : (R)rho_i * cont;
+            R a[3] = {0, 0, 0};
+            if (fluid) {
+                const R vfac = I.visc_form == 1 ? (R)(1.0 / rho_i) : (R)1;
+                for (int q = 0; q < 3; ++q) {
+                    av[q] *= vfac;
+                    as[q] /= mi;
+                    const R gq = sizeof(R) == 8 ? (R)I.g[q] : (R)I.f_g[q];
+                    a[q] = ap[q] + av[q] + as[q] + gq;
+                }
             }
-            if (fluid) amag2 = (double)a[0] * a[0] + (double)a[1] * a[1] + (double)a[2] * a[2];
-        }
+            out.x = a[0]; out.y = a[1]; out.z = a[2];
+            if (sub == 0) ((R4<R>*)d.acc)[i] = out;
+            if (TERMS && sub == 0) {
+                R4<R>* T = (R4<R>*)d.terms;
+                R4<R> t;
+                t.w = 0;
+                t.x = fluid ? ap[0] : 0; t.y = fluid ? ap[1] : 0; t.z = fluid ? ap[2] : 0;
+                T[3 * (size_t)i + 0] = t;
+                t.x = av[0]; t.y = av[1]; t.z = av[2];
+                T[3 * (size_t)i + 1] = t;
+                t.x = as[0]; t.y = as[1]; t.z = as[2];
+                T[3 * (size_t)i + 2] = t;
+            }
+            if (!isfinite((double)out.x) || !isfinite((double)out.y) || !isfinite((double)out.z) ||
+                !isfinite((double)out.w))
+                atomicOr(d.status, ST_NONFINITE);
+            if (REDUCE && sub == 0) {
+                const uint32_t kind = info_kind(info);
+                if (kind != K_WALL) {
+                    const double ux = vi.x, uy = vi.y, uz = vi.z;
+                    umag2 = ux * ux + uy * uy + uz * uz;
+                }
+                if (fluid) amag2 = (double)a[0] * a[0] + (double)a[1] * a[1] + (double)a[2] * a[2];
+            }
+        });
     }
     // wave-level reductions: interaction count always, |u|^2 and |a|^2 maxima at S^n
     const unsigned long long wsum = wave_sum(nint);
@@ -1170,7 +1326,7 @@ __global__ void k_export(Dev d, int pass, const uint32_t* __restrict__ off, uint
     uint32_t c = 0;
     const uint32_t base = pass ? off[i] : 0;
     // the same neighbour walk as the physics passes
-    for_each_neighbor<R, DIM, 4>(d, I, pos, i, L, [](uint32_t) { return NoExtra{}; },
+    for_each_neighbor<R, DIM, 4, 1>(d, I, pos, i, L, 0u, [](uint32_t) { return NoExtra{}; },
         [&](uint32_t k, const R*, R, const R4<R>&, NoExtra) {
             if (pass) out[base + c] = O.id[k];
             ++c;
@@ -1223,12 +1379,20 @@ void launch_nlist(const Dev& d, const Launch& L, hipStream_t s)
     }));
 }
 
+// Lanes per particle of the neighbour passes: 1, 2 or 4 (checked by the runtime).
+#define SPHX_LANES(LANES, CALL)                                         \
+    do {                                                                \
+        if ((LANES) == 4) { constexpr int P = 4; CALL; }                \
+        else if ((LANES) == 2) { constexpr int P = 2; CALL; }           \
+        else { constexpr int P = 1; CALL; }                             \
+    } while (0)
+
 void launch_renorm(const Dev& d, bool force, const Launch& L, hipStream_t s)
 {
     const int f = force ? 1 : 0;
+    const dim3 grid(blocks_for(d.n * L.lanes, L.block)), block(L.block);
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_renorm<R, D>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d,
-                           L.xcd_remap, f);
+        SPHX_LANES(L.lanes, ({ hipLaunchKernelGGL((k_renorm<R, D, P>), grid, block, 0, s, d, L.xcd_remap, f); }));
         hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, 1, f);
     }));
 }
@@ -1242,25 +1406,27 @@ void launch_derive(const Dev& d, const Launch&, hipStream_t s)
 
 void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s)
 {
-    const dim3 grid(blocks_for(d.n, L.block)), block(L.block);
+    const dim3 grid(blocks_for(d.n * L.lanes, L.block)), block(L.block);
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_colour<R, D>), grid, block, 0, s, d, star ? 1 : 0, L.xcd_remap);
+        SPHX_LANES(L.lanes, ({
+            hipLaunchKernelGGL((k_colour<R, D, P>), grid, block, 0, s, d, star ? 1 : 0, L.xcd_remap);
+        }));
     }));
 }
 
 void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hipStream_t s)
 {
-    const dim3 grid(blocks_for(d.n, L.block)), block(L.block);
+    const dim3 grid(blocks_for(d.n * L.force_lanes, L.block)), block(L.block);
     const int st = star ? 1 : 0;
-    SPHX_DISPATCH(d.precision, d.dim, ({
+    SPHX_DISPATCH(d.precision, d.dim, SPHX_LANES(L.force_lanes, ({
         if (L.debug_terms) {
-            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, true>), grid, block, 0, s, d, st, L.xcd_remap);
-            else hipLaunchKernelGGL((k_force<R, D, false, true>), grid, block, 0, s, d, st, L.xcd_remap);
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, P, true, true>), grid, block, 0, s, d, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, P, false, true>), grid, block, 0, s, d, st, L.xcd_remap);
         } else {
-            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, true, false>), grid, block, 0, s, d, st, L.xcd_remap);
-            else hipLaunchKernelGGL((k_force<R, D, false, false>), grid, block, 0, s, d, st, L.xcd_remap);
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, P, true, false>), grid, block, 0, s, d, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, P, false, false>), grid, block, 0, s, d, st, L.xcd_remap);
         }
-    }));
+    })));
 }
 
 void launch_dt(const Dev& d, double dt_override, hipStream_t s)

@@ -89,12 +89,15 @@ def test_neighbour_sets_fp32_cell_relative(name, oracle_rates):
     assert len(diff) <= 1e-4 * len(a)
 
 
+@pytest.mark.parametrize("lanes", [1, 2, 4])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("name", list(SCENES))
-def test_rates_match_oracle(name, prec, oracle_rates):
+def test_rates_match_oracle(name, prec, lanes, oracle_rates):
     s, ref, _ = oracle_rates(name)
-    print(f"case rates {name} precision={prec} n={s.n}", flush=True)
+    print(f"case rates {name} precision={prec} lanes={lanes} n={s.n}", flush=True)
     sim = binding.Sim(s, precision=prec)
+    sim.set_option(binding.OPT_LANES, lanes)
+    sim.set_option(binding.OPT_FORCE_LANES, lanes)
     sim.set_option(binding.OPT_DEBUG_TERMS, 1)
     sim.renormalize_density()
     sim.compute_forces()
@@ -116,21 +119,24 @@ def test_rates_match_oracle(name, prec, oracle_rates):
     assert rel_to(P, ref[oracle.P], np.abs(ref[oracle.P]).max()) < 10 * tol
 
 
-def _one_step(scene, prec, nsteps=1):
+def _one_step(scene, prec, nsteps=1, lanes=1):
     o = oracle.Oracle(scene)
     o.step(nsteps)
     sim = binding.Sim(scene, precision=prec)
+    sim.set_option(binding.OPT_LANES, lanes)
+    sim.set_option(binding.OPT_FORCE_LANES, lanes)
     sim.step(nsteps)
     sim.sync()
     return o, sim
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("name", ["drop2d", "drop3d_small", "periodic3d", "drop2d_eq11_eq5"])
-def test_one_step_matches_oracle(name, prec):
+def test_one_step_matches_oracle(name, prec, lanes):
     s = SCENES[name]()
-    print(f"case step {name} precision={prec} n={s.n}", flush=True)
-    o, sim = _one_step(s, prec)
+    print(f"case step {name} precision={prec} lanes={lanes} n={s.n}", flush=True)
+    o, sim = _one_step(s, prec, lanes=lanes)
     dx = s.dx[0]
     rho0 = max(p[0] for p in s.phases[0])
     ur = np.abs(o.get(oracle.U)).max()
@@ -154,13 +160,16 @@ def test_neighbour_sets_stay_exact_after_gpu_steps():
     assert np.array_equal(goff, off) and np.array_equal(gids, ids)
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("prec", PRECS)
-def test_steps_are_deterministic_and_graph_matches_eager(prec):
+def test_steps_are_deterministic_and_graph_matches_eager(prec, lanes):
     s = inputs.drop2d(perturb=True)
     a = binding.Sim(s, precision=prec)
     b = binding.Sim(s, precision=prec)
     c = binding.Sim(s, precision=prec, graph=False)
     for sim in (a, b, c):
+        sim.set_option(binding.OPT_LANES, lanes)
+        sim.set_option(binding.OPT_FORCE_LANES, lanes)
         sim.step(6)
         sim.sync()
     for f in (binding.F_X, binding.F_U, binding.F_RHO):
@@ -263,11 +272,15 @@ def clumped2d(extra=40, seed=3):
 SCENES["clumped2d"] = clumped2d
 
 
+@pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("prec", PRECS)
-def test_list_overflow_falls_back_to_the_stencil(prec, oracle_rates):
+def test_list_overflow_falls_back_to_the_stencil(prec, lanes, oracle_rates):
     s, ref, (off, ids) = oracle_rates("clumped2d")
     assert np.diff(off).max() > 48                  # beyond the 2D list capacity
+    print(f"case overflow precision={prec} lanes={lanes}", flush=True)
     sim = binding.Sim(s, precision=prec)
+    sim.set_option(binding.OPT_LANES, lanes)
+    sim.set_option(binding.OPT_FORCE_LANES, lanes)
     if prec == binding.FP64:
         goff, gids = sim.get_neighbors()
         assert np.array_equal(goff, off) and np.array_equal(gids, ids)
