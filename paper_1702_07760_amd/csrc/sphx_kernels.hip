@@ -300,13 +300,13 @@ template <> struct StencilBatch<double> { static constexpr int U = 4; };
 
 // Visit every j != i with |r_ij|^2 < cut2 among the 3^d cells around i's cell:
 // body(j, r_ij, |r_ij|^2, record of j, list code).  When P lanes share particle i,
-// lane `sub` takes every P-th candidate of each cell run.
-template <class R, int DIM, int P = 1, class IC, class Body>
+// lane `sub` takes every P-th candidate of each cell run.  U candidates are loaded per
+// batch.
+template <class R, int DIM, int P = 1, int U = StencilBatch<R>::U, class IC, class Body>
 __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __restrict__ cstart,
                                               const R4<R>* __restrict__ pos, uint32_t i,
                                               const Lane<R>& L, R cut2, uint32_t sub, Body&& body)
 {
-    constexpr int U = StencilBatch<R>::U;
     const int nx = I.nc[0];
     const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
@@ -367,6 +367,11 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
 
 struct NoExtra {};
 
+// Largest block of the neighbour passes.  Larger blocks (tried up to 1024 threads) were
+// slower on the 3D drop: fewer, larger workgroups leave a longer tail, and the register
+// cap of a 1024-thread block (128) makes the force pass spill.
+template <class R> struct MaxBlock { static constexpr int value = 256; };
+
 // Visit the entries of i's neighbour list with |r_ij|^2 < 4h^2 at the positions `pos`:
 // body(j, r_ij, |r_ij|^2, record of j, load(j)).  Entries are stored column-major
 // (entry q of particle i at q * n + i), so a wave reads them coalesced; U entries are
@@ -414,6 +419,8 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
 }
 
 // Either the list (normal case) or, for a particle whose list overflowed, the stencil.
+// The stencil fallback is rare and walks one candidate at a time: batching it would
+// raise the register count, and so lower the occupancy, of the common list path.
 template <class R, int DIM, int U, int P, class IC, class Load, class Body>
 __device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, const R4<R>* __restrict__ pos,
                                                   uint32_t i, const Lane<R>& L, uint32_t sub, Load&& load,
@@ -423,7 +430,7 @@ __device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, con
     if (cnt <= d.cap) {
         for_list<R, DIM, U, P>(d, I, pos, i, L, cnt, sub, load, body);
     } else {
-        for_neighbors<R, DIM, P>(I, d.cstart, pos, i, L, cut2_of<R>(I), sub,
+        for_neighbors<R, DIM, P, 1>(I, d.cstart, pos, i, L, cut2_of<R>(I), sub,
                                  [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t) {
                                      body(k, r, r2, pj, load(k));
                                  });
@@ -722,7 +729,7 @@ __global__ void k_decide(Dev d)
 // pair within 2h at the predicted positions of the step as well.  Also flags
 // particles with an other-phase particle in their list (interface candidates).
 template <class R, int DIM>
-__global__ void __launch_bounds__(256) k_nlist(Dev d, int remap)
+__global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
 {
     if (!d.flags[0]) return;
     const int cur = *d.curp;
@@ -841,7 +848,7 @@ template <class R, class IC> __device__ __forceinline__ R kernel_f(const IC& I, 
 }
 
 template <class R, int DIM, int P>
-__global__ void __launch_bounds__(256) k_renorm(Dev d, int remap, int force)
+__global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap, int force)
 {
     if (!force && !renorm_due(d)) return;
     uint32_t i, sub;
@@ -898,7 +905,7 @@ __global__ void __launch_bounds__(256) k_renorm(Dev d, int remap, int force)
 // ----------------------------------------------- Eq. (16) colour gradient (pass A)
 
 template <class R, int DIM, int P>
-__global__ void __launch_bounds__(256) k_colour(Dev d, int star, int remap)
+__global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star, int remap)
 {
     uint32_t i, sub;
     lane_split<P>(remap, i, sub);
@@ -963,7 +970,7 @@ template <class R> struct ForceBatch { static constexpr int U = SPHX_FORCE_BATCH
 template <> struct ForceBatch<double> { static constexpr int U = 2; };
 
 template <class R, int DIM, int P, bool REDUCE, bool TERMS>
-__global__ void __launch_bounds__(256) k_force(Dev d, int star, int remap)
+__global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, int remap)
 {
     const int cur = *d.curp;
     uint32_t i, sub;

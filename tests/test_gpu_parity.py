@@ -404,3 +404,25 @@ def test_still_tank_rebuilds_rarely():
     b0 = sim.stats()["builds"]
     sim.step(40)
     assert sim.stats()["builds"] - b0 <= 4
+
+
+@pytest.mark.parametrize("block", [64, 128, 192])
+def test_rates_with_other_block_sizes(block, oracle_rates):
+    s, ref, _ = oracle_rates("drop3d_small")
+    print(f"case rates block={block}", flush=True)
+    sim = binding.Sim(s, precision=binding.FP32_CELLREL)
+    sim.set_option(binding.OPT_BLOCK, block)
+    sim.renormalize_density()
+    sim.compute_forces()
+    sim.sync()
+    tol = TOL[binding.FP32_CELLREL]
+    assert rel_to(sim.get_field(binding.F_RHO), ref[oracle.RHO], 1000.0) < tol
+    total_scale = ref[oracle.SAP] + ref[oracle.SAV] + ref[oracle.SAS]
+    assert enorm(sim.get_field(binding.F_A), ref[oracle.A], total_scale) < tol
+
+
+def test_blocks_above_256_are_rejected():
+    sim = binding.Sim(inputs.drop2d(), precision=binding.FP64)
+    with pytest.raises(binding.SphxError, match="block"):
+        sim.set_option(binding.OPT_BLOCK, 512)
+    sim.set_option(binding.OPT_BLOCK, 256)
