@@ -969,6 +969,165 @@ __device__ __forceinline__ void tension_dot(R c, const R g[3], R gn2, const R w[
 template <class R> struct ForceBatch { static constexpr int U = SPHX_FORCE_BATCH; };
 template <> struct ForceBatch<double> { static constexpr int U = 2; };
 
+// Per-lane state of the force pass for particle i: its own quantities, the sums of
+// Eqs. (6), (8), (10)/(11), (17) over its neighbours, and the epilogue that turns them
+// into the rates.
+template <class R, int DIM> struct ForceLane {
+    uint32_t info, ph;
+    bool fluid, fli, massform;
+    R4<R> vi;
+    R mi, Ai, alpha, ci, gi2, vp0, vp1, delta2;
+    R gi[3];
+    R cont, ap[3], av[3], as[3];
+    uint32_t cnt;
+
+    template <class IC>
+    __device__ __forceinline__ void init(const IC& I, uint32_t info_, const R4<R>& vi_, const R4<R>& xi,
+                                         const R4<R>* __restrict__ gc, uint32_t i)
+    {
+        info = info_;
+        ph = info_phase(info);
+        fluid = info_kind(info) == K_FLUID;
+        vi = vi_;
+        mi = xi.x;
+        Ai = xi.y / mi;                          // P_i / rho_i^2
+        fli = xi.z != (R)0;
+        alpha = sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s;
+        gi[0] = gi[1] = gi[2] = 0;
+        ci = 0;
+        gi2 = 0;
+        if (fli) {
+            const R4<R> g4 = gc[i];
+            gi[0] = g4.x; gi[1] = g4.y; gi[2] = g4.z;
+            gi2 = g4.w * g4.w;
+            ci = alpha * (vi.w * vi.w) / g4.w;
+        }
+        // selects, not a dynamic index, keep the table in scalar registers
+        if constexpr (sizeof(R) == 8) {
+            vp0 = ph ? I.vpair[1][0] : I.vpair[0][0];
+            vp1 = ph ? I.vpair[1][1] : I.vpair[0][1];
+            delta2 = I.delta2;
+        } else {
+            vp0 = ph ? I.f_vpair[1][0] : I.f_vpair[0][0];
+            vp1 = ph ? I.f_vpair[1][1] : I.f_vpair[0][1];
+            delta2 = I.f_delta2;
+        }
+        massform = I.cont_form == 1;
+        cont = 0;
+        for (int q = 0; q < 3; ++q) ap[q] = av[q] = as[q] = 0;
+        cnt = 0;
+    }
+
+    // One neighbour j = k with r_ij, |r_ij|^2 < 4h^2, position record pj, velocity
+    // record vk = (u_j, V_j) and aux record xk = (m_j, m_j A_j, flag_j).
+    template <class IC>
+    __device__ __forceinline__ void pair(const IC& I, const R4<R>* __restrict__ gc, uint32_t k, const R* r,
+                                         R r2, const R4<R>& pj, const R4<R>& vk, const R4<R>& xk)
+    {
+        ++cnt;
+        const R F = kernel_f<R>(I, r2);
+        const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
+        const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
+        const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+        cont += (massform ? xk.x : vk.w) * udw;                   // Eq. (6) / (5)
+        if (!fluid) return;
+        const R pc = xk.x * Ai + xk.y;                            // m_j (A_i + A_j)
+        ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
+        const R lap = (F * r2) * frcp(r2 + delta2);               // r.gradW / (r^2 + delta^2)
+        const R cv = vk.w * (pos_phase(pj) ? vp1 : vp0) * lap;
+        av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
+        const bool flk = xk.z != (R)0;
+        if (fli || flk) {
+            R t[3];
+            if (fli) {
+                tension_dot<R, DIM>(ci, gi, gi2, w, t);
+                as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+            }
+            if (flk) {
+                const R4<R> g4 = gc[k];
+                const R gk[3] = {g4.x, g4.y, g4.z};
+                const R ck = fdiv(alpha * (vk.w * vk.w), g4.w);
+                tension_dot<R, DIM>(ck, gk, g4.w * g4.w, w, t);
+                as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+            }
+        }
+    }
+
+    // Combine the P lanes of the particle, then (on its first lane) store the rates
+    // (and the three terms when asked) and return |u_i|^2, |a_i|^2 for the time step.
+    template <int P, bool REDUCE, bool TERMS, class IC>
+    __device__ __forceinline__ void finish(const Dev& d, const IC& I, uint32_t i, uint32_t sub, R rho_stored,
+                                           double& umag2, double& amag2)
+    {
+        cont = group_sum<P>(cont);
+        for (int q = 0; q < 3; ++q) {
+            ap[q] = group_sum<P>(ap[q]);
+            av[q] = group_sum<P>(av[q]);
+            as[q] = group_sum<P>(as[q]);
+        }
+        const double rho_i = rho_of<R>(I, ph, rho_stored);
+        R4<R> out;
+        out.w = massform ? cont : (R)rho_i * cont;
+        R a[3] = {0, 0, 0};
+        if (fluid) {
+            const R vfac = I.visc_form == 1 ? (R)(1.0 / rho_i) : (R)1;
+            for (int q = 0; q < 3; ++q) {
+                av[q] *= vfac;
+                as[q] /= mi;
+                const R gq = sizeof(R) == 8 ? (R)I.g[q] : (R)I.f_g[q];
+                a[q] = ap[q] + av[q] + as[q] + gq;
+            }
+        }
+        out.x = a[0]; out.y = a[1]; out.z = a[2];
+        if (sub == 0) ((R4<R>*)d.acc)[i] = out;
+        if (TERMS && sub == 0) {
+            R4<R>* T = (R4<R>*)d.terms;
+            R4<R> t;
+            t.w = 0;
+            t.x = fluid ? ap[0] : 0; t.y = fluid ? ap[1] : 0; t.z = fluid ? ap[2] : 0;
+            T[3 * (size_t)i + 0] = t;
+            t.x = av[0]; t.y = av[1]; t.z = av[2];
+            T[3 * (size_t)i + 1] = t;
+            t.x = as[0]; t.y = as[1]; t.z = as[2];
+            T[3 * (size_t)i + 2] = t;
+        }
+        if (!isfinite((double)out.x) || !isfinite((double)out.y) || !isfinite((double)out.z) ||
+            !isfinite((double)out.w))
+            atomicOr(d.status, ST_NONFINITE);
+        if (REDUCE && sub == 0) {
+            if (info_kind(info) != K_WALL) {
+                const double ux = vi.x, uy = vi.y, uz = vi.z;
+                umag2 = ux * ux + uy * uy + uz * uz;
+            }
+            if (fluid) amag2 = (double)a[0] * a[0] + (double)a[1] * a[1] + (double)a[2] * a[2];
+        }
+    }
+};
+
+// Wave-level reductions at the end of a force pass: the interaction count always, the
+// |u|^2 and |a|^2 maxima (for the time step) when REDUCE.
+template <bool REDUCE>
+__device__ __forceinline__ void force_reduce(const Dev& d, bool valid, uint32_t inst, unsigned long long nint,
+                                             double umag2, double amag2)
+{
+    const unsigned long long wsum = wave_sum(nint);
+    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(d.inter, wsum);
+    if (REDUCE) {
+        const uint32_t inst0 = __shfl(inst, 0, 64);
+        const bool uniform = __all(!valid || inst == inst0);
+        if (uniform) {
+            const double um = wave_max(umag2), am = wave_max(amag2);
+            if ((threadIdx.x & 63) == 0) {
+                max_update(&d.run[inst0].umax2, um);
+                max_update(&d.run[inst0].amax2, am);
+            }
+        } else if (valid) {
+            max_update(&d.run[inst].umax2, umag2);
+            max_update(&d.run[inst].amax2, amag2);
+        }
+    }
+}
+
 template <class R, int DIM, int P, bool REDUCE, bool TERMS>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, int remap)
 {
@@ -989,135 +1148,22 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
         const uint32_t info = O.info[i];
         inst = info_inst(info);
         per_instance(d, inst, [&](const InstU& I) {
-            const uint32_t ph = info_phase(info);
-            const bool fluid = info_kind(info) == K_FLUID;
             const R4<R> pi = pos[i];
             Lane<R> L;
             L.load(I, pi, O.key[i]);
-            const R4<R> vi = vel[i];
-            const R4<R> xi = aux[i];                 // (m, m A, flag)
-            const R mi = xi.x;
-            const R Ai = xi.y / mi;                  // P_i / rho_i^2
-            const bool fli = xi.z != (R)0;
-            R gi[3] = {0, 0, 0}, ci = 0, gi2 = 0;
-            const R alpha = sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s;
-            if (fli) {
-                const R4<R> g4 = gc[i];
-                gi[0] = g4.x; gi[1] = g4.y; gi[2] = g4.z;
-                gi2 = g4.w * g4.w;
-                ci = alpha * (vi.w * vi.w) / g4.w;
-            }
-            R vp0, vp1, delta2;
-            // selects, not a dynamic index, keep the table in scalar registers
-            if constexpr (sizeof(R) == 8) {
-                vp0 = ph ? I.vpair[1][0] : I.vpair[0][0];
-                vp1 = ph ? I.vpair[1][1] : I.vpair[0][1];
-                delta2 = I.delta2;
-            } else {
-                vp0 = ph ? I.f_vpair[1][0] : I.f_vpair[0][0];
-                vp1 = ph ? I.f_vpair[1][1] : I.f_vpair[0][1];
-                delta2 = I.f_delta2;
-            }
-            const bool massform = I.cont_form == 1;
-            R cont = 0, ap[3] = {0, 0, 0}, av[3] = {0, 0, 0}, as[3] = {0, 0, 0};
-            uint32_t cnt = 0;
+            ForceLane<R, DIM> F;
+            F.init(I, info, vel[i], aux[i], gc, i);
             struct VA { R4<R> v, a; };
             for_each_neighbor<R, DIM, ForceBatch<R>::U, P>(d, I, pos, i, L, sub,
                 [&](uint32_t k) { return VA{vel[k], aux[k]}; },
                 [&](uint32_t k, const R* r, R r2, const R4<R>& pj, const VA& x) {
-                    ++cnt;
-                    const R F = kernel_f<R>(I, r2);
-                    const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
-                    const R4<R>& vk = x.v;
-                    const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
-                    const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
-                    const R4<R>& xk = x.a;
-                    cont += (massform ? xk.x : vk.w) * udw;                   // Eq. (6) / (5)
-                    if (!fluid) return;
-                    const R pc = xk.x * Ai + xk.y;                            // m_j (A_i + A_j)
-                    ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
-                    const R lap = (F * r2) * frcp(r2 + delta2);               // r.gradW / (r^2 + delta^2)
-                    const R cv = vk.w * (pos_phase(pj) ? vp1 : vp0) * lap;
-                    av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
-                    const bool flk = xk.z != (R)0;
-                    if (fli || flk) {
-                        R t[3];
-                        if (fli) {
-                            tension_dot<R, DIM>(ci, gi, gi2, w, t);
-                            as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
-                        }
-                        if (flk) {
-                            const R4<R> g4 = gc[k];
-                            const R gk[3] = {g4.x, g4.y, g4.z};
-                            const R ck = fdiv(alpha * (vk.w * vk.w), g4.w);
-                            tension_dot<R, DIM>(ck, gk, g4.w * g4.w, w, t);
-                            as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
-                        }
-                    }
+                    F.pair(I, gc, k, r, r2, pj, x.v, x.a);
                 });
-            nint = cnt;
-            cont = group_sum<P>(cont);
-            for (int q = 0; q < 3; ++q) {
-                ap[q] = group_sum<P>(ap[q]);
-                av[q] = group_sum<P>(av[q]);
-                as[q] = group_sum<P>(as[q]);
-            }
-            const double rho_i = rho_of<R>(I, ph, ((const R*)S.rho)[i]);
-            R4<R> out;
-            out.w = massform ? cont : (R)rho_i * cont;
-            R a[3] = {0, 0, 0};
-            if (fluid) {
-                const R vfac = I.visc_form == 1 ? (R)(1.0 / rho_i) : (R)1;
-                for (int q = 0; q < 3; ++q) {
-                    av[q] *= vfac;
-                    as[q] /= mi;
-                    const R gq = sizeof(R) == 8 ? (R)I.g[q] : (R)I.f_g[q];
-                    a[q] = ap[q] + av[q] + as[q] + gq;
-                }
-            }
-            out.x = a[0]; out.y = a[1]; out.z = a[2];
-            if (sub == 0) ((R4<R>*)d.acc)[i] = out;
-            if (TERMS && sub == 0) {
-                R4<R>* T = (R4<R>*)d.terms;
-                R4<R> t;
-                t.w = 0;
-                t.x = fluid ? ap[0] : 0; t.y = fluid ? ap[1] : 0; t.z = fluid ? ap[2] : 0;
-                T[3 * (size_t)i + 0] = t;
-                t.x = av[0]; t.y = av[1]; t.z = av[2];
-                T[3 * (size_t)i + 1] = t;
-                t.x = as[0]; t.y = as[1]; t.z = as[2];
-                T[3 * (size_t)i + 2] = t;
-            }
-            if (!isfinite((double)out.x) || !isfinite((double)out.y) || !isfinite((double)out.z) ||
-                !isfinite((double)out.w))
-                atomicOr(d.status, ST_NONFINITE);
-            if (REDUCE && sub == 0) {
-                const uint32_t kind = info_kind(info);
-                if (kind != K_WALL) {
-                    const double ux = vi.x, uy = vi.y, uz = vi.z;
-                    umag2 = ux * ux + uy * uy + uz * uz;
-                }
-                if (fluid) amag2 = (double)a[0] * a[0] + (double)a[1] * a[1] + (double)a[2] * a[2];
-            }
+            nint = F.cnt;
+            F.template finish<P, REDUCE, TERMS>(d, I, i, sub, ((const R*)S.rho)[i], umag2, amag2);
         });
     }
-    // wave-level reductions: interaction count always, |u|^2 and |a|^2 maxima at S^n
-    const unsigned long long wsum = wave_sum(nint);
-    if ((threadIdx.x & 63) == 0 && wsum) atomicAdd(d.inter, wsum);
-    if (REDUCE) {
-        const uint32_t inst0 = __shfl(inst, 0, 64);
-        const bool uniform = __all(!valid || inst == inst0);
-        if (uniform) {
-            const double um = wave_max(umag2), am = wave_max(amag2);
-            if ((threadIdx.x & 63) == 0) {
-                max_update(&d.run[inst0].umax2, um);
-                max_update(&d.run[inst0].amax2, am);
-            }
-        } else if (valid) {
-            max_update(&d.run[inst].umax2, umag2);
-            max_update(&d.run[inst].amax2, amag2);
-        }
-    }
+    force_reduce<REDUCE>(d, valid, inst, nint, umag2, amag2);
 }
 
 // ----------------------------------------------------------- time step (a9)
@@ -1423,8 +1469,8 @@ void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s)
 
 void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hipStream_t s)
 {
-    const dim3 grid(blocks_for(d.n * L.force_lanes, L.block)), block(L.block);
     const int st = star ? 1 : 0;
+    const dim3 grid(blocks_for(d.n * L.force_lanes, L.block)), block(L.block);
     SPHX_DISPATCH(d.precision, d.dim, SPHX_LANES(L.force_lanes, ({
         if (L.debug_terms) {
             if (reduce_max) hipLaunchKernelGGL((k_force<R, D, P, true, true>), grid, block, 0, s, d, st, L.xcd_remap);
