@@ -107,7 +107,7 @@ struct Dev {
 };
 
 struct Launch {
-    int block = 256;
+    int block = 64;      // threads per block of the neighbour passes (autotuned on the 3D drop)
     int xcd_remap = 1;
     int lanes = 4;       // lanes per particle in the renormalisation and colour passes (1, 2, 4)
     int force_lanes = 1; // lanes per particle in the force pass (1, 2, 4)

@@ -2,19 +2,22 @@
 
 Times short graph-replayed runs of a scene over a grid of options and keeps the
 fastest.  The options:
-  block      threads per block of the neighbour passes (64, 128, 256);
-  xcd_remap  consecutive tiles on one XCD, or the default round-robin;
-  skin       neighbour skin in units of h, which sets the cell size (2 + skin) h and
-             the list radius (2 + skin/2) h; larger cells mean more candidates per
-             list build, a larger skin means longer lists.
+  block        threads per block of the neighbour passes (64, 128, 256);
+  xcd_remap    consecutive tiles on one XCD, or the default round-robin;
+  lanes        lanes per particle in the renormalisation and colour passes (1, 2, 4);
+  force_lanes  lanes per particle in the force pass (1, 2, 4);
+  skin         neighbour skin in units of h, which sets the cell size and list radius
+               (2 + skin) h; a larger skin means longer lists, a smaller one more
+               frequent rebuilds (a particle may move skin h / 4 between them).
 The skin changes which extra pairs sit in the lists (they are filtered out), not
-the physics, except through the time-step limit dt <= skin h / (2 max|u|).
+the physics, except through the time-step limit dt <= skin h / (2 max|u|).  The grid
+is searched one option at a time (coordinate descent from the defaults), not as a
+full product.
 Results are cached per (GPU arch, dimension, precision, particle-count bucket) in
 a JSON file beside this module.
 """
 from __future__ import annotations
 
-import itertools
 import json
 import math
 import os
@@ -25,7 +28,9 @@ from . import binding
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 BLOCKS = (64, 128, 256)
 REMAPS = (0, 1)
+LANES = (1, 2, 4)
 SKINS = (0.05, 0.1, 0.2)
+DEFAULTS = {"skin": 0.1, "block": 64, "xcd_remap": 1, "lanes": 4, "force_lanes": None}
 
 
 def cache_key(scene, precision, arch="gfx950"):
@@ -40,11 +45,14 @@ def load_cache() -> dict:
     return {}
 
 
-def _time(scene, precision, block, remap, steps, warmup):
-    sim = binding.Sim(scene, precision=precision)
+def _time(scene, precision, opts, steps, warmup):
+    sim = binding.Sim(scene.with_params(skin_coef=opts["skin"]), precision=precision)
     try:
-        sim.set_option(binding.OPT_BLOCK, block)
-        sim.set_option(binding.OPT_XCD_REMAP, remap)
+        sim.set_option(binding.OPT_BLOCK, opts["block"])
+        sim.set_option(binding.OPT_XCD_REMAP, opts["xcd_remap"])
+        sim.set_option(binding.OPT_LANES, opts["lanes"])
+        if opts["force_lanes"] is not None:
+            sim.set_option(binding.OPT_FORCE_LANES, opts["force_lanes"])
         sim.step(warmup)
         sim.sync()
         t0 = time.perf_counter()
@@ -56,17 +64,26 @@ def _time(scene, precision, block, remap, steps, warmup):
 
 
 def tune(scene, precision=binding.FP32_CELLREL, steps=20, warmup=3, skins=SKINS,
-         blocks=BLOCKS, remaps=REMAPS, save=True, log=print) -> dict:
-    """Time every option combination and return (and cache) the fastest."""
+         blocks=BLOCKS, remaps=REMAPS, lanes=LANES, save=True, log=print) -> dict:
+    """Coordinate descent over the options; returns (and caches) the fastest set."""
+    grid = {"skin": skins, "block": blocks, "xcd_remap": remaps, "lanes": lanes, "force_lanes": lanes}
+    best = dict(DEFAULTS)
+    best["force_lanes"] = 1 if precision == binding.FP32_CELLREL else 2
     results = []
-    for skin in skins:
-        sc = scene.with_params(skin_coef=skin)
-        for block, remap in itertools.product(blocks, remaps):
-            ms = 1e3 * _time(sc, precision, block, remap, steps, warmup)
-            results.append(dict(skin=skin, block=block, xcd_remap=remap, ms_per_step=ms))
+    best_ms = 1e3 * _time(scene, precision, best, steps, warmup)
+    results.append(dict(best, ms_per_step=best_ms))
+    for key, values in grid.items():
+        for v in values:
+            if v == best[key]:
+                continue
+            trial = dict(best, **{key: v})
+            ms = 1e3 * _time(scene, precision, trial, steps, warmup)
+            results.append(dict(trial, ms_per_step=ms))
             if log:
-                log(f"tune skin={skin} block={block} remap={remap}: {ms:.4f} ms/step")
-    best = min(results, key=lambda r: r["ms_per_step"])
+                log(f"tune {trial}: {ms:.4f} ms/step")
+            if ms < best_ms:
+                best, best_ms = trial, ms
+    best = dict(best, ms_per_step=best_ms)
     if save:
         cache = load_cache()
         cache[cache_key(scene, precision)] = dict(best=best, all=results)
@@ -86,3 +103,6 @@ def apply(sim, best):
     if best:
         sim.set_option(binding.OPT_BLOCK, int(best["block"]))
         sim.set_option(binding.OPT_XCD_REMAP, int(best["xcd_remap"]))
+        sim.set_option(binding.OPT_LANES, int(best["lanes"]))
+        if best.get("force_lanes") is not None:
+            sim.set_option(binding.OPT_FORCE_LANES, int(best["force_lanes"]))

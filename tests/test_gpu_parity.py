@@ -406,7 +406,7 @@ def test_still_tank_rebuilds_rarely():
     assert sim.stats()["builds"] - b0 <= 4
 
 
-@pytest.mark.parametrize("block", [64, 128, 192])
+@pytest.mark.parametrize("block", [128, 192, 256])
 def test_rates_with_other_block_sizes(block, oracle_rates):
     s, ref, _ = oracle_rates("drop3d_small")
     print(f"case rates block={block}", flush=True)
@@ -426,3 +426,16 @@ def test_blocks_above_256_are_rejected():
     with pytest.raises(binding.SphxError, match="block"):
         sim.set_option(binding.OPT_BLOCK, 512)
     sim.set_option(binding.OPT_BLOCK, 256)
+
+
+def test_tuner_returns_a_working_option_set():
+    from paper_1702_07760_amd import tune
+    s = inputs.drop2d(perturb=True)
+    best = tune.tune(s, steps=2, warmup=1, skins=(0.1,), blocks=(128, 256), remaps=(1,), lanes=(1, 4),
+                     save=False, log=None)
+    assert best["ms_per_step"] > 0
+    assert best["lanes"] in (1, 4) and best["force_lanes"] in (1, 4) and best["block"] in (128, 256)
+    sim = binding.Sim(s.with_params(skin_coef=best["skin"]), precision=binding.FP32_CELLREL)
+    tune.apply(sim, best)
+    sim.step(2)
+    sim.sync()
