@@ -258,7 +258,6 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
         d.S[s].pos = c.take<char>(un * 4 * R);
         d.S[s].vel = c.take<char>(un * 4 * R);
         d.S[s].aux = c.take<char>(un * 4 * R);
-        d.S[s].rho = c.take<char>(un * R);
         d.S[s].plo = precision ? c.take<float4>(un) : nullptr;
         d.S[s].vlo = precision ? c.take<float4>(un) : nullptr;
         d.O[s].key = c.take<uint32_t>(un);
@@ -269,7 +268,6 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.star.pos = c.take<char>(un * 4 * R);
     d.star.vel = c.take<char>(un * 4 * R);
     d.star.aux = c.take<char>(un * 4 * R);
-    d.star.rho = c.take<char>(un * R);
     d.star.plo = nullptr;
     d.star.vlo = nullptr;
     d.rho_tmp = c.take<char>(un * R);
@@ -424,7 +422,7 @@ struct BlobHeader {
     int64_t n;
     uint32_t ncell, rates_valid, cap, pad;
 };
-constexpr uint64_t kMagic = 0x5350485853543032ull;   // "SPHXST02"
+constexpr uint64_t kMagic = 0x5350485853543033ull;   // "SPHXST03"
 
 struct Span { void* p; size_t bytes; };
 
@@ -436,7 +434,7 @@ std::vector<Span> state_spans(sphx_ctx* c, int s)
     const size_t n = (size_t)c->n, R = c->precision ? 4 : 8;
     Dev& d = c->dev;
     std::vector<Span> v = {
-        {d.S[s].pos, n * 4 * R}, {d.S[s].vel, n * 4 * R}, {d.S[s].aux, n * 4 * R}, {d.S[s].rho, n * R},
+        {d.S[s].pos, n * 4 * R}, {d.S[s].vel, n * 4 * R}, {d.S[s].aux, n * 4 * R},
         {d.O[s].key, n * 4}, {d.O[s].id, n * 4}, {d.O[s].info, n * 4}, {d.cstart, ((size_t)c->ncell + 1) * 4},
         {d.run, sizeof(InstRun) * c->ninst}, {d.acc, n * 4 * R}, {d.gc, n * 4 * R},
         {d.nbl, n * d.cap * 4}, {d.nbc, n * 4}, {d.nbx, n}, {d.xb, n * 4 * R}};
@@ -595,7 +593,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     c->has_moving = moving;
     drop_graphs(c);
 
-    std::vector<char> pos(n * 4 * R), vel(n * 4 * R), aux(n * 4 * R), rh(n * R);
+    std::vector<char> pos(n * 4 * R), vel(n * 4 * R), aux(n * 4 * R);
     std::vector<float4> plo(f32 ? n : 0), vlo(f32 ? n : 0);
     std::vector<uint32_t> key(n), id(n), info(n);
     std::vector<double4> ref(n);
@@ -617,8 +615,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
             if (!f32) {
                 ((double4*)pos.data())[i] = make_double4(xi[0], xi[1], xi[2], (double)phase[i]);
                 ((double4*)vel.data())[i] = make_double4(u[3 * i], c->dim > 1 ? u[3 * i + 1] : 0.0, c->dim > 2 ? u[3 * i + 2] : 0.0, 0.0);
-                ((double4*)aux.data())[i] = make_double4(m[i], 0.0, 0.0, 0.0);
-                ((double*)rh.data())[i] = rho[i];
+                ((double4*)aux.data())[i] = make_double4(m[i], 0.0, 0.0, rho[i]);   // V, m P / rho^2: derived
             } else {
                 float o[3], e[3], uu[3], ue[3];
                 for (int d = 0; d < 3; ++d) {
@@ -638,8 +635,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
                 plo[i] = make_float4(e[0], e[1], e[2], (float)(dr - (double)drf));
                 ((float4*)vel.data())[i] = make_float4(uu[0], uu[1], uu[2], 0.0f);
                 vlo[i] = make_float4(ue[0], ue[1], ue[2], 0.0f);
-                ((float4*)aux.data())[i] = make_float4((float)m[i], 0.0f, 0.0f, 0.0f);
-                ((float*)rh.data())[i] = drf;
+                ((float4*)aux.data())[i] = make_float4((float)m[i], 0.0f, 0.0f, drf);
             }
         }
     }
@@ -658,7 +654,6 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemcpyAsync(d.S[0].pos, pos.data(), pos.size(), hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(d.S[0].vel, vel.data(), vel.size(), hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(d.S[0].aux, aux.data(), aux.size(), hipMemcpyHostToDevice, s));
-    HIP_OK(c, hipMemcpyAsync(d.S[0].rho, rh.data(), rh.size(), hipMemcpyHostToDevice, s));
     if (f32) {
         HIP_OK(c, hipMemcpyAsync(d.S[0].plo, plo.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
         HIP_OK(c, hipMemcpyAsync(d.S[0].vlo, vlo.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
@@ -855,13 +850,6 @@ sphx_status sphx_get_field(sphx_ctx* c, int32_t field, double* out)
         for (int64_t k = 0; k < 4 * n; ++k) v[k] = f32 ? (double)((float*)raw.data())[k] : ((double*)raw.data())[k];
         return SPHX_OK;
     };
-    auto fetch1 = [&](const void* src, std::vector<double>& v) -> sphx_status {
-        std::vector<char> raw(n * R);
-        HIP_OK(c, hipMemcpy(raw.data(), src, raw.size(), hipMemcpyDeviceToHost));
-        v.resize(n);
-        for (int64_t k = 0; k < n; ++k) v[k] = f32 ? (double)((float*)raw.data())[k] : ((double*)raw.data())[k];
-        return SPHX_OK;
-    };
     std::vector<float4> lo;
     auto rho_of = [&](const std::vector<double>& r, int64_t k) {
         if (!f32) return r[k];
@@ -912,7 +900,8 @@ sphx_status sphx_get_field(sphx_ctx* c, int32_t field, double* out)
     }
     case SPHX_F_RHO:
     case SPHX_F_P: {
-        if ((e = fetch1(S.rho, a))) return e;
+        if ((e = fetch4(S.aux, a))) return e;   // density in aux.w
+        for (int64_t k = 0; k < n; ++k) a[k] = a[4 * k + 3];
         if (f32) {
             lo.resize(n);
             HIP_OK(c, hipMemcpy(lo.data(), S.plo, n * sizeof(float4), hipMemcpyDeviceToHost));

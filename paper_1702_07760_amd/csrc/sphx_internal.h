@@ -54,10 +54,10 @@ struct InstRun {
 
 // One copy of the cell-sorted particle state.
 struct StateSet {
-    void* pos;   // R4: FP64 (x, y, z, 0); FP32 (ox, oy, oz, bits(cell key))
+    void* pos;   // R4: FP64 (x, y, z, phase); FP32 (ox, oy, oz, bits(cell key | phase << 31))
     void* vel;   // R4: (ux, uy, uz, V = m / rho)
-    void* aux;   // R4: (m, m P / rho^2, interface flag, 0)
-    void* rho;   // FP64: rho; FP32: rho - rho0
+    void* aux;   // R4: (m, m P / rho^2, +-V, rho); the sign of z is the interface flag,
+                 //     w is rho in FP64 and rho - rho0 in FP32
     float4* plo; // FP32 only: compensation of (ox, oy, oz, rho - rho0)
     float4* vlo; // FP32 only: compensation of (ux, uy, uz)
 };

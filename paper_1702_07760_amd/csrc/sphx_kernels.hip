@@ -685,7 +685,6 @@ __global__ void k_gather(Dev d, int with_ref)
     ((R4<R>*)SB.pos)[k] = p;
     ((R4<R>*)SB.vel)[k] = ((const R4<R>*)SA.vel)[src];
     ((R4<R>*)SB.aux)[k] = ((const R4<R>*)SA.aux)[src];
-    ((R*)SB.rho)[k] = ((const R*)SA.rho)[src];
     if constexpr (sizeof(R) == 4) {
         SB.plo[k] = SA.plo[src];
         SB.vlo[k] = SA.vlo[src];
@@ -769,7 +768,9 @@ __device__ __forceinline__ double rho_of(const IC& I, uint32_t phase, R stored)
     else return (phase ? I.rho0[1] : I.rho0[0]) + (double)stored;   // no dynamic index: I may live in SGPRs
 }
 
-// Derived quantities of one particle: V = m / rho into vel.w, m P / rho^2 into aux.y.
+// Derived quantities of one particle from its stored density: V = m / rho into vel.w
+// and aux.z (the copy read by the renormalisation, positive: interface flag cleared),
+// m P / rho^2 into aux.y, the density itself into aux.w.
 template <class R>
 __device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R stored, R4<R>& vel, R4<R>& aux)
 {
@@ -777,8 +778,11 @@ __device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R s
     const double y = sizeof(R) == 8 ? rho / I.rho0[phase] : 1.0 + (double)stored / I.rho0[phase];
     const double P = tait(y, I.beta[phase]);
     const double m = (double)aux.x;
-    vel.w = (R)(m / rho);
+    const R V = (R)(m / rho);
+    vel.w = V;
     aux.y = (R)(m * (P / (rho * rho)));
+    aux.z = V;
+    aux.w = stored;
 }
 
 // After Eq. (7): move the renormalised density into the state and re-derive.
@@ -799,13 +803,13 @@ __global__ void k_derive(Dev d, int from_tmp, int force)
     const uint32_t info = d.O[cur].info[k];
     const InstDev& I = d.inst[info_inst(info)];
     const StateSet& S = d.S[cur];
-    R r = from_tmp ? ((const R*)d.rho_tmp)[k] : ((const R*)S.rho)[k];
-    if (from_tmp) {
-        ((R*)S.rho)[k] = r;
-        if constexpr (sizeof(R) == 4) S.plo[k].w = 0.0f;   // a fresh value: no carried error
-    }
     R4<R> vel = ((R4<R>*)S.vel)[k];
     R4<R> aux = ((R4<R>*)S.aux)[k];
+    R r = aux.w;
+    if (from_tmp) {
+        r = ((const R*)d.rho_tmp)[k];
+        if constexpr (sizeof(R) == 4) S.plo[k].w = 0.0f;   // a fresh value: no carried error
+    }
     derive_one<R>(I, info_phase(info), r, vel, aux);
     ((R4<R>*)S.vel)[k] = vel;
     ((R4<R>*)S.aux)[k] = aux;
@@ -860,7 +864,6 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
     const R4<R>* pos = (const R4<R>*)S.pos;
     const R4<R>* vel = (const R4<R>*)S.vel;
     const R4<R>* aux = (const R4<R>*)S.aux;
-    const R* rho = (const R*)S.rho;
     const R4<R> pi = pos[i];
     const uint32_t ph = pos_phase(pi);
     per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
@@ -874,8 +877,9 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
             // Eq. (7) as written: sum m_j W_ij / sum (m_j / rho_j) W_ij, self included
             num = aux[i].x * w0;
             den = vel[i].w * w0;
+            // m_j and V_j (|aux.z|: its sign is the interface flag) from one record
             for_each_neighbor<R, DIM, 2, P>(d, I, pos, i, L, sub,
-                [&](uint32_t k) { return Pair{aux[k].x, vel[k].w}; },
+                [&](uint32_t k) { return Pair{aux[k].x, fabs(aux[k].z)}; },
                 [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
                     if (pos_phase(pj) != ph) return;
                     const R w = kernel_w<R>(I, r2);
@@ -885,10 +889,14 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
         } else {
             // the same quotient minus rho0, as a V_j W_ij-weighted mean of (rho_j - rho0):
             // m_j - rho0 V_j = V_j (rho_j - rho0), so nothing cancels in FP32
-            num = vel[i].w * w0 * rho[i];
+            num = vel[i].w * w0 * aux[i].w;
             den = vel[i].w * w0;
+            // (V_j, rho_j - rho0) as one 8-byte load of aux.zw (|aux.z| = V_j)
             for_each_neighbor<R, DIM, 4, P>(d, I, pos, i, L, sub,
-                [&](uint32_t k) { return Pair{vel[k].w, rho[k]}; },
+                [&](uint32_t k) {
+                    const float2 zw = *(const float2*)&aux[k].z;
+                    return Pair{fabsf(zw.x), zw.y};
+                },
                 [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
                     if (pos_phase(pj) != ph) return;
                     const R vw = x.a * kernel_w<R>(I, r2);
@@ -946,7 +954,8 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star, 
         R4<R> out;
         out.x = g[0]; out.y = g[1]; out.z = g[2]; out.w = gn;
         gc[i] = out;
-        aux[i].z = gn > 0 ? (R)1 : (R)0;
+        const R v = fabs(aux[i].z);
+        aux[i].z = gn > 0 ? -v : v;       // interface flag: the sign of the V copy
     }
 }
 
@@ -991,7 +1000,7 @@ template <class R, int DIM> struct ForceLane {
         vi = vi_;
         mi = xi.x;
         Ai = xi.y / mi;                          // P_i / rho_i^2
-        fli = xi.z != (R)0;
+        fli = xi.z < (R)0;                       // interface flag (sign of the V copy)
         alpha = sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s;
         gi[0] = gi[1] = gi[2] = 0;
         ci = 0;
@@ -1019,7 +1028,8 @@ template <class R, int DIM> struct ForceLane {
     }
 
     // One neighbour j = k with r_ij, |r_ij|^2 < 4h^2, position record pj, velocity
-    // record vk = (u_j, V_j) and aux record xk = (m_j, m_j A_j, flag_j).
+    // record vk = (u_j, V_j) and aux record xk = (m_j, m_j A_j, +-V_j, rho_j); the sign
+    // of xk.z is j's interface flag.
     template <class IC>
     __device__ __forceinline__ void pair(const IC& I, const R4<R>* __restrict__ gc, uint32_t k, const R* r,
                                          R r2, const R4<R>& pj, const R4<R>& vk, const R4<R>& xk)
@@ -1036,7 +1046,7 @@ template <class R, int DIM> struct ForceLane {
         const R lap = (F * r2) * frcp(r2 + delta2);               // r.gradW / (r^2 + delta^2)
         const R cv = vk.w * (pos_phase(pj) ? vp1 : vp0) * lap;
         av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
-        const bool flk = xk.z != (R)0;
+        const bool flk = xk.z < (R)0;
         if (fli || flk) {
             R t[3];
             if (fli) {
@@ -1160,7 +1170,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
                     F.pair(I, gc, k, r, r2, pj, x.v, x.a);
                 });
             nint = F.cnt;
-            F.template finish<P, REDUCE, TERMS>(d, I, i, sub, ((const R*)S.rho)[i], umag2, amag2);
+            F.template finish<P, REDUCE, TERMS>(d, I, i, sub, aux[i].w, umag2, amag2);
         });
     }
     force_reduce<REDUCE>(d, valid, inst, nint, umag2, amag2);
@@ -1272,12 +1282,11 @@ __global__ void k_predict(Dev d)
     } else if (kind == K_MOVING) {
         moving_state<R>(I, O.ref[k], O.key[k], d.run[b].t + hdt, p, v);
     }
-    R r = ((const R*)S.rho)[k] + h * a.w;
+    const R r = x.w + h * a.w;
     derive_one<R>(I, info_phase(info), r, v, x);
     ((R4<R>*)d.star.pos)[k] = p;
     ((R4<R>*)d.star.vel)[k] = v;
     ((R4<R>*)d.star.aux)[k] = x;
-    ((R*)d.star.rho)[k] = r;
 }
 
 // S^{n+1} = S^n + dt R(S*), in place
@@ -1298,7 +1307,7 @@ __device__ __forceinline__ double correct_one(const Dev& d, int cur, uint32_t k,
     R4<R> x = ((const R4<R>*)S.aux)[k];
     const R4<R> us = ((const R4<R>*)d.star.vel)[k];
     const R4<R> a = ((const R4<R>*)d.acc)[k];
-    R r = ((const R*)S.rho)[k];
+    R r = x.w;
     bool bad = false;
     if constexpr (sizeof(R) == 8) {
         if (kind == K_FLUID) {
@@ -1335,7 +1344,6 @@ __device__ __forceinline__ double correct_one(const Dev& d, int cur, uint32_t k,
     ((R4<R>*)S.pos)[k] = p;
     ((R4<R>*)S.vel)[k] = v;
     ((R4<R>*)S.aux)[k] = x;
-    ((R*)S.rho)[k] = r;
     const R4<R> xb = ((const R4<R>*)d.xb)[k];
     const double ex = (double)p.x - (double)xb.x, ey = (double)p.y - (double)xb.y;
     const double ez = DIM == 3 ? (double)p.z - (double)xb.z : 0.0;

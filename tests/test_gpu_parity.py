@@ -434,7 +434,8 @@ def test_tuner_returns_a_working_option_set():
     best = tune.tune(s, steps=2, warmup=1, skins=(0.1,), blocks=(128, 256), remaps=(1,), lanes=(1, 4),
                      save=False, log=None)
     assert best["ms_per_step"] > 0
-    assert best["lanes"] in (1, 4) and best["force_lanes"] in (1, 4) and best["block"] in (128, 256)
+    # the search starts from the defaults (block 64, 4 lanes, 1 force lane in FP32)
+    assert best["lanes"] in (1, 4) and best["force_lanes"] in (1, 4) and best["block"] in (64, 128, 256)
     sim = binding.Sim(s.with_params(skin_coef=best["skin"]), precision=binding.FP32_CELLREL)
     tune.apply(sim, best)
     sim.step(2)
