@@ -99,8 +99,9 @@ enum {
     SPHX_OPT_XCD_REMAP = 3,   /* 1: map consecutive particle tiles to one XCD (default 1) */
     SPHX_OPT_GRAPH = 4,       /* 1: sphx_step replays a captured hipGraph per step (default 1) */
     SPHX_OPT_LANES = 5,       /* lanes that share one particle's neighbour loop in the renormalisation
-                                 and colour passes: 1, 2 or 4 (default 4); each lane takes every
-                                 lanes-th neighbour and the partial sums are combined in-wave */
+                                 pass: 1, 2 or 4 (default 4); each lane takes every lanes-th
+                                 neighbour and the partial sums are combined in-wave (the colour
+                                 pass always runs 8 lanes per particle) */
     SPHX_OPT_FORCE_LANES = 7, /* the same for the force pass (default: 1 in FP32, 2 in FP64) */
     SPHX_OPT_PROFILE = 6      /* 1: no graphs; every kernel group is bracketed by HIP events on the
                                  context stream and its time is reported in sphx_stats */

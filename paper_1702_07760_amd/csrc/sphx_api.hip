@@ -247,7 +247,8 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.cap = list_cap(dim);
     d.nbl = c.take<uint32_t>(un * d.cap);
     d.nbc = c.take<uint32_t>(un);
-    d.nbx = c.take<uint8_t>(un);
+    d.ilist = c.take<uint32_t>(un);
+    d.icount = c.take<uint32_t>(1);
     d.xb = c.take<char>(un * 4 * R);
     d.newkey = c.take<uint32_t>(un);
     d.slot = c.take<uint32_t>(un);
@@ -437,7 +438,7 @@ std::vector<Span> state_spans(sphx_ctx* c, int s)
         {d.S[s].pos, n * 4 * R}, {d.S[s].vel, n * 4 * R}, {d.S[s].aux, n * 4 * R},
         {d.O[s].key, n * 4}, {d.O[s].id, n * 4}, {d.O[s].info, n * 4}, {d.cstart, ((size_t)c->ncell + 1) * 4},
         {d.run, sizeof(InstRun) * c->ninst}, {d.acc, n * 4 * R}, {d.gc, n * 4 * R},
-        {d.nbl, n * d.cap * 4}, {d.nbc, n * 4}, {d.nbx, n}, {d.xb, n * 4 * R}};
+        {d.nbl, n * d.cap * 4}, {d.nbc, n * 4}, {d.ilist, n * 4}, {d.icount, 4}, {d.xb, n * 4 * R}};
     if (c->precision) {
         v.push_back({d.S[s].plo, n * 16});
         v.push_back({d.S[s].vlo, n * 16});
@@ -647,6 +648,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemcpyAsync(d.run, run.data(), sizeof(InstRun) * c->ninst, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemsetAsync(d.status, 0, sizeof(uint32_t), s));
     HIP_OK(c, hipMemsetAsync(d.inter, 0, sizeof(unsigned long long), s));
+    HIP_OK(c, hipMemsetAsync(d.icount, 0, sizeof(uint32_t), s));
     HIP_OK(c, hipMemsetAsync(d.cnt, 0, sizeof(uint32_t) * c->ncell, s));
     HIP_OK(c, hipMemsetAsync(d.acc, 0, n * 4 * R, s));
     HIP_OK(c, hipMemsetAsync(d.gc, 0, n * 4 * R, s));

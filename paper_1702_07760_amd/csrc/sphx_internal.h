@@ -93,7 +93,8 @@ struct Dev {
     // neighbour list of the current sort order, column-major: entry q of i at q * n + i
     uint32_t* nbl;       // n * cap entries (index | cell-offset code << 26)
     uint32_t* nbc;       // n counts (> cap: overflowed, the passes walk the stencil)
-    uint8_t* nbx;        // n: an other-phase particle is in the list
+    uint32_t* ilist;     // colour-pass particles (another phase in the list), in build order
+    uint32_t* icount;    // their number
     uint32_t cap;
     void* xb;            // R4: positions at the last build (FP32: cell offsets)
     // state
@@ -109,7 +110,7 @@ struct Dev {
 struct Launch {
     int block = 64;      // threads per block of the neighbour passes (autotuned on the 3D drop)
     int xcd_remap = 1;
-    int lanes = 4;       // lanes per particle in the renormalisation and colour passes (1, 2, 4)
+    int lanes = 4;       // lanes per particle in the renormalisation pass (1, 2, 4)
     int force_lanes = 1; // lanes per particle in the force pass (1, 2, 4)
     bool debug_terms = false;
 };

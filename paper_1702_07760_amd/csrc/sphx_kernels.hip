@@ -388,7 +388,7 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
     using X = decltype(load(0u));
     const uint32_t n = (uint32_t)d.n;
     const char* __restrict__ base = (const char*)d.nbl;
-    const uint32_t lane_off = (sub * n + i) * 4u;   // < 2^30: n < 2^26, sub < 4
+    const uint32_t lane_off = (sub * n + i) * 4u;   // < 2^31: n < 2^26, sub < 8
     const size_t step = (size_t)P * n * 4u;
     const R cut2 = cut2_of<R>(I);
     for (uint32_t t0 = 0; t0 * P + sub < cnt; t0 += U) {
@@ -437,13 +437,15 @@ __device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, con
     }
 }
 
-// Sum over the P consecutive lanes that share one particle (P = 1, 2 or 4; the
+// Sum over the P consecutive lanes that share one particle (P = 1, 2, 4 or 8; the
 // lanes of a group are all active or all inactive).
 template <int P, class T>
 __device__ __forceinline__ T group_sum(T v)
 {
+    static_assert(P == 1 || P == 2 || P == 4 || P == 8, "lanes per particle");
     if (P >= 2) v += __shfl_xor(v, 1, 64);
     if (P >= 4) v += __shfl_xor(v, 2, 64);
+    if (P >= 8) v += __shfl_xor(v, 4, 64);
     return v;
 }
 
@@ -720,13 +722,16 @@ __global__ void k_decide(Dev d)
     if (threadIdx.x == 0) {
         d.flags[0] = (uint32_t)rebuild;
         d.flags[1] = 0u;
+        if (rebuild) *d.icount = 0u;   // the list build appends the colour-pass particles
     }
 }
 
-// Neighbour list at the positions of S[cur]: every j within the list radius
-// (2h plus half the skin, with a rounding margin), so that the same list holds every
-// pair within 2h at the predicted positions of the step as well.  Also flags
-// particles with an other-phase particle in their list (interface candidates).
+// Neighbour list at the current positions: every j within the cell size (2 + skin) h
+// (with a rounding margin).  Together with the rebuild rule this holds every pair within
+// 2h at any state evaluated before the next rebuild.  Particles with an other-phase
+// particle in their list (the only ones whose colour gradient can be non-zero) are
+// appended to the colour-pass index list; every other particle gets a zero gradient
+// and a cleared interface flag here, once per build.
 template <class R, int DIM>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
 {
@@ -754,7 +759,21 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
                                   other |= pos_phase(pj) != ph;
                               });
         d.nbc[i] = cnt;
-        d.nbx[i] = other ? 1 : 0;
+        const unsigned long long m = __ballot(other);
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(d.icount, (uint32_t)__popcll(m));
+        base = __shfl(base, leader < 0 ? 0 : leader, 64);
+        if (other) {
+            d.ilist[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+        } else {
+            R4<R> z;
+            z.x = z.y = z.z = z.w = (R)0;
+            ((R4<R>*)d.gc)[i] = z;
+            R4<R>& a = ((R4<R>*)d.S[cur].aux)[i];
+            a.z = fabs(a.z);
+        }
     });
 }
 
@@ -912,29 +931,36 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
 
 // ----------------------------------------------- Eq. (16) colour gradient (pass A)
 
-template <class R, int DIM, int P>
-__global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star, int remap)
+// Lanes per particle and list entries per batch of the colour pass.  It runs over the
+// compact list of particles with another phase in their neighbour list (about 1 % of
+// the particles in the drop), so its time is the latency of one particle's walk: many
+// lanes per particle shorten that walk.  kColourLanes * kColourBatch divides the list
+// capacity.
+constexpr int kColourLanes = 8, kColourBatch = 2;
+
+template <class R, int DIM>
+__global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
 {
-    uint32_t i, sub;
-    lane_split<P>(remap, i, sub);
-    if (i >= d.n) return;
+    constexpr int P = kColourLanes;
     const int cur = *d.curp;
+    const uint32_t count = *d.icount;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t sub = t % P, stride = gridDim.x * blockDim.x / P;
     const Sorted& O = d.O[cur];
     const StateSet& S = star ? d.star : d.S[cur];
     R4<R>* gc = (R4<R>*)d.gc;
     R4<R>* aux = (R4<R>*)S.aux;
-    R g[3] = {0, 0, 0};
-    R gn = 0;
-    if (d.nbx[i]) {   // only particles with an other-phase particle in their list
-        const R4<R>* pos = (const R4<R>*)S.pos;
-        const R4<R>* vel = (const R4<R>*)S.vel;
+    const R4<R>* pos = (const R4<R>*)S.pos;
+    const R4<R>* vel = (const R4<R>*)S.vel;
+    for (uint32_t g = t / P; g < count; g += stride) {
+        const uint32_t i = d.ilist[g];
         const R4<R> pi = pos[i];
         const uint32_t ph = pos_phase(pi);
         R s[3] = {0, 0, 0};
         per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
             Lane<R> L;
             L.load(I, pi, O.key[i]);
-            for_each_neighbor<R, DIM, 4, P>(d, I, pos, i, L, sub, [](uint32_t) { return NoExtra{}; },
+            for_each_neighbor<R, DIM, kColourBatch, P>(d, I, pos, i, L, sub, [](uint32_t) { return NoExtra{}; },
                 [&](uint32_t k, const R* r, R r2, const R4<R>& pj, NoExtra) {
                     if (pos_phase(pj) == ph) return;             // C_j^y = 1 only for the other phase
                     const R vk = vel[k].w;                       // 1 / sigma_k
@@ -944,18 +970,19 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star, 
                     s[2] += f * r[2];
                 });
         });
-        const R vi = vel[i].w;                               // sigma_i = 1 / V_i
-        g[0] = group_sum<P>(s[0]) / vi;
-        g[1] = group_sum<P>(s[1]) / vi;
-        g[2] = group_sum<P>(s[2]) / vi;
-        gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-    }
-    if (sub == 0) {
-        R4<R> out;
-        out.x = g[0]; out.y = g[1]; out.z = g[2]; out.w = gn;
-        gc[i] = out;
-        const R v = fabs(aux[i].z);
-        aux[i].z = gn > 0 ? -v : v;       // interface flag: the sign of the V copy
+        const R vi = vel[i].w;                                   // sigma_i = 1 / V_i
+        R g3[3];
+        g3[0] = group_sum<P>(s[0]) / vi;
+        g3[1] = group_sum<P>(s[1]) / vi;
+        g3[2] = group_sum<P>(s[2]) / vi;
+        const R gn = sqrt(g3[0] * g3[0] + g3[1] * g3[1] + g3[2] * g3[2]);
+        if (sub == 0) {
+            R4<R> out;
+            out.x = g3[0]; out.y = g3[1]; out.z = g3[2]; out.w = gn;
+            gc[i] = out;
+            const R v = fabs(aux[i].z);
+            aux[i].z = gn > 0 ? -v : v;       // interface flag: the sign of the V copy
+        }
     }
 }
 
@@ -1467,11 +1494,11 @@ void launch_derive(const Dev& d, const Launch&, hipStream_t s)
 
 void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s)
 {
-    const dim3 grid(blocks_for(d.n * L.lanes, L.block)), block(L.block);
+    // grid-stride over the colour list, whose length is known only on the device
+    const unsigned nb = blocks_for(d.n * kColourLanes, L.block);
+    const dim3 grid(nb < 4096u ? nb : 4096u), block(L.block);
     SPHX_DISPATCH(d.precision, d.dim, ({
-        SPHX_LANES(L.lanes, ({
-            hipLaunchKernelGGL((k_colour<R, D, P>), grid, block, 0, s, d, star ? 1 : 0, L.xcd_remap);
-        }));
+        hipLaunchKernelGGL((k_colour<R, D>), grid, block, 0, s, d, star ? 1 : 0);
     }));
 }
 

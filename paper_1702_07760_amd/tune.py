@@ -4,7 +4,7 @@ Times short graph-replayed runs of a scene over a grid of options and keeps the
 fastest.  The options:
   block        threads per block of the neighbour passes (64, 128, 256);
   xcd_remap    consecutive tiles on one XCD, or the default round-robin;
-  lanes        lanes per particle in the renormalisation and colour passes (1, 2, 4);
+  lanes        lanes per particle in the renormalisation pass (1, 2, 4);
   force_lanes  lanes per particle in the force pass (1, 2, 4);
   skin         neighbour skin in units of h, which sets the cell size and list radius
                (2 + skin) h; a larger skin means longer lists, a smaller one more
