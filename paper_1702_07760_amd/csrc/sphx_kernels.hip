@@ -301,8 +301,10 @@ template <> struct StencilBatch<double> { static constexpr int U = 4; };
 // Visit every j != i with |r_ij|^2 < cut2 among the 3^d cells around i's cell:
 // body(j, r_ij, |r_ij|^2, record of j, list code).  When P lanes share particle i,
 // lane `sub` takes every P-th candidate of each cell run.  U candidates are loaded per
-// batch.
-template <class R, int DIM, int P = 1, int U = StencilBatch<R>::U, class IC, class Body>
+// batch.  With ALL, the lanes of a group step through each run together and the body
+// is called for every candidate slot with a flag `in` (a candidate j != i within the
+// cutoff), so that the group can rank its accepted candidates with a ballot.
+template <class R, int DIM, int P = 1, int U = StencilBatch<R>::U, bool ALL = false, class IC, class Body>
 __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __restrict__ cstart,
                                               const R4<R>* __restrict__ pos, uint32_t i,
                                               const Lane<R>& L, R cut2, uint32_t sub, Body&& body)
@@ -345,18 +347,36 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
             }
             for (int seg = 0; seg < 2; ++seg) {
                 const uint32_t a = seg ? a1 : a0, b = seg ? b1 : b0;
-                for (uint32_t k0 = a + sub; k0 < b; k0 += U * P) {
-                    R4<R> pj[U];
+                if constexpr (ALL) {
+                    // group-uniform trip count: every lane of the group sees every slot
+                    for (uint32_t kb = a; kb < b; kb += U * P) {
+                        const uint32_t k0 = kb + sub;
+                        R4<R> pj[U];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) pj[u] = pos[min(k0 + (uint32_t)(u * P), b - 1)];
+                        for (int u = 0; u < U; ++u) pj[u] = pos[min(k0 + (uint32_t)(u * P), b - 1)];
 #pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const uint32_t k = k0 + (uint32_t)(u * P);
-                        if (k < b && k != i) {
+                        for (int u = 0; u < U; ++u) {
+                            const uint32_t k = k0 + (uint32_t)(u * P);
                             R r[3];
                             const uint32_t code = pair_r<DIM>(I, L, row, pj[u], r);
                             const R r2 = dist2<DIM>(r[0], r[1], r[2]);
-                            if (r2 < cut2) body(k, r, r2, pj[u], code);
+                            body(k, r, r2, pj[u], code, k < b && k != i && r2 < cut2);
+                        }
+                    }
+                } else {
+                    for (uint32_t k0 = a + sub; k0 < b; k0 += U * P) {
+                        R4<R> pj[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) pj[u] = pos[min(k0 + (uint32_t)(u * P), b - 1)];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const uint32_t k = k0 + (uint32_t)(u * P);
+                            if (k < b && k != i) {
+                                R r[3];
+                                const uint32_t code = pair_r<DIM>(I, L, row, pj[u], r);
+                                const R r2 = dist2<DIM>(r[0], r[1], r[2]);
+                                if (r2 < cut2) body(k, r, r2, pj[u], code);
+                            }
                         }
                     }
                 }
@@ -728,21 +748,29 @@ __global__ void k_decide(Dev d)
 
 // Neighbour list at the current positions: every j within the cell size (2 + skin) h
 // (with a rounding margin).  Together with the rebuild rule this holds every pair within
-// 2h at any state evaluated before the next rebuild.  Particles with an other-phase
-// particle in their list (the only ones whose colour gradient can be non-zero) are
-// appended to the colour-pass index list; every other particle gets a zero gradient
-// and a cleared interface flag here, once per build.
+// 2h at any state evaluated before the next rebuild.  kNlistLanes lanes share a particle
+// and take every kNlistLanes-th candidate; a ballot ranks each slot's accepted
+// candidates, so the list keeps the candidate order (the same as one lane would write).
+// Particles with an other-phase particle in their list (the only ones whose colour
+// gradient can be non-zero) are appended to the colour-pass index list; every other
+// particle gets a zero gradient and a cleared interface flag here, once per build.
+constexpr int kNlistLanes = 4;
+
 template <class R, int DIM>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
 {
+    constexpr int P = kNlistLanes;
     if (!d.flags[0]) return;
     const int cur = *d.curp;
-    const uint32_t i = tile_index(remap) * blockDim.x + threadIdx.x;
+    uint32_t i, sub;
+    lane_split<P>(remap, i, sub);
     if (i >= d.n) return;
     const Sorted& O = d.O[cur];
     const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
     const R4<R> pi = pos[i];
-    ((R4<R>*)d.xb)[i] = pi;
+    if (sub == 0) ((R4<R>*)d.xb)[i] = pi;
+    const uint32_t lane = threadIdx.x & 63, gbase = lane & ~(uint32_t)(P - 1);
+    const uint32_t gmask = (1u << P) - 1u, below = (1u << sub) - 1u;
     per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
         Lane<R> L;
         L.load(I, pi, O.key[i]);
@@ -752,22 +780,27 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
         const uint32_t cap = d.cap;
         uint32_t cnt = 0;
         bool other = false;
-        for_neighbors<R, DIM>(I, d.cstart, pos, i, L, cutl2_of<R>(I), 0u,
-                              [&](uint32_t k, const R*, R, const R4<R>& pj, uint32_t code) {
-                                  if (cnt < cap) nb[(size_t)cnt * n] = k | (code << kIdxBits);
-                                  ++cnt;
-                                  other |= pos_phase(pj) != ph;
-                              });
-        d.nbc[i] = cnt;
-        const unsigned long long m = __ballot(other);
-        const int lane = threadIdx.x & 63;
+        for_neighbors<R, DIM, P, StencilBatch<R>::U, true>(I, d.cstart, pos, i, L, cutl2_of<R>(I), sub,
+            [&](uint32_t k, const R*, R, const R4<R>& pj, uint32_t code, bool in) {
+                const uint32_t grp = (uint32_t)(__ballot(in) >> gbase) & gmask;
+                if (in) {
+                    const uint32_t q = cnt + (uint32_t)__popc(grp & below);
+                    if (q < cap) nb[(size_t)q * n] = k | (code << kIdxBits);
+                    other |= pos_phase(pj) != ph;
+                }
+                cnt += (uint32_t)__popc(grp);
+            });
+        const bool gother = ((uint32_t)(__ballot(other) >> gbase) & gmask) != 0u;
+        if (sub == 0) d.nbc[i] = cnt;
+        const bool append = sub == 0 && gother;
+        const unsigned long long m = __ballot(append);
         const int leader = __ffsll((long long)m) - 1;
         uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(d.icount, (uint32_t)__popcll(m));
+        if ((int)lane == leader) base = atomicAdd(d.icount, (uint32_t)__popcll(m));
         base = __shfl(base, leader < 0 ? 0 : leader, 64);
-        if (other) {
+        if (append) {
             d.ilist[base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
-        } else {
+        } else if (sub == 0 && !gother) {
             R4<R> z;
             z.x = z.y = z.z = z.w = (R)0;
             ((R4<R>*)d.gc)[i] = z;
@@ -1441,7 +1474,8 @@ static void build_impl(const Dev& d, const Launch& L, hipStream_t s)
     hipLaunchKernelGGL(k_rank, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
     hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, d.O[0].ref ? 1 : 0);
     hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d);
-    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, L.xcd_remap);
+    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n * kNlistLanes, L.block)), dim3(L.block), 0, s, d,
+                       L.xcd_remap);
 }
 
 #define SPHX_DISPATCH(PREC, DIM, CALL)                                  \
@@ -1463,7 +1497,8 @@ void launch_build(const Dev& d, const Launch& L, hipStream_t s)
 void launch_nlist(const Dev& d, const Launch& L, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n, L.block)), dim3(L.block), 0, s, d, L.xcd_remap);
+        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n * kNlistLanes, L.block)), dim3(L.block), 0, s, d,
+                           L.xcd_remap);
     }));
 }
 
