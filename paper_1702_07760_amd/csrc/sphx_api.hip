@@ -506,6 +506,7 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
     sphx_ctx* c = new sphx_ctx();
     c->precision = precision;
     c->launch.force_lanes = precision == 0 ? 2 : 1;   // measured best on the 3D drop
+    c->launch.xcd_remap = precision == 0 ? 1 : 4;     // likewise (FP32: about 1.5 %)
     c->dim = per_inst[0].dim;
     c->ninst = ninst;
     c->nphase = nphase;
@@ -771,7 +772,11 @@ sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
         if (value < 64 || value > 256 || value % 64) return fail(c, SPHX_E_ARG, "block must be 64, 128, 192 or 256");
         c->launch.block = (int)value;
         break;
-    case SPHX_OPT_XCD_REMAP: c->launch.xcd_remap = value != 0; break;
+    case SPHX_OPT_XCD_REMAP:
+        if (value < 0 || value > 64 || (value > 1 && (value & (value - 1))))
+            return fail(c, SPHX_E_ARG, "xcd_remap must be 0, 1 or a power of two up to 64");
+        c->launch.xcd_remap = (int)value;
+        break;
     case SPHX_OPT_LANES:
     case SPHX_OPT_FORCE_LANES:
         if (value != 1 && value != 2 && value != 4) return fail(c, SPHX_E_ARG, "lanes must be 1, 2 or 4");

@@ -31,11 +31,24 @@ __device__ __forceinline__ uint32_t tile_index(int remap)
 {
     const uint32_t b = blockIdx.x, G = gridDim.x;
     if (!remap) return b;
-    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
-    // run of tiles so that neighbouring particles share one L2.
+    // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of
+    // tiles so that neighbouring particles share one L2.
     const uint32_t X = 8, full = (G / X) * X;
     if (b >= full) return b;
-    return (b % X) * (G / X) + b / X;
+    const uint32_t per = G / X, xcd = b % X;
+    uint32_t j = b / X;
+    if (remap >= 2) {
+        // and within an XCD, assuming its 32 CUs are dealt round-robin as well, give the
+        // K = remap workgroups a CU holds at once K consecutive tiles (shared neighbours
+        // in its L1); a bijection on each full chunk of 32 K workgroups
+        constexpr uint32_t S = 32;
+        const uint32_t K = (uint32_t)remap, C = S * K;
+        if (j / C < per / C) {
+            const uint32_t r = j % C;
+            j = (j / C) * C + (r % S) * K + r / S;
+        }
+    }
+    return xcd * per + j;
 }
 
 __device__ __forceinline__ int wrapi(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }

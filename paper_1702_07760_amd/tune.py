@@ -3,7 +3,8 @@
 Times short graph-replayed runs of a scene over a grid of options and keeps the
 fastest.  The options:
   block        threads per block of the neighbour passes (64, 128, 256);
-  xcd_remap    consecutive tiles on one XCD, or the default round-robin;
+  xcd_remap    tile order: dispatch order (0), consecutive tiles per XCD (1), and K
+               consecutive tiles per CU as well (K = 4, 16);
   lanes        lanes per particle in the renormalisation pass (1, 2, 4);
   force_lanes  lanes per particle in the force pass (1, 2, 4);
   skin         neighbour skin in units of h, which sets the cell size and list radius
@@ -27,10 +28,10 @@ from . import binding
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 BLOCKS = (64, 128, 256)
-REMAPS = (0, 1)
+REMAPS = (0, 1, 4, 16)
 LANES = (1, 2, 4)
 SKINS = (0.05, 0.1, 0.2)
-DEFAULTS = {"skin": 0.1, "block": 64, "xcd_remap": 1, "lanes": 4, "force_lanes": None}
+DEFAULTS = {"skin": 0.1, "block": 64, "xcd_remap": None, "lanes": 4, "force_lanes": None}
 
 
 def cache_key(scene, precision, arch="gfx950"):
@@ -69,6 +70,7 @@ def tune(scene, precision=binding.FP32_CELLREL, steps=20, warmup=3, skins=SKINS,
     grid = {"skin": skins, "block": blocks, "xcd_remap": remaps, "lanes": lanes, "force_lanes": lanes}
     best = dict(DEFAULTS)
     best["force_lanes"] = 1 if precision == binding.FP32_CELLREL else 2
+    best["xcd_remap"] = 4 if precision == binding.FP32_CELLREL else 1
     results = []
     best_ms = 1e3 * _time(scene, precision, best, steps, warmup)
     results.append(dict(best, ms_per_step=best_ms))

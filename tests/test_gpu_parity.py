@@ -431,12 +431,48 @@ def test_blocks_above_256_are_rejected():
 def test_tuner_returns_a_working_option_set():
     from paper_1702_07760_amd import tune
     s = inputs.drop2d(perturb=True)
-    best = tune.tune(s, steps=2, warmup=1, skins=(0.1,), blocks=(128, 256), remaps=(1,), lanes=(1, 4),
+    best = tune.tune(s, steps=2, warmup=1, skins=(0.1,), blocks=(128, 256), remaps=(1, 16), lanes=(1, 4),
                      save=False, log=None)
     assert best["ms_per_step"] > 0
-    # the search starts from the defaults (block 64, 4 lanes, 1 force lane in FP32)
+    # the search starts from the defaults (block 64, 4 lanes, 1 force lane, 4 tiles per CU in FP32)
     assert best["lanes"] in (1, 4) and best["force_lanes"] in (1, 4) and best["block"] in (64, 128, 256)
+    assert best["xcd_remap"] in (1, 4, 16)
     sim = binding.Sim(s.with_params(skin_coef=best["skin"]), precision=binding.FP32_CELLREL)
     tune.apply(sim, best)
     sim.step(2)
     sim.sync()
+
+
+@pytest.mark.parametrize("remap", [0, 1, 16])
+def test_rates_with_other_tile_orders(remap, oracle_rates):
+    s, ref, _ = oracle_rates("drop3d_small")
+    print(f"case rates remap={remap}", flush=True)
+    sim = binding.Sim(s, precision=binding.FP32_CELLREL)
+    sim.set_option(binding.OPT_XCD_REMAP, remap)
+    sim.renormalize_density()
+    sim.compute_forces()
+    sim.sync()
+    tol = TOL[binding.FP32_CELLREL]
+    assert rel_to(sim.get_field(binding.F_RHO), ref[oracle.RHO], 1000.0) < tol
+    total_scale = ref[oracle.SAP] + ref[oracle.SAV] + ref[oracle.SAS]
+    assert enorm(sim.get_field(binding.F_A), ref[oracle.A], total_scale) < tol
+    with pytest.raises(binding.SphxError, match="xcd_remap"):
+        sim.set_option(binding.OPT_XCD_REMAP, 3)
+
+
+def test_tile_orders_give_identical_rates_on_the_full_drop():
+    # every particle's sums are independent of which workgroup computes them, so the
+    # tile permutations (full 32 K chunks only exist at this size) change nothing
+    s = inputs.drop3d()
+    out = []
+    for remap in (1, 4, 16):
+        sim = binding.Sim(s, precision=binding.FP32_CELLREL)
+        sim.set_option(binding.OPT_XCD_REMAP, remap)
+        sim.renormalize_density()
+        sim.compute_forces()
+        sim.sync()
+        out.append([sim.get_field(f) for f in (binding.F_RHO, binding.F_A, binding.F_DRHO)])
+        sim.close()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
