@@ -216,7 +216,7 @@ struct Carver {
     {
         off = (off + 255) & ~size_t(255);
         T* p = base ? (T*)(base + off) : nullptr;
-        off += count * sizeof(T) + (count == 0 ? 0 : 0);
+        off += count * sizeof(T);
         return p;
     }
 };

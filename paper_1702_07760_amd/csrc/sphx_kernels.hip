@@ -837,15 +837,23 @@ __device__ __forceinline__ double rho_of(const IC& I, uint32_t phase, R stored)
 // and aux.z (the copy read by the renormalisation, positive: interface flag cleared),
 // m P / rho^2 into aux.y, the density itself into aux.w.
 template <class R>
-__device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R stored, R4<R>& vel, R4<R>& aux)
+__device__ __forceinline__ void derive_values(const InstDev& I, uint32_t phase, R stored, R m_, R& V, R& mA)
 {
     const double rho = rho_of<R>(I, phase, stored);
     const double y = sizeof(R) == 8 ? rho / I.rho0[phase] : 1.0 + (double)stored / I.rho0[phase];
     const double P = tait(y, I.beta[phase]);
-    const double m = (double)aux.x;
-    const R V = (R)(m / rho);
+    const double m = (double)m_;
+    V = (R)(m / rho);
+    mA = (R)(m * (P / (rho * rho)));
+}
+
+template <class R>
+__device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R stored, R4<R>& vel, R4<R>& aux)
+{
+    R V, mA;
+    derive_values<R>(I, phase, stored, aux.x, V, mA);
     vel.w = V;
-    aux.y = (R)(m * (P / (rho * rho)));
+    aux.y = mA;
     aux.z = V;
     aux.w = stored;
 }
@@ -868,16 +876,19 @@ __global__ void k_derive(Dev d, int from_tmp, int force)
     const uint32_t info = d.O[cur].info[k];
     const InstDev& I = d.inst[info_inst(info)];
     const StateSet& S = d.S[cur];
-    R4<R> vel = ((R4<R>*)S.vel)[k];
     R4<R> aux = ((R4<R>*)S.aux)[k];
-    R r = aux.w;
-    if (from_tmp) {
-        r = ((const R*)d.rho_tmp)[k];
-        if constexpr (sizeof(R) == 4) S.plo[k].w = 0.0f;   // a fresh value: no carried error
-    }
-    derive_one<R>(I, info_phase(info), r, vel, aux);
-    ((R4<R>*)S.vel)[k] = vel;
+    const R r = from_tmp ? ((const R*)d.rho_tmp)[k] : aux.w;
+    R V, mA;
+    derive_values<R>(I, info_phase(info), r, aux.x, V, mA);
+    // only V (vel.w) and the aux record change: a vel load and store of the velocity
+    // itself would double this kernel's traffic and latency
+    ((R*)S.vel)[4 * (size_t)k + 3] = V;
+    aux.y = mA;
+    aux.z = V;
+    aux.w = r;
     ((R4<R>*)S.aux)[k] = aux;
+    if constexpr (sizeof(R) == 4)
+        if (from_tmp) S.plo[k].w = 0.0f;   // a fresh value: no carried error
 }
 
 // -------------------------------------------------------- Eq. (7) renormalise
