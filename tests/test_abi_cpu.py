@@ -37,7 +37,7 @@ def _create(scene, precision=0, mutate=None, nphase=None):
 
 
 @pytest.mark.parametrize("case", ["gamma", "dim", "h", "skin", "phase_rho0", "precision",
-                                  "nphase", "count", "periodic_small", "lohi"])
+                                  "nphase", "count", "count_max", "periodic_small", "lohi"])
 def test_create_rejects_bad_arguments(case):
     s = inputs.drop2d()
     prec, nphase = 0, None
@@ -55,6 +55,8 @@ def test_create_rejects_bad_arguments(case):
             ph[1].rho0 = 0.0
         elif case == "count":
             cnt[0] = 0
+        elif case == "count_max":
+            cnt[0] = 1 << 26          # list entries hold 26-bit particle indices
         elif case == "periodic_small":
             p[0].periodic[0] = 1
             p[0].hi[0] = p[0].lo[0] + 4 * p[0].h

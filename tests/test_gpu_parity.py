@@ -476,3 +476,72 @@ def test_tile_orders_give_identical_rates_on_the_full_drop():
     for other in out[1:]:
         for a, b in zip(out[0], other):
             assert np.array_equal(a, b)
+
+
+# ---- edge cases: one particle, ragged sizes, one phase only, exact cutoff ties
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n", [1, 63, 65])
+def test_isolated_particles_fall_freely(n, prec):
+    s = inputs.isolated_particles(dim=3, n=n, spacing=3.0, h=1.0)
+    k = np.arange(n)
+    s.x[:, 0] = 0.5 + 3.0 * (k % 8)          # an 8-wide grid, 3 m (> 2h) apart, inside the box
+    s.x[:, 1] = 0.5 + 3.0 * (k // 8)
+    print(f"case isolated n={n} precision={prec}", flush=True)
+    o, sim = _one_step(s, prec, nsteps=3)
+    assert sim.stats()["interactions"] == 0
+    assert rel_to(sim.get_field(binding.F_X), o.get(oracle.X), 1e-3) < TOL[prec]
+    assert rel_to(sim.get_field(binding.F_U), o.get(oracle.U), 1.0) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("dim,side", [(2, 9), (3, 9)])
+def test_ragged_lattices_match_oracle(dim, side, prec):
+    # 81 and 729 particles: whole waves plus a partial one, with an oil region
+    s = inputs.lattice_box(dim, side, 1e-3, periodic=True,
+                           oil=lambda x: x[:, 0] < side * 1e-3 / 2)
+    rng = np.random.default_rng(5)
+    s.u[:, :dim] = rng.uniform(-0.2, 0.2, (s.n, dim))
+    # a parity state perturbs the density too: at exactly rho0 the pressure is the
+    # rounding noise of (rho/rho0)^7 - 1 on both sides, and its E-norm is meaningless
+    s.rho *= 1 + rng.uniform(-0.005, 0.005, s.n)
+    s.params[0]["alpha_s"] = 0.02
+    print(f"case ragged dim={dim} n={s.n} precision={prec}", flush=True)
+    o = oracle.Oracle(s)
+    o.renormalize()
+    o.rates()
+    sim = binding.Sim(s, precision=prec)
+    sim.renormalize_density()
+    sim.compute_forces()
+    tol = TOL[prec]
+    assert rel_to(sim.get_field(binding.F_RHO), o.get(oracle.RHO), 1000.0) < tol
+    scale = o.get(oracle.SAP) + o.get(oracle.SAV) + o.get(oracle.SAS)
+    assert enorm(sim.get_field(binding.F_A), o.get(oracle.A), scale) < tol
+    assert enorm(sim.get_field(binding.F_DRHO), o.get(oracle.DRHO), o.get(oracle.SDRHO)) < tol
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_single_phase_tank_has_no_interface(prec):
+    s = inputs.still_tank(2)
+    print(f"case single phase precision={prec}", flush=True)
+    o, sim = _one_step(s, prec, nsteps=2)
+    assert np.all(sim.get_field(binding.F_GRADC) == 0.0)
+    assert rel_to(sim.get_field(binding.F_X), o.get(oracle.X), s.dx[0]) < TOL[prec]
+    assert rel_to(sim.get_field(binding.F_RHO), o.get(oracle.RHO), 1000.0) < TOL[prec]
+
+
+def test_pairs_exactly_at_the_cutoff_are_not_neighbours():
+    # h = 0.25: a pair exactly 2h = 0.5 apart (r^2 == 4h^2 in FP64) is excluded, a pair one
+    # ulp (of the coordinate) closer is included, on both sides
+    s = inputs.isolated_particles(dim=2, n=4, spacing=3.0, h=0.25, u0=(0.0, 0.0))
+    s.x[1] = s.x[0] + [0.5, 0.0, 0.0]
+    s.x[3] = s.x[2] + [0.5, 0.0, 0.0]
+    s.x[3, 0] = np.nextafter(s.x[3, 0], 0.0)
+    assert (s.x[1, 0] - s.x[0, 0]) ** 2 == 4 * 0.25 ** 2
+    assert (s.x[3, 0] - s.x[2, 0]) ** 2 < 4 * 0.25 ** 2
+    o = oracle.Oracle(s)
+    off, ids = o.neighbors()
+    sim = binding.Sim(s, precision=binding.FP64)
+    goff, gids = sim.get_neighbors()
+    assert np.array_equal(goff, off) and np.array_equal(gids, ids)
+    assert list(np.diff(goff)) == [0, 0, 1, 1]
