@@ -413,9 +413,6 @@ template <class R> struct MaxBlock { static constexpr int value = 256; };
 // same for all lanes and the lane part sub n + i is fixed.  A batch may read entries
 // past cnt (never past the capacity, a multiple of U P); they are replaced by a valid
 // index and skipped.
-#ifndef SPHX_LIST_PREFETCH
-#define SPHX_LIST_PREFETCH 1
-#endif
 template <class R, int DIM, int U, int P, class IC, class Load, class Body>
 __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>* __restrict__ pos,
                                          uint32_t i, const Lane<R>& L, uint32_t cnt, uint32_t sub,
@@ -427,50 +424,31 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
     const uint32_t lane_off = (sub * n + i) * 4u;   // < 2^31: n < 2^26, sub < 8
     const size_t step = (size_t)P * n * 4u;
     const R cut2 = cut2_of<R>(I);
-#if SPHX_LIST_PREFETCH
-    // the entries of the next D batches are in flight while a batch is computed; each
-    // batch's request goes out after the current gathers: vector loads retire in order,
-    // so a wait for the gathers does not wait for the list entries too
-    constexpr int D = SPHX_LIST_PREFETCH;
-    uint32_t nxt[D][U];
+    auto entry = [&](uint32_t q) { return *(const uint32_t*)(base + (size_t)q * step + lane_off); };
+    // the entries of the next batch are in flight while a batch is computed; they are
+    // requested after the current gathers: vector loads retire in order, so a wait for
+    // the gathers does not wait for the list entries too
+    uint32_t nxt[U];
+    if (sub < cnt) {
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-        if ((uint32_t)(a * U) * P + sub < cnt) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                nxt[a][u] = *(const uint32_t*)(base + (size_t)(a * U + u) * step + lane_off);
-        }
-#endif
+        for (int u = 0; u < U; ++u) nxt[u] = entry((uint32_t)u);
+    }
     for (uint32_t t0 = 0; t0 * P + sub < cnt; t0 += U) {
         uint32_t e[U];
         R4<R> pj[U];
         X x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-#if SPHX_LIST_PREFETCH
-            const uint32_t raw = nxt[0][u];
-#else
-            const uint32_t raw = *(const uint32_t*)(base + (size_t)(t0 + (uint32_t)u) * step + lane_off);
-#endif
-            e[u] = (t0 + (uint32_t)u) * P + sub < cnt ? raw : 0u;
-        }
+        for (int u = 0; u < U; ++u) e[u] = (t0 + (uint32_t)u) * P + sub < cnt ? nxt[u] : 0u;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t k = e[u] & kIdxMask;
             pj[u] = pos[k];
             x[u] = load(k);
         }
-#if SPHX_LIST_PREFETCH
+        if ((t0 + U) * P + sub < cnt) {
 #pragma unroll
-        for (int a = 0; a + 1 < D; ++a)
-#pragma unroll
-            for (int u = 0; u < U; ++u) nxt[a][u] = nxt[a + 1][u];
-        if ((t0 + (uint32_t)(D * U)) * P + sub < cnt) {
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                nxt[D - 1][u] = *(const uint32_t*)(base + (size_t)(t0 + (uint32_t)(D * U + u)) * step + lane_off);
+            for (int u = 0; u < U; ++u) nxt[u] = entry(t0 + U + (uint32_t)u);
         }
-#endif
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if ((t0 + (uint32_t)u) * P + sub < cnt) {
