@@ -423,13 +423,42 @@ struct BlobHeader {
     int64_t n;
     uint32_t ncell, rates_valid, cap, pad;
 };
-constexpr uint64_t kMagic = 0x5350485853543033ull;   // "SPHXST03"
+constexpr uint64_t kMagic = 0x5350485853543034ull;   // "SPHXST04"
 
 struct Span { void* p; size_t bytes; };
 
 // Everything a continuation depends on, in the sorted order of state set `s`: the state,
 // the cell table, the neighbour list and its build positions, the per-instance run
 // variables and the last rates.
+// The per-instance mass table: umass stays 1 for an instance while all its particles
+// of one phase share one mass.  particle(i, inst, phase, mass) describes particle i.
+template <class F>
+void mass_table(sphx_ctx* c, int64_t n, F&& particle)
+{
+    std::vector<char> seen((size_t)c->ninst * 2, 0);
+    for (InstDev& I : c->inst) {
+        I.umass = 1;
+        I.mass[0] = I.mass[1] = 0.0;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t b = 0, q = 0;
+        double m = 0.0;
+        particle(i, b, q, m);
+        InstDev& I = c->inst[b];
+        char& s = seen[(size_t)b * 2 + q];
+        if (!s) {
+            I.mass[q] = m;
+            s = 1;
+        } else if (m != I.mass[q]) {
+            I.umass = 0;
+        }
+    }
+    for (InstDev& I : c->inst) {
+        I.f_mass[0] = (float)I.mass[0];
+        I.f_mass[1] = (float)I.mass[1];
+    }
+}
+
 std::vector<Span> state_spans(sphx_ctx* c, int s)
 {
     const size_t n = (size_t)c->n, R = c->precision ? 4 : 8;
@@ -615,7 +644,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
             key[i] = I.cell_base + (uint32_t)cc[0] + (uint32_t)I.nc[0] * ((uint32_t)cc[1] + (uint32_t)I.nc[1] * (uint32_t)cc[2]);
             const double r0 = I.rho0[phase[i]];
             if (!f32) {
-                ((double4*)pos.data())[i] = make_double4(xi[0], xi[1], xi[2], (double)phase[i]);
+                ((double4*)pos.data())[i] = make_double4(xi[0], xi[1], xi[2], 0.0);   // w = m P / rho^2: derived
                 ((double4*)vel.data())[i] = make_double4(u[3 * i], c->dim > 1 ? u[3 * i + 1] : 0.0, c->dim > 2 ? u[3 * i + 2] : 0.0, 0.0);
                 ((double4*)aux.data())[i] = make_double4(m[i], 0.0, 0.0, rho[i]);   // V, m P / rho^2: derived
             } else {
@@ -630,10 +659,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
                 }
                 const double dr = rho[i] - r0;
                 const float drf = (float)dr;
-                uint32_t kb = key[i] | ((uint32_t)phase[i] << 31);
-                float kf;
-                std::memcpy(&kf, &kb, 4);
-                ((float4*)pos.data())[i] = make_float4(o[0], o[1], o[2], kf);
+                ((float4*)pos.data())[i] = make_float4(o[0], o[1], o[2], 0.0f);   // w: derived
                 plo[i] = make_float4(e[0], e[1], e[2], (float)(dr - (double)drf));
                 ((float4*)vel.data())[i] = make_float4(uu[0], uu[1], uu[2], 0.0f);
                 vlo[i] = make_float4(ue[0], ue[1], ue[2], 0.0f);
@@ -641,6 +667,11 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
             }
         }
     }
+    mass_table(c, n, [&](int64_t i, uint32_t& b, uint32_t& q, double& mi) {
+        b = info_inst(info[i]);
+        q = phase[i];
+        mi = f32 ? (double)(float)m[i] : m[i];
+    });
     Dev& d = c->dev;
     const hipStream_t s = c->stream;
     HIP_OK(c, hipMemcpyAsync((void*)d.inst, c->inst.data(), sizeof(InstDev) * c->ninst, hipMemcpyHostToDevice, s));
@@ -1048,10 +1079,40 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
     if (bytes != total) return fail(c, SPHX_E_ARG, "blob size mismatch");
     HIP_OK(c, hipStreamSynchronize(c->stream));
     const char* p = (const char*)blob + sizeof h;
+    // the mass table of the blob's particles: aux (third span) holds m in x, info (sixth)
+    // the instance and phase
+    {
+        const bool f32 = c->precision == 1;
+        const char* aux = p + spans[0].bytes + spans[1].bytes;
+        const char* inf = aux + spans[2].bytes + spans[3].bytes + spans[4].bytes;
+        auto info_at = [&](int64_t i) {
+            uint32_t f;
+            std::memcpy(&f, inf + 4 * (size_t)i, 4);
+            return f;
+        };
+        for (int64_t i = 0; i < c->n; ++i) {
+            const uint32_t f = info_at(i);
+            if (info_inst(f) >= (uint32_t)c->ninst || info_phase(f) >= (uint32_t)c->nphase)
+                return fail(c, SPHX_E_ARG, "blob: particle %lld has a bad instance or phase", (long long)i);
+        }
+        mass_table(c, c->n, [&](int64_t i, uint32_t& b, uint32_t& q, double& mi) {
+            const uint32_t f = info_at(i);
+            b = info_inst(f);
+            q = info_phase(f);
+            if (f32) {
+                float v;
+                std::memcpy(&v, aux + 16 * (size_t)i, 4);
+                mi = v;
+            } else {
+                std::memcpy(&mi, aux + 32 * (size_t)i, 8);
+            }
+        });
+    }
     for (auto& s : spans) {
         HIP_OK(c, hipMemcpy(s.p, p, s.bytes, hipMemcpyHostToDevice));
         p += s.bytes;
     }
+    HIP_OK(c, hipMemcpy((void*)c->dev.inst, c->inst.data(), sizeof(InstDev) * c->ninst, hipMemcpyHostToDevice));
     const int cur = h.cur;
     const uint32_t flags[2] = {0u, 0u};
     HIP_OK(c, hipMemcpy(c->dev.curp, &cur, sizeof cur, hipMemcpyHostToDevice));

@@ -37,9 +37,13 @@ struct InstDev {
     int32_t n_piston;
     double piston_t_end;
     double pa[kMaxPiston], pw[kMaxPiston], pphi[kMaxPiston];
+    // particle mass by phase, valid when umass = 1: every particle of the instance with
+    // that phase has this mass (the force pass then reads no mass per neighbour)
+    int32_t umass;
+    double mass[2];
     // FP32 copies for the cell-relative kernels
     float f_cs[3], f_inv_h, f_cut2, f_cutl2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3];
-    float f_vpair[2][2], f_rho0[2];
+    float f_vpair[2][2], f_rho0[2], f_mass[2];
 };
 
 // Per-instance run variables on the device.
@@ -54,10 +58,9 @@ struct InstRun {
 
 // One copy of the cell-sorted particle state.
 struct StateSet {
-    void* pos;   // R4: FP64 (x, y, z, phase); FP32 (ox, oy, oz, bits(cell key | phase << 31))
-    void* vel;   // R4: (ux, uy, uz, V = m / rho)
-    void* aux;   // R4: (m, m P / rho^2, +-V, rho); the sign of z is the interface flag,
-                 //     w is rho in FP64 and rho - rho0 in FP32
+    void* pos;   // R4: FP64 (x, y, z, m P / rho^2); FP32 (ox, oy, oz, m P / rho^2)
+    void* vel;   // R4: (ux, uy, uz, +-V), V = m / rho; the sign of w is the interface flag
+    void* aux;   // R4: (m, m P / rho^2, V, rho); w is rho in FP64 and rho - rho0 in FP32
     float4* plo; // FP32 only: compensation of (ox, oy, oz, rho - rho0)
     float4* vlo; // FP32 only: compensation of (ux, uy, uz)
 };

@@ -121,8 +121,10 @@ __device__ __forceinline__ double ufirst(double v)
 struct InstU {
     uint32_t cell_base;
     int32_t nc[3], periodic[3], cont_form, visc_form;
-    double span[3], cut2, cutl2, inv_h, wcoef, fcoef, delta2, alpha_s, g[3], rho0[2], vpair[2][2];
-    float f_cs[3], f_inv_h, f_cut2, f_cutl2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3], f_vpair[2][2];
+    int32_t umass;
+    double span[3], cut2, cutl2, inv_h, wcoef, fcoef, delta2, alpha_s, g[3], rho0[2], vpair[2][2], mass[2];
+    float f_cs[3], f_inv_h, f_cut2, f_cutl2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3], f_vpair[2][2],
+        f_mass[2];
 };
 
 __device__ __forceinline__ InstU uniform_inst(const InstDev& I)
@@ -139,6 +141,7 @@ __device__ __forceinline__ InstU uniform_inst(const InstDev& I)
     }
     u.cont_form = ufirst(I.cont_form);
     u.visc_form = ufirst(I.visc_form);
+    u.umass = ufirst(I.umass);
     u.cut2 = ufirst(I.cut2);
     u.cutl2 = ufirst(I.cutl2);
     u.inv_h = ufirst(I.inv_h);
@@ -155,6 +158,8 @@ __device__ __forceinline__ InstU uniform_inst(const InstDev& I)
     u.f_alpha_s = ufirst(I.f_alpha_s);
     for (int a = 0; a < 2; ++a) {
         u.rho0[a] = ufirst(I.rho0[a]);
+        u.mass[a] = ufirst(I.mass[a]);
+        u.f_mass[a] = ufirst(I.f_mass[a]);
         for (int b = 0; b < 2; ++b) {
             u.vpair[a][b] = ufirst(I.vpair[a][b]);
             u.f_vpair[a][b] = ufirst(I.f_vpair[a][b]);
@@ -212,13 +217,15 @@ template <> struct Lane<float> {
 // Per-row constants: the y/z cell offsets of a stencil row are fixed.
 template <class R> struct Row {
     uint32_t base;   // key of the row's first cell
-    uint32_t code;   // (delta_y + 1) << 2 | (delta_z + 1) << 4, delta = c_i - c_j
+    uint32_t code;   // 3 (delta_y + 1) + 9 (delta_z + 1), delta = c_i - c_j
     float dy, dz;    // delta_y, delta_z as floats
 };
 
-// Neighbour-list entry: particle index in the low 26 bits, the cell offset
-// delta = c_i - c_j (each component in {-1, 0, 1}, stored + 1) in the top 6 bits.
-constexpr uint32_t kIdxBits = 26, kIdxMask = (1u << kIdxBits) - 1u;
+// Neighbour-list entry: particle index j in the low 26 bits; in FP32 the cell offset
+// delta = c_i - c_j (components in {-1, 0, 1}) as (dx + 1) + 3 (dy + 1) + 9 (dz + 1) in
+// bits 26-30; the phase of j in bit 31 (phases never change, so the list carries them).
+constexpr uint32_t kIdxBits = 26, kIdxMask = (1u << kIdxBits) - 1u, kCodeMask = 31u, kPhaseShift = 31;
+__device__ __forceinline__ uint32_t entry_phase(uint32_t e) { return e >> kPhaseShift; }
 
 template <int DIM>
 __device__ __forceinline__ double dist2(double rx, double ry, double rz)
@@ -244,16 +251,11 @@ __device__ __forceinline__ double min_image(double v, const IC& I, int d)
     return v;
 }
 
-// Phase of a particle, carried in the w slot of its position record
-// (FP64: as a number; FP32: bit 31 above the cell key).
-__device__ __forceinline__ uint32_t pos_phase(const double4& p) { return (uint32_t)p.w; }
-__device__ __forceinline__ uint32_t pos_phase(const float4& p) { return __float_as_uint(p.w) >> 31; }
-
 // r_ij for a stencil candidate (FP64: absolute positions, minimal image).  Returns the
 // list-entry offset code (unused in FP64).
 template <int DIM, class IC>
 __device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<double>& L, const Row<double>&,
-                                           const double4& pj, double r[3])
+                                           const double4& pj, uint32_t, double r[3])
 {
     r[0] = min_image(L.x[0] - pj.x, I, 0);
     r[1] = min_image(L.x[1] - pj.y, I, 1);
@@ -261,17 +263,17 @@ __device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<double>& L, c
     return 0u;
 }
 
-// r_ij for a stencil candidate (FP32: cell offsets; pj.w holds j's cell key).
+// r_ij for a stencil candidate (FP32: cell offsets; keyj is j's cell key).
 template <int DIM, class IC>
 __device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<float>& L, const Row<float>& row,
-                                           const float4& pj, float r[3])
+                                           const float4& pj, uint32_t keyj, float r[3])
 {
-    int dcx = L.c[0] - (int)((__float_as_uint(pj.w) & 0x7fffffffu) - row.base);
+    int dcx = L.c[0] - (int)(keyj - row.base);
     if (I.periodic[0]) dcx = dcx > 1 ? dcx - I.nc[0] : (dcx < -1 ? dcx + I.nc[0] : dcx);
     r[0] = fmaf((float)dcx, I.f_cs[0], L.o[0] - pj.x);
     r[1] = fmaf(row.dy, I.f_cs[1], L.o[1] - pj.y);
     r[2] = DIM == 3 ? fmaf(row.dz, I.f_cs[2], L.o[2] - pj.z) : 0.0f;
-    return (uint32_t)(dcx + 1) | row.code;
+    return (uint32_t)(dcx + 1) + row.code;
 }
 
 // r_ij for a list entry e (same arithmetic as the stencil form above).
@@ -288,9 +290,14 @@ template <int DIM, class IC>
 __device__ __forceinline__ void list_pair_r(const IC& I, const Lane<float>& L, const float4& pj,
                                             uint32_t e, float r[3])
 {
-    const float dx = (float)((int)((e >> 26) & 3u) - 1);
-    const float dy = (float)((int)((e >> 28) & 3u) - 1);
-    const float dz = (float)((int)(e >> 30) - 1);
+    // c = (dx + 1) + 3 (dy + 1) + 9 (dz + 1) < 27: c / 9 = (57 c) >> 9 and, for the
+    // remainder m < 9, m / 3 = (11 m) >> 5 (exact on these ranges)
+    const uint32_t c = (e >> kIdxBits) & kCodeMask;
+    const uint32_t cz = (c * 57u) >> 9, m = c - 9u * cz;
+    const uint32_t cy = (m * 11u) >> 5, cx = m - 3u * cy;
+    const float dx = (float)((int)cx - 1);
+    const float dy = (float)((int)cy - 1);
+    const float dz = (float)((int)cz - 1);
     r[0] = fmaf(dx, I.f_cs[0], L.o[0] - pj.x);
     r[1] = fmaf(dy, I.f_cs[1], L.o[1] - pj.y);
     r[2] = DIM == 3 ? fmaf(dz, I.f_cs[2], L.o[2] - pj.z) : 0.0f;
@@ -312,16 +319,19 @@ template <class R> struct StencilBatch { static constexpr int U = 8; };
 template <> struct StencilBatch<double> { static constexpr int U = 4; };
 
 // Visit every j != i with |r_ij|^2 < cut2 among the 3^d cells around i's cell:
-// body(j, r_ij, |r_ij|^2, record of j, list code).  When P lanes share particle i,
+// body(j, r_ij, |r_ij|^2, record of j, phase of j, list code).  The candidate's cell
+// key (FP32) and phase come from the sorted key and info arrays.  When P lanes share particle i,
 // lane `sub` takes every P-th candidate of each cell run.  U candidates are loaded per
 // batch.  With ALL, the lanes of a group step through each run together and the body
 // is called for every candidate slot with a flag `in` (a candidate j != i within the
 // cutoff), so that the group can rank its accepted candidates with a ballot.
 template <class R, int DIM, int P = 1, int U = StencilBatch<R>::U, bool ALL = false, class IC, class Body>
 __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __restrict__ cstart,
-                                              const R4<R>* __restrict__ pos, uint32_t i,
+                                              const Sorted& O, const R4<R>* __restrict__ pos, uint32_t i,
                                               const Lane<R>& L, R cut2, uint32_t sub, Body&& body)
 {
+    const uint32_t* __restrict__ keys = O.key;
+    const uint32_t* __restrict__ infos = O.info;
     const int nx = I.nc[0];
     const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
@@ -336,7 +346,7 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
             else if (cy < 0 || cy >= I.nc[1]) continue;
             Row<R> row;
             row.base = I.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)I.nc[1] * (uint32_t)cz);
-            row.code = (uint32_t)(1 - dy) << 2 | (uint32_t)(1 - dz) << 4;
+            row.code = 3u * (uint32_t)(1 - dy) + 9u * (uint32_t)(1 - dz);
             row.dy = (float)(-dy);
             row.dz = (float)(-dz);
             uint32_t a0, b0, a1 = 0, b1 = 0;
@@ -365,30 +375,42 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
                     for (uint32_t kb = a; kb < b; kb += U * P) {
                         const uint32_t k0 = kb + sub;
                         R4<R> pj[U];
+                        uint32_t kj[U], fj[U];
 #pragma unroll
-                        for (int u = 0; u < U; ++u) pj[u] = pos[min(k0 + (uint32_t)(u * P), b - 1)];
+                        for (int u = 0; u < U; ++u) {
+                            const uint32_t kk = min(k0 + (uint32_t)(u * P), b - 1);
+                            pj[u] = pos[kk];
+                            kj[u] = sizeof(R) == 4 ? keys[kk] : 0u;
+                            fj[u] = infos[kk];
+                        }
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const uint32_t k = k0 + (uint32_t)(u * P);
                             R r[3];
-                            const uint32_t code = pair_r<DIM>(I, L, row, pj[u], r);
+                            const uint32_t code = pair_r<DIM>(I, L, row, pj[u], kj[u], r);
                             const R r2 = dist2<DIM>(r[0], r[1], r[2]);
-                            body(k, r, r2, pj[u], code, k < b && k != i && r2 < cut2);
+                            body(k, r, r2, pj[u], info_phase(fj[u]), code, k < b && k != i && r2 < cut2);
                         }
                     }
                 } else {
                     for (uint32_t k0 = a + sub; k0 < b; k0 += U * P) {
                         R4<R> pj[U];
+                        uint32_t kj[U], fj[U];
 #pragma unroll
-                        for (int u = 0; u < U; ++u) pj[u] = pos[min(k0 + (uint32_t)(u * P), b - 1)];
+                        for (int u = 0; u < U; ++u) {
+                            const uint32_t kk = min(k0 + (uint32_t)(u * P), b - 1);
+                            pj[u] = pos[kk];
+                            kj[u] = sizeof(R) == 4 ? keys[kk] : 0u;
+                            fj[u] = infos[kk];
+                        }
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const uint32_t k = k0 + (uint32_t)(u * P);
                             if (k < b && k != i) {
                                 R r[3];
-                                const uint32_t code = pair_r<DIM>(I, L, row, pj[u], r);
+                                const uint32_t code = pair_r<DIM>(I, L, row, pj[u], kj[u], r);
                                 const R r2 = dist2<DIM>(r[0], r[1], r[2]);
-                                if (r2 < cut2) body(k, r, r2, pj[u], code);
+                                if (r2 < cut2) body(k, r, r2, pj[u], info_phase(fj[u]), code);
                             }
                         }
                     }
@@ -406,7 +428,7 @@ struct NoExtra {};
 template <class R> struct MaxBlock { static constexpr int value = 256; };
 
 // Visit the entries of i's neighbour list with |r_ij|^2 < 4h^2 at the positions `pos`:
-// body(j, r_ij, |r_ij|^2, record of j, load(j)).  Entries are stored column-major
+// body(j, r_ij, |r_ij|^2, record of j, phase of j, load(j)).  Entries are stored column-major
 // (entry q of particle i at q * n + i), so a wave reads them coalesced; U entries are
 // fetched per batch so that their loads are in flight together.  With P lanes per
 // particle, lane `sub` takes the entries q = t P + sub: the row offset t P n is the
@@ -455,7 +477,7 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
                 R r[3];
                 list_pair_r<DIM>(I, L, pj[u], e[u], r);
                 const R r2 = dist2<DIM>(r[0], r[1], r[2]);
-                if (r2 < cut2) body(e[u] & kIdxMask, r, r2, pj[u], x[u]);
+                if (r2 < cut2) body(e[u] & kIdxMask, r, r2, pj[u], entry_phase(e[u]), x[u]);
             }
         }
     }
@@ -465,17 +487,17 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
 // The stencil fallback is rare and walks one candidate at a time: batching it would
 // raise the register count, and so lower the occupancy, of the common list path.
 template <class R, int DIM, int U, int P, class IC, class Load, class Body>
-__device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, const R4<R>* __restrict__ pos,
-                                                  uint32_t i, const Lane<R>& L, uint32_t sub, Load&& load,
-                                                  Body&& body)
+__device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, const Sorted& O,
+                                                  const R4<R>* __restrict__ pos, uint32_t i, const Lane<R>& L,
+                                                  uint32_t sub, Load&& load, Body&& body)
 {
     const uint32_t cnt = d.nbc[i];
     if (cnt <= d.cap) {
         for_list<R, DIM, U, P>(d, I, pos, i, L, cnt, sub, load, body);
     } else {
-        for_neighbors<R, DIM, P, 1>(I, d.cstart, pos, i, L, cut2_of<R>(I), sub,
-                                 [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t) {
-                                     body(k, r, r2, pj, load(k));
+        for_neighbors<R, DIM, P, 1>(I, d.cstart, O, pos, i, L, cut2_of<R>(I), sub,
+                                 [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t phj, uint32_t) {
+                                     body(k, r, r2, pj, phj, load(k));
                                  });
     }
 }
@@ -725,9 +747,7 @@ __global__ void k_gather(Dev d, int with_ref)
     if (with_ref) B.ref[k] = A.ref[src];
     const StateSet& SA = d.S[cur];
     const StateSet& SB = d.S[nxt];
-    R4<R> p = ((const R4<R>*)SA.pos)[src];
-    if constexpr (sizeof(R) == 4) p.w = __uint_as_float(key | (info_phase(A.info[src]) << 31));
-    ((R4<R>*)SB.pos)[k] = p;
+    ((R4<R>*)SB.pos)[k] = ((const R4<R>*)SA.pos)[src];
     ((R4<R>*)SB.vel)[k] = ((const R4<R>*)SA.vel)[src];
     ((R4<R>*)SB.aux)[k] = ((const R4<R>*)SA.aux)[src];
     if constexpr (sizeof(R) == 4) {
@@ -797,19 +817,19 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
     per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
         Lane<R> L;
         L.load(I, pi, O.key[i]);
-        const uint32_t ph = pos_phase(pi);
+        const uint32_t ph = info_phase(O.info[i]);
         uint32_t* nb = d.nbl + i;
         const size_t n = (size_t)d.n;
         const uint32_t cap = d.cap;
         uint32_t cnt = 0;
         bool other = false;
-        for_neighbors<R, DIM, P, StencilBatch<R>::U, true>(I, d.cstart, pos, i, L, cutl2_of<R>(I), sub,
-            [&](uint32_t k, const R*, R, const R4<R>& pj, uint32_t code, bool in) {
+        for_neighbors<R, DIM, P, StencilBatch<R>::U, true>(I, d.cstart, O, pos, i, L, cutl2_of<R>(I), sub,
+            [&](uint32_t k, const R*, R, const R4<R>&, uint32_t phj, uint32_t code, bool in) {
                 const uint32_t grp = (uint32_t)(__ballot(in) >> gbase) & gmask;
                 if (in) {
                     const uint32_t q = cnt + (uint32_t)__popc(grp & below);
-                    if (q < cap) nb[(size_t)q * n] = k | (code << kIdxBits);
-                    other |= pos_phase(pj) != ph;
+                    if (q < cap) nb[(size_t)q * n] = k | (code << kIdxBits) | (phj << kPhaseShift);
+                    other |= phj != ph;
                 }
                 cnt += (uint32_t)__popc(grp);
             });
@@ -827,8 +847,8 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
             R4<R> z;
             z.x = z.y = z.z = z.w = (R)0;
             ((R4<R>*)d.gc)[i] = z;
-            R4<R>& a = ((R4<R>*)d.S[cur].aux)[i];
-            a.z = fabs(a.z);
+            R* vw = (R*)d.S[cur].vel + 4 * (size_t)i + 3;
+            *vw = fabs(*vw);
         }
     });
 }
@@ -844,8 +864,9 @@ __device__ __forceinline__ double rho_of(const IC& I, uint32_t phase, R stored)
 }
 
 // Derived quantities of one particle from its stored density: V = m / rho into vel.w
-// and aux.z (the copy read by the renormalisation, positive: interface flag cleared),
-// m P / rho^2 into aux.y, the density itself into aux.w.
+// (positive: interface flag cleared) and aux.z (the copy read by the renormalisation),
+// m P / rho^2 into pos.w (read per neighbour by the force pass) and aux.y, the density
+// itself into aux.w.
 template <class R>
 __device__ __forceinline__ void derive_values(const InstDev& I, uint32_t phase, R stored, R m_, R& V, R& mA)
 {
@@ -858,10 +879,12 @@ __device__ __forceinline__ void derive_values(const InstDev& I, uint32_t phase, 
 }
 
 template <class R>
-__device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R stored, R4<R>& vel, R4<R>& aux)
+__device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R stored, R4<R>& pos, R4<R>& vel,
+                                           R4<R>& aux)
 {
     R V, mA;
     derive_values<R>(I, phase, stored, aux.x, V, mA);
+    pos.w = mA;
     vel.w = V;
     aux.y = mA;
     aux.z = V;
@@ -890,8 +913,9 @@ __global__ void k_derive(Dev d, int from_tmp, int force)
     const R r = from_tmp ? ((const R*)d.rho_tmp)[k] : aux.w;
     R V, mA;
     derive_values<R>(I, info_phase(info), r, aux.x, V, mA);
-    // only V (vel.w) and the aux record change: a vel load and store of the velocity
-    // itself would double this kernel's traffic and latency
+    // only m A (pos.w), V (vel.w) and the aux record change: loads and stores of the
+    // whole position and velocity records would triple this kernel's traffic
+    ((R*)S.pos)[4 * (size_t)k + 3] = mA;
     ((R*)S.vel)[4 * (size_t)k + 3] = V;
     aux.y = mA;
     aux.z = V;
@@ -951,8 +975,9 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
     const R4<R>* vel = (const R4<R>*)S.vel;
     const R4<R>* aux = (const R4<R>*)S.aux;
     const R4<R> pi = pos[i];
-    const uint32_t ph = pos_phase(pi);
-    per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
+    const uint32_t info = O.info[i];
+    const uint32_t ph = info_phase(info);
+    per_instance(d, info_inst(info), [&](const InstU& I) {
         Lane<R> L;
         L.load(I, pi, O.key[i]);
         // the self term once per particle, on its first lane
@@ -962,12 +987,12 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
         if constexpr (sizeof(R) == 8) {
             // Eq. (7) as written: sum m_j W_ij / sum (m_j / rho_j) W_ij, self included
             num = aux[i].x * w0;
-            den = vel[i].w * w0;
-            // m_j and V_j (|aux.z|: its sign is the interface flag) from one record
-            for_each_neighbor<R, DIM, 2, P>(d, I, pos, i, L, sub,
-                [&](uint32_t k) { return Pair{aux[k].x, fabs(aux[k].z)}; },
-                [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
-                    if (pos_phase(pj) != ph) return;
+            den = aux[i].z * w0;
+            // m_j and V_j (the copy in aux.z) from one record
+            for_each_neighbor<R, DIM, 2, P>(d, I, O, pos, i, L, sub,
+                [&](uint32_t k) { return Pair{aux[k].x, aux[k].z}; },
+                [&](uint32_t, const R*, R r2, const R4<R>&, uint32_t phj, const Pair& x) {
+                    if (phj != ph) return;
                     const R w = kernel_w<R>(I, r2);
                     num += x.a * w;
                     den += x.b * w;
@@ -975,16 +1000,16 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
         } else {
             // the same quotient minus rho0, as a V_j W_ij-weighted mean of (rho_j - rho0):
             // m_j - rho0 V_j = V_j (rho_j - rho0), so nothing cancels in FP32
-            num = vel[i].w * w0 * aux[i].w;
-            den = vel[i].w * w0;
-            // (V_j, rho_j - rho0) as one 8-byte load of aux.zw (|aux.z| = V_j)
-            for_each_neighbor<R, DIM, 4, P>(d, I, pos, i, L, sub,
+            num = aux[i].z * w0 * aux[i].w;
+            den = aux[i].z * w0;
+            // (V_j, rho_j - rho0) as one 8-byte load of aux.zw
+            for_each_neighbor<R, DIM, 4, P>(d, I, O, pos, i, L, sub,
                 [&](uint32_t k) {
                     const float2 zw = *(const float2*)&aux[k].z;
-                    return Pair{fabsf(zw.x), zw.y};
+                    return Pair{zw.x, zw.y};
                 },
-                [&](uint32_t, const R*, R r2, const R4<R>& pj, const Pair& x) {
-                    if (pos_phase(pj) != ph) return;
+                [&](uint32_t, const R*, R r2, const R4<R>&, uint32_t phj, const Pair& x) {
+                    if (phj != ph) return;
                     const R vw = x.a * kernel_w<R>(I, r2);
                     num += vw * x.b;
                     den += vw;
@@ -1016,20 +1041,20 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
     const Sorted& O = d.O[cur];
     const StateSet& S = star ? d.star : d.S[cur];
     R4<R>* gc = (R4<R>*)d.gc;
-    R4<R>* aux = (R4<R>*)S.aux;
     const R4<R>* pos = (const R4<R>*)S.pos;
-    const R4<R>* vel = (const R4<R>*)S.vel;
+    R4<R>* vel = (R4<R>*)S.vel;
     for (uint32_t g = t / P; g < count; g += stride) {
         const uint32_t i = d.ilist[g];
         const R4<R> pi = pos[i];
-        const uint32_t ph = pos_phase(pi);
+        const uint32_t info = O.info[i];
+        const uint32_t ph = info_phase(info);
         R s[3] = {0, 0, 0};
-        per_instance(d, info_inst(O.info[i]), [&](const InstU& I) {
+        per_instance(d, info_inst(info), [&](const InstU& I) {
             Lane<R> L;
             L.load(I, pi, O.key[i]);
-            for_each_neighbor<R, DIM, kColourBatch, P>(d, I, pos, i, L, sub, [](uint32_t) { return NoExtra{}; },
-                [&](uint32_t k, const R* r, R r2, const R4<R>& pj, NoExtra) {
-                    if (pos_phase(pj) == ph) return;             // C_j^y = 1 only for the other phase
+            for_each_neighbor<R, DIM, kColourBatch, P>(d, I, O, pos, i, L, sub, [](uint32_t) { return NoExtra{}; },
+                [&](uint32_t k, const R* r, R r2, const R4<R>&, uint32_t phj, NoExtra) {
+                    if (phj == ph) return;                       // C_j^y = 1 only for the other phase
                     const R vk = vel[k].w;                       // 1 / sigma_k
                     const R f = kernel_f<R>(I, r2) * (vk * vk);
                     s[0] += f * r[0];
@@ -1037,7 +1062,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
                     s[2] += f * r[2];
                 });
         });
-        const R vi = vel[i].w;                                   // sigma_i = 1 / V_i
+        const R vi = fabs(vel[i].w);                             // sigma_i = 1 / V_i
         R g3[3];
         g3[0] = group_sum<P>(s[0]) / vi;
         g3[1] = group_sum<P>(s[1]) / vi;
@@ -1047,8 +1072,8 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
             R4<R> out;
             out.x = g3[0]; out.y = g3[1]; out.z = g3[2]; out.w = gn;
             gc[i] = out;
-            const R v = fabs(aux[i].z);
-            aux[i].z = gn > 0 ? -v : v;       // interface flag: the sign of the V copy
+            R* vw = (R*)vel + 4 * (size_t)i + 3;
+            *vw = gn > 0 ? -vi : vi;          // interface flag: the sign of V in the velocity record
         }
     }
 }
@@ -1088,13 +1113,14 @@ template <class R, int DIM> struct ForceLane {
     __device__ __forceinline__ void init(const IC& I, uint32_t info_, const R4<R>& vi_, const R4<R>& xi,
                                          const R4<R>* __restrict__ gc, uint32_t i)
     {
+        // vi_ = (u_i, +-V_i), the sign of V being the interface flag; xi = (m_i, m_i A_i)
         info = info_;
         ph = info_phase(info);
         fluid = info_kind(info) == K_FLUID;
         vi = vi_;
         mi = xi.x;
         Ai = xi.y / mi;                          // P_i / rho_i^2
-        fli = xi.z < (R)0;                       // interface flag (sign of the V copy)
+        fli = vi_.w < (R)0;                      // interface flag
         alpha = sizeof(R) == 8 ? (R)I.alpha_s : (R)I.f_alpha_s;
         gi[0] = gi[1] = gi[2] = 0;
         ci = 0;
@@ -1121,26 +1147,27 @@ template <class R, int DIM> struct ForceLane {
         cnt = 0;
     }
 
-    // One neighbour j = k with r_ij, |r_ij|^2 < 4h^2, position record pj, velocity
-    // record vk = (u_j, V_j) and aux record xk = (m_j, m_j A_j, +-V_j, rho_j); the sign
-    // of xk.z is j's interface flag.
+    // One neighbour j = k with r_ij, |r_ij|^2 < 4h^2, position record pj = (x_j, m_j A_j),
+    // phase phj, velocity record vk = (u_j, +-V_j), the sign of V_j being j's interface
+    // flag, and mass mj.
     template <class IC>
     __device__ __forceinline__ void pair(const IC& I, const R4<R>* __restrict__ gc, uint32_t k, const R* r,
-                                         R r2, const R4<R>& pj, const R4<R>& vk, const R4<R>& xk)
+                                         R r2, const R4<R>& pj, uint32_t phj, const R4<R>& vk, R mj)
     {
         ++cnt;
         const R F = kernel_f<R>(I, r2);
         const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
         const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
         const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
-        cont += (massform ? xk.x : vk.w) * udw;                   // Eq. (6) / (5)
+        const R Vj = fabs(vk.w);
+        cont += (massform ? mj : Vj) * udw;                       // Eq. (6) / (5)
         if (!fluid) return;
-        const R pc = xk.x * Ai + xk.y;                            // m_j (A_i + A_j)
+        const R pc = mj * Ai + pj.w;                              // m_j (A_i + A_j)
         ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
         const R lap = (F * r2) * frcp(r2 + delta2);               // r.gradW / (r^2 + delta^2)
-        const R cv = vk.w * (pos_phase(pj) ? vp1 : vp0) * lap;
+        const R cv = Vj * (phj ? vp1 : vp0) * lap;
         av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
-        const bool flk = xk.z < (R)0;
+        const bool flk = vk.w < (R)0;
         if (fli || flk) {
             R t[3];
             if (fli) {
@@ -1257,11 +1284,23 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
             L.load(I, pi, O.key[i]);
             ForceLane<R, DIM> F;
             F.init(I, info, vel[i], aux[i], gc, i);
-            struct VA { R4<R> v, a; };
-            for_each_neighbor<R, DIM, ForceBatch<R>::U, P>(d, I, pos, i, L, sub,
-                [&](uint32_t k) { return VA{vel[k], aux[k]}; },
-                [&](uint32_t k, const R* r, R r2, const R4<R>& pj, const VA& x) {
-                    F.pair(I, gc, k, r, r2, pj, x.v, x.a);
+            // per neighbour: the position record (x_j, m_j A_j) and the velocity record
+            // (u_j, +-V_j); m_j from the per-phase table when the instance's masses are
+            // uniform per phase, else from the aux record
+            const bool umass = I.umass != 0;
+            R m0, m1;
+            if constexpr (sizeof(R) == 8) { m0 = I.mass[0]; m1 = I.mass[1]; }
+            else { m0 = I.f_mass[0]; m1 = I.f_mass[1]; }
+            struct VM { R4<R> v; R m; };
+            for_each_neighbor<R, DIM, ForceBatch<R>::U, P>(d, I, O, pos, i, L, sub,
+                [&](uint32_t k) {
+                    VM x;
+                    x.v = vel[k];
+                    x.m = umass ? (R)0 : aux[k].x;
+                    return x;
+                },
+                [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t phj, const VM& x) {
+                    F.pair(I, gc, k, r, r2, pj, phj, x.v, umass ? (phj ? m1 : m0) : x.m);
                 });
             nint = F.cnt;
             F.template finish<P, REDUCE, TERMS>(d, I, i, sub, aux[i].w, umag2, amag2);
@@ -1377,7 +1416,7 @@ __global__ void k_predict(Dev d)
         moving_state<R>(I, O.ref[k], O.key[k], d.run[b].t + hdt, p, v);
     }
     const R r = x.w + h * a.w;
-    derive_one<R>(I, info_phase(info), r, v, x);
+    derive_one<R>(I, info_phase(info), r, p, v, x);
     ((R4<R>*)d.star.pos)[k] = p;
     ((R4<R>*)d.star.vel)[k] = v;
     ((R4<R>*)d.star.aux)[k] = x;
@@ -1434,7 +1473,7 @@ __device__ __forceinline__ double correct_one(const Dev& d, int cur, uint32_t k,
     bad = !isfinite((double)p.x) || !isfinite((double)p.y) || !isfinite((double)p.z) ||
           !isfinite((double)v.x) || !isfinite((double)v.y) || !isfinite((double)v.z) || !isfinite((double)r);
     if (bad) atomicOr(d.status, ST_NONFINITE);
-    derive_one<R>(I, info_phase(info), r, v, x);
+    derive_one<R>(I, info_phase(info), r, p, v, x);
     ((R4<R>*)S.pos)[k] = p;
     ((R4<R>*)S.vel)[k] = v;
     ((R4<R>*)S.aux)[k] = x;
@@ -1481,8 +1520,8 @@ __global__ void k_export(Dev d, int pass, const uint32_t* __restrict__ off, uint
     uint32_t c = 0;
     const uint32_t base = pass ? off[i] : 0;
     // the same neighbour walk as the physics passes
-    for_each_neighbor<R, DIM, 4, 1>(d, I, pos, i, L, 0u, [](uint32_t) { return NoExtra{}; },
-        [&](uint32_t k, const R*, R, const R4<R>&, NoExtra) {
+    for_each_neighbor<R, DIM, 4, 1>(d, I, O, pos, i, L, 0u, [](uint32_t) { return NoExtra{}; },
+        [&](uint32_t k, const R*, R, const R4<R>&, uint32_t, NoExtra) {
             if (pass) out[base + c] = O.id[k];
             ++c;
         });

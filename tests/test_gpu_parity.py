@@ -35,8 +35,17 @@ def periodic_drop(dim, n=24, seed=11):
     return s
 
 
+def jitter_mass(s, seed=21, amp=0.01):
+    """Per-particle masses m (1 + U[-amp, amp]): no instance has one mass per phase."""
+    rng = np.random.default_rng(seed)
+    s.m = s.m * (1 + rng.uniform(-amp, amp, s.n))
+    return s
+
+
 SCENES = {
     "drop2d": lambda: inputs.drop2d(perturb=True),
+    "drop2d_varmass": lambda: jitter_mass(inputs.drop2d(perturb=True)),
+    "drop3d_varmass": lambda: jitter_mass(inputs.drop3d(scale=0.3, perturb=True)),
     "drop3d_small": lambda: inputs.drop3d(scale=0.3, perturb=True),
     "periodic2d": lambda: periodic_drop(2),
     "periodic3d": lambda: periodic_drop(3, 14),
@@ -132,7 +141,7 @@ def _one_step(scene, prec, nsteps=1, lanes=1):
 
 @pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("prec", PRECS)
-@pytest.mark.parametrize("name", ["drop2d", "drop3d_small", "periodic3d", "drop2d_eq11_eq5"])
+@pytest.mark.parametrize("name", ["drop2d", "drop3d_small", "periodic3d", "drop2d_eq11_eq5", "drop2d_varmass"])
 def test_one_step_matches_oracle(name, prec, lanes):
     s = SCENES[name]()
     print(f"case step {name} precision={prec} lanes={lanes} n={s.n}", flush=True)
@@ -191,6 +200,42 @@ def test_checkpoint_round_trip_is_bit_identical(prec):
     for f in (binding.F_X, binding.F_U, binding.F_RHO):
         assert np.array_equal(a.get_field(f), c.get_field(f))
     assert a.stats()["steps"] == c.stats()["steps"] == 8
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_restored_state_brings_its_own_masses(prec):
+    # a context set up with one mass per phase takes a checkpoint whose masses vary per
+    # particle: it must then step exactly as the context that wrote the checkpoint
+    s = inputs.drop2d(perturb=True)
+    v = jitter_mass(inputs.drop2d(perturb=True))
+    a = binding.Sim(v, precision=prec)
+    a.step(2)
+    blob = a.get_state()
+    a.step(3)
+    b = binding.Sim(s, precision=prec)
+    b.set_state(blob)
+    b.step(3)
+    for f in (binding.F_X, binding.F_U, binding.F_RHO):
+        assert np.array_equal(a.get_field(f), b.get_field(f))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_batched_instances_with_and_without_one_mass_per_phase(prec):
+    # instance 1 has per-particle masses, instances 0 and 2 one mass per phase
+    parts = [inputs.drop2d(perturb=True, dx=dx) for dx in (2.5e-3, 3.3e-3, 4e-3)]
+    jitter_mass(parts[1])
+    scene = inputs.concat("batch_mass", parts)
+    sim = binding.Sim(scene, precision=prec)
+    sim.step(2)
+    sim.sync()
+    x = sim.get_field(binding.F_X)
+    rho = sim.get_field(binding.F_RHO)
+    for b, part in enumerate(parts):
+        o = oracle.Oracle(part)
+        o.step(2)
+        a, e = scene.inst_offsets[b], scene.inst_offsets[b + 1]
+        assert rel_to(x[a:e], o.get(oracle.X), part.dx[0]) < TOL[prec]
+        assert rel_to(rho[a:e], o.get(oracle.RHO), 1000.0) < TOL[prec]
 
 
 @pytest.mark.parametrize("prec", PRECS)
