@@ -240,7 +240,7 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.status = c.take<uint32_t>(1);
     d.inter = c.take<unsigned long long>(1);
     d.curp = c.take<int>(1);
-    d.flags = c.take<uint32_t>(2);
+    d.flags = c.take<uint32_t>(4);
     d.cnt = c.take<uint32_t>(ncell);
     d.cstart = c.take<uint32_t>((size_t)ncell + 1);
     d.scan_tmp = c.take<uint32_t>((ncell + 2047) / 2048 + 1);
@@ -421,7 +421,7 @@ struct BlobHeader {
     uint64_t magic;
     int32_t precision, dim, ninst, cur;
     int64_t n;
-    uint32_t ncell, rates_valid, cap, pad;
+    uint32_t ncell, rates_valid, cap, qpos;   // qpos: device flag 2 (pos.w holds q)
 };
 constexpr uint64_t kMagic = 0x5350485853543034ull;   // "SPHXST04"
 
@@ -707,7 +707,8 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
         d.O[1].ref = tmp.O[1].ref;
     }
     const int zero = 0;
-    const uint32_t flags[2] = {0u, 1u};          // the first build is requested
+    // the first build is requested; the set-up derive leaves q in pos.w
+    const uint32_t flags[3] = {0u, 1u, 1u};
     HIP_OK(c, hipMemcpyAsync(d.curp, &zero, sizeof zero, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(d.flags, flags, sizeof flags, hipMemcpyHostToDevice, s));
     launch_derive(d, c->launch, s);
@@ -747,6 +748,7 @@ sphx_status sphx_compute_forces(sphx_ctx* c)
     if (!c) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
     enqueue_build(c);
+    launch_restore(c->dev, c->stream);   // m P / rho^2 into pos.w, wherever q was left there
     enqueue_rates(c, false, true);
     c->rates_valid = true;
     HIP_OK(c, hipGetLastError());
@@ -1051,8 +1053,10 @@ sphx_status sphx_get_state(sphx_ctx* c, void* blob, size_t cap, size_t* need)
     *need = total;
     if (!blob || cap < total) return SPHX_OK;
     const sphx_status st = status_of(c);
+    uint32_t qpos = 0;
+    HIP_OK(c, hipMemcpy(&qpos, c->dev.flags + 2, sizeof qpos, hipMemcpyDeviceToHost));
     BlobHeader h{kMagic, c->precision, c->dim, c->ninst, cur, c->n, c->ncell, (uint32_t)c->rates_valid,
-                 c->dev.cap, 0};
+                 c->dev.cap, qpos};
     char* p = (char*)blob;
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
@@ -1114,7 +1118,7 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
     }
     HIP_OK(c, hipMemcpy((void*)c->dev.inst, c->inst.data(), sizeof(InstDev) * c->ninst, hipMemcpyHostToDevice));
     const int cur = h.cur;
-    const uint32_t flags[2] = {0u, 0u};
+    const uint32_t flags[3] = {0u, 0u, h.qpos ? 1u : 0u};
     HIP_OK(c, hipMemcpy(c->dev.curp, &cur, sizeof cur, hipMemcpyHostToDevice));
     HIP_OK(c, hipMemcpy(c->dev.flags, flags, sizeof flags, hipMemcpyHostToDevice));
     HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * 4));

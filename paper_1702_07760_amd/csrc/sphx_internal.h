@@ -58,7 +58,8 @@ struct InstRun {
 
 // One copy of the cell-sorted particle state.
 struct StateSet {
-    void* pos;   // R4: FP64 (x, y, z, m P / rho^2); FP32 (ox, oy, oz, m P / rho^2)
+    void* pos;   // R4: FP64 (x, y, z, w); FP32 (ox, oy, oz, w); w = m P / rho^2 during rate
+                 //     evaluations, q = (rho - rho0) / rho from a state update to Eq. (7)
     void* vel;   // R4: (ux, uy, uz, +-V), V = m / rho; the sign of w is the interface flag
     void* aux;   // R4: (m, m P / rho^2, V, rho); w is rho in FP64 and rho - rho0 in FP32
     float4* plo; // FP32 only: compensation of (ox, oy, oz, rho - rho0)
@@ -83,7 +84,8 @@ struct Dev {
     uint32_t* status;
     unsigned long long* inter;
     int* curp;           // which state set (0/1) holds the current sorted state
-    uint32_t* flags;     // [0] rebuild in this step, [1] rebuild requested by the host
+    uint32_t* flags;     // [0] rebuild in this step, [1] rebuild requested by the host,
+                         // [2] pos.w holds q = (rho - rho0) / rho rather than m P / rho^2
     // build scratch
     uint32_t* cnt;       // ncell
     uint32_t* cstart;    // ncell + 1
@@ -131,6 +133,7 @@ void launch_predict(const Dev& d, const Launch& L, hipStream_t s);
 void launch_correct(const Dev& d, const Launch& L, hipStream_t s);
 void launch_finish(const Dev& d, hipStream_t s);
 void launch_derive(const Dev& d, const Launch& L, hipStream_t s);
+void launch_restore(const Dev& d, hipStream_t s);
 // neighbour export: counts (pass 0) or ids (pass 1) in sorted order
 void launch_export(const Dev& d, int pass, const uint32_t* off, uint32_t* out,
                    const Launch& L, hipStream_t s);

@@ -865,8 +865,11 @@ __device__ __forceinline__ double rho_of(const IC& I, uint32_t phase, R stored)
 
 // Derived quantities of one particle from its stored density: V = m / rho into vel.w
 // (positive: interface flag cleared) and aux.z (the copy read by the renormalisation),
-// m P / rho^2 into pos.w (read per neighbour by the force pass) and aux.y, the density
-// itself into aux.w.
+// m P / rho^2 into aux.y, the density itself into aux.w.  The w slot of the position
+// record holds m P / rho^2 while rates are evaluated (the force pass reads it per
+// neighbour); from a state update to the next Eq. (7) it holds q = (rho - rho0) / rho
+// instead, the one number per neighbour that Eq. (7) needs when masses are uniform
+// per phase (device flag 2 says which).
 template <class R>
 __device__ __forceinline__ void derive_values(const InstDev& I, uint32_t phase, R stored, R m_, R& V, R& mA)
 {
@@ -879,12 +882,20 @@ __device__ __forceinline__ void derive_values(const InstDev& I, uint32_t phase, 
 }
 
 template <class R>
+__device__ __forceinline__ R q_of(const InstDev& I, uint32_t phase, R stored)
+{
+    const double rho = rho_of<R>(I, phase, stored);
+    const double dr = sizeof(R) == 8 ? rho - I.rho0[phase] : (double)stored;
+    return (R)(dr / rho);
+}
+
+template <class R>
 __device__ __forceinline__ void derive_one(const InstDev& I, uint32_t phase, R stored, R4<R>& pos, R4<R>& vel,
-                                           R4<R>& aux)
+                                           R4<R>& aux, bool qfield)
 {
     R V, mA;
     derive_values<R>(I, phase, stored, aux.x, V, mA);
-    pos.w = mA;
+    pos.w = qfield ? q_of<R>(I, phase, stored) : mA;
     vel.w = V;
     aux.y = mA;
     aux.z = V;
@@ -899,30 +910,40 @@ __device__ __forceinline__ bool renorm_due(const Dev& d)
     return e > 0 && d.run[0].step % e == 0;
 }
 
+// mode 0 (set-up): derive from the stored density, q into pos.w.
+// mode 1 (after Eq. (7)): derive from the renormalised density when Eq. (7) ran, else
+//   only put m P / rho^2 back into pos.w.
+// mode 2: only put m P / rho^2 back into pos.w (before rates outside a full step).
+// Modes 1 and 2 clear flag 2 (pos.w holds q); the host sets it after mode 0.
 template <class R>
-__global__ void k_derive(Dev d, int from_tmp, int force)
+__global__ void k_derive(Dev d, int mode, int force)
 {
-    if (from_tmp && !force && !renorm_due(d)) return;
     const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0 && mode != 0) d.flags[2] = 0u;
     if (k >= d.n) return;
+    const StateSet& S = d.S[cur];
+    const bool fresh = mode == 1 && (force || renorm_due(d));
+    if (mode != 0 && !fresh) {
+        ((R*)S.pos)[4 * (size_t)k + 3] = ((const R*)S.aux)[4 * (size_t)k + 1];
+        return;
+    }
     const uint32_t info = d.O[cur].info[k];
     const InstDev& I = d.inst[info_inst(info)];
-    const StateSet& S = d.S[cur];
     R4<R> aux = ((R4<R>*)S.aux)[k];
-    const R r = from_tmp ? ((const R*)d.rho_tmp)[k] : aux.w;
+    const R r = fresh ? ((const R*)d.rho_tmp)[k] : aux.w;
     R V, mA;
     derive_values<R>(I, info_phase(info), r, aux.x, V, mA);
-    // only m A (pos.w), V (vel.w) and the aux record change: loads and stores of the
-    // whole position and velocity records would triple this kernel's traffic
-    ((R*)S.pos)[4 * (size_t)k + 3] = mA;
+    // only pos.w, V (vel.w) and the aux record change: loads and stores of the whole
+    // position and velocity records would triple this kernel's traffic
+    ((R*)S.pos)[4 * (size_t)k + 3] = mode == 0 ? q_of<R>(I, info_phase(info), r) : mA;
     ((R*)S.vel)[4 * (size_t)k + 3] = V;
     aux.y = mA;
     aux.z = V;
     aux.w = r;
     ((R4<R>*)S.aux)[k] = aux;
     if constexpr (sizeof(R) == 4)
-        if (from_tmp) S.plo[k].w = 0.0f;   // a fresh value: no carried error
+        if (fresh) S.plo[k].w = 0.0f;   // a fresh value: no carried error
 }
 
 // -------------------------------------------------------- Eq. (7) renormalise
@@ -977,11 +998,35 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
     const R4<R> pi = pos[i];
     const uint32_t info = O.info[i];
     const uint32_t ph = info_phase(info);
+    const bool qpos = d.flags[2] != 0u;   // pos.w holds q = (rho - rho0) / rho
     per_instance(d, info_inst(info), [&](const InstU& I) {
         Lane<R> L;
         L.load(I, pi, O.key[i]);
         // the self term once per particle, on its first lane
         const R w0 = sub == 0 ? kernel_w<R>(I, (R)0) : (R)0;
+        const double rho0 = ph ? I.rho0[1] : I.rho0[0];
+        if (qpos && I.umass) {
+            // every j in the sums has i's phase and so i's mass m: Eq. (7) becomes
+            // sum W / sum (W / rho_j) = rho0 S / (S - Q) with S = sum W_ij and
+            // Q = sum W_ij q_j, since 1 / rho_j = (1 - q_j) / rho0; one record per neighbour
+            R sw = w0, sq = w0 * pi.w;
+            for_each_neighbor<R, DIM, sizeof(R) == 8 ? 2 : 4, P>(d, I, O, pos, i, L, sub,
+                [](uint32_t) { return NoExtra{}; },
+                [&](uint32_t, const R*, R r2, const R4<R>& pj, uint32_t phj, NoExtra) {
+                    if (phj != ph) return;
+                    const R w = kernel_w<R>(I, r2);
+                    sw += w;
+                    sq += w * pj.w;
+                });
+            sw = group_sum<P>(sw);
+            sq = group_sum<P>(sq);
+            if (sub == 0) {
+                const double S = sw, Q = sq;
+                // FP32 stores rho - rho0 = rho0 Q / (S - Q)
+                ((R*)d.rho_tmp)[i] = sizeof(R) == 8 ? (R)(rho0 * S / (S - Q)) : (R)(rho0 * Q / (S - Q));
+            }
+            return;
+        }
         struct Pair { R a, b; };
         R num, den;
         if constexpr (sizeof(R) == 8) {
@@ -1338,6 +1383,7 @@ __global__ void k_dt(Dev d, double dt_override)
 __global__ void k_finish(Dev d)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b == 0) d.flags[2] = 1u;   // the corrector left q in pos.w
     if (b >= d.ninst) return;
     d.run[b].t = d.run[b].t_next;
     d.run[b].step += 1;
@@ -1416,7 +1462,7 @@ __global__ void k_predict(Dev d)
         moving_state<R>(I, O.ref[k], O.key[k], d.run[b].t + hdt, p, v);
     }
     const R r = x.w + h * a.w;
-    derive_one<R>(I, info_phase(info), r, p, v, x);
+    derive_one<R>(I, info_phase(info), r, p, v, x, false);
     ((R4<R>*)d.star.pos)[k] = p;
     ((R4<R>*)d.star.vel)[k] = v;
     ((R4<R>*)d.star.aux)[k] = x;
@@ -1473,7 +1519,7 @@ __device__ __forceinline__ double correct_one(const Dev& d, int cur, uint32_t k,
     bad = !isfinite((double)p.x) || !isfinite((double)p.y) || !isfinite((double)p.z) ||
           !isfinite((double)v.x) || !isfinite((double)v.y) || !isfinite((double)v.z) || !isfinite((double)r);
     if (bad) atomicOr(d.status, ST_NONFINITE);
-    derive_one<R>(I, info_phase(info), r, p, v, x);
+    derive_one<R>(I, info_phase(info), r, p, v, x, true);
     ((R4<R>*)S.pos)[k] = p;
     ((R4<R>*)S.vel)[k] = v;
     ((R4<R>*)S.aux)[k] = x;
@@ -1597,6 +1643,13 @@ void launch_derive(const Dev& d, const Launch&, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
         hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, 0, 0);
+    }));
+}
+
+void launch_restore(const Dev& d, hipStream_t s)
+{
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        hipLaunchKernelGGL((k_derive<R>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, 2, 0);
     }));
 }
 

@@ -203,6 +203,24 @@ def test_checkpoint_round_trip_is_bit_identical(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["drop2d", "drop3d_small", "periodic3d"])
+def test_both_forms_of_eq7_match_the_oracle(name, prec, oracle_rates):
+    # right after set-up the renormalisation reads q = (rho - rho0) / rho from the
+    # position record (one record per neighbour, masses uniform per phase); after a rate
+    # evaluation it reads m_j and V_j from the aux record instead.  Both are Eq. (7).
+    s, ref, _ = oracle_rates(name)
+    a = binding.Sim(s, precision=prec)
+    a.renormalize_density()
+    b = binding.Sim(s, precision=prec)
+    b.compute_forces()
+    b.renormalize_density()
+    rho0 = max(p[0] for p in s.phases[0])
+    ra, rb = a.get_field(binding.F_RHO), b.get_field(binding.F_RHO)
+    assert rel_to(ra, ref[oracle.RHO], rho0) < TOL[prec]
+    assert rel_to(rb, ref[oracle.RHO], rho0) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_restored_state_brings_its_own_masses(prec):
     # a context set up with one mass per phase takes a checkpoint whose masses vary per
     # particle: it must then step exactly as the context that wrote the checkpoint
