@@ -363,13 +363,11 @@ void enqueue_integrate(sphx_ctx* c, double dt_override)
 {
     {
         Timed t(c, SPHX_PH_INTEGRATE);
-        launch_dt(c->dev, dt_override, c->stream);
-        launch_predict(c->dev, c->launch, c->stream);
+        launch_predict(c->dev, dt_override, c->launch, c->stream);   // a9 inside
     }
     enqueue_rates(c, true, false);
     Timed t(c, SPHX_PH_INTEGRATE);
-    launch_correct(c->dev, c->launch, c->stream);
-    launch_finish(c->dev, c->stream);
+    launch_correct(c->dev, c->launch, c->stream);   // ends the step
 }
 
 void enqueue_renorm(sphx_ctx* c, bool force)

@@ -128,10 +128,8 @@ void launch_nlist(const Dev& d, const Launch& L, hipStream_t s);     // list of 
 void launch_renorm(const Dev& d, bool force, const Launch& L, hipStream_t s);
 void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s);
 void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hipStream_t s);
-void launch_dt(const Dev& d, double dt_fixed_override, hipStream_t s);
-void launch_predict(const Dev& d, const Launch& L, hipStream_t s);
+void launch_predict(const Dev& d, double dt_override, const Launch& L, hipStream_t s);   // with a9
 void launch_correct(const Dev& d, const Launch& L, hipStream_t s);
-void launch_finish(const Dev& d, hipStream_t s);
 void launch_derive(const Dev& d, const Launch& L, hipStream_t s);
 void launch_restore(const Dev& d, hipStream_t s);
 // neighbour export: counts (pass 0) or ids (pass 1) in sorted order

@@ -17,6 +17,7 @@
 #include "sphx_internal.h"
 
 #include <math.h>
+#include <type_traits>
 
 namespace sphx {
 
@@ -1332,21 +1333,27 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
             // per neighbour: the position record (x_j, m_j A_j) and the velocity record
             // (u_j, +-V_j); m_j from the per-phase table when the instance's masses are
             // uniform per phase, else from the aux record
-            const bool umass = I.umass != 0;
             R m0, m1;
             if constexpr (sizeof(R) == 8) { m0 = I.mass[0]; m1 = I.mass[1]; }
             else { m0 = I.f_mass[0]; m1 = I.f_mass[1]; }
             struct VM { R4<R> v; R m; };
-            for_each_neighbor<R, DIM, ForceBatch<R>::U, P>(d, I, O, pos, i, L, sub,
-                [&](uint32_t k) {
-                    VM x;
-                    x.v = vel[k];
-                    x.m = umass ? (R)0 : aux[k].x;
-                    return x;
-                },
-                [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t phj, const VM& x) {
-                    F.pair(I, gc, k, r, r2, pj, phj, x.v, umass ? (phj ? m1 : m0) : x.m);
-                });
+            // one loop per case, so that the walk carries no per-neighbour branch on it
+            auto walk = [&](auto uniform) {
+                constexpr bool UM = decltype(uniform)::value;
+                for_each_neighbor<R, DIM, ForceBatch<R>::U, P>(d, I, O, pos, i, L, sub,
+                    [&](uint32_t k) {
+                        VM x;
+                        x.v = vel[k];
+                        if constexpr (UM) x.m = (R)0;
+                        else x.m = aux[k].x;
+                        return x;
+                    },
+                    [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t phj, const VM& x) {
+                        F.pair(I, gc, k, r, r2, pj, phj, x.v, UM ? (phj ? m1 : m0) : x.m);
+                    });
+            };
+            if (I.umass) walk(std::true_type{});
+            else walk(std::false_type{});
             nint = F.cnt;
             F.template finish<P, REDUCE, TERMS>(d, I, i, sub, aux[i].w, umag2, amag2);
         });
@@ -1356,13 +1363,14 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
 
 // ----------------------------------------------------------- time step (a9)
 
-__global__ void k_dt(Dev d, double dt_override)
+// The time step of instance b from the maxima of the last rate evaluation at S^n (or
+// the override / fixed value).  Every thread that asks gets the same value: the same
+// arithmetic on the same inputs.
+__device__ __forceinline__ double step_dt(const Dev& d, uint32_t b, double dt_override, double& umax)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= d.ninst) return;
     const InstDev& I = d.inst[b];
-    InstRun& R = d.run[b];
-    const double umax = sqrt(__longlong_as_double((long long)R.umax2));
+    const InstRun& R = d.run[b];
+    umax = sqrt(__longlong_as_double((long long)R.umax2));
     const double amax = sqrt(__longlong_as_double((long long)R.amax2));
     double dt;
     if (dt_override > 0.0) dt = dt_override;
@@ -1373,20 +1381,34 @@ __global__ void k_dt(Dev d, double dt_override)
         dt = fmin(dt, I.dt_const);
         if (umax > 0.0) dt = fmin(dt, 0.5 * I.skin / umax);
     }
-    // the corrector reuses the cells of S^n: every pair within 2h at the predicted
-    // positions must still lie in neighbouring cells
-    if (dt * umax > 0.5 * I.skin * (1.0 + 1e-12) || !(dt > 0.0)) atomicOr(d.status, ST_DT);
-    R.dt = dt;
-    R.t_next = R.t + dt;
+    return dt;
 }
 
-__global__ void k_finish(Dev d)
+// Store each instance's step (grid-stride over instances; run by the predictor).
+__device__ __forceinline__ void store_steps(const Dev& d, double dt_override)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b == 0) d.flags[2] = 1u;   // the corrector left q in pos.w
-    if (b >= d.ninst) return;
-    d.run[b].t = d.run[b].t_next;
-    d.run[b].step += 1;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < (uint32_t)d.ninst; b += stride) {
+        double umax;
+        const double dt = step_dt(d, b, dt_override, umax);
+        // the corrector reuses the cells of S^n: every pair within 2h at the predicted
+        // positions must still lie in neighbouring cells
+        if (dt * umax > 0.5 * d.inst[b].skin * (1.0 + 1e-12) || !(dt > 0.0)) atomicOr(d.status, ST_DT);
+        d.run[b].dt = dt;
+        d.run[b].t_next = d.run[b].t + dt;
+    }
+}
+
+// End of a step (grid-stride over instances; run by the corrector, whose particle
+// updates read dt and t_next only).
+__device__ __forceinline__ void finish_steps(const Dev& d)
+{
+    const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+    if (t0 == 0) d.flags[2] = 1u;   // the corrector leaves q in pos.w
+    for (uint32_t b = t0; b < (uint32_t)d.ninst; b += stride) {
+        d.run[b].t = d.run[b].t_next;
+        d.run[b].step += 1;
+    }
 }
 
 // -------------------------------------------------------- integrator (a10)
@@ -1432,8 +1454,9 @@ __device__ __forceinline__ void kahan_add(float& s, float& e, float y)
 
 // S* = S^n + dt/2 R(S^n)
 template <class R, int DIM>
-__global__ void k_predict(Dev d)
+__global__ void k_predict(Dev d, double dt_override)
 {
+    store_steps(d, dt_override);
     const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n) return;
@@ -1442,7 +1465,8 @@ __global__ void k_predict(Dev d)
     const uint32_t info = O.info[k];
     const uint32_t b = info_inst(info);
     const InstDev& I = d.inst[b];
-    const double hdt = 0.5 * d.run[b].dt;
+    double umax;
+    const double hdt = 0.5 * step_dt(d, b, dt_override, umax);
     const uint32_t kind = info_kind(info);
     R4<R> p = ((const R4<R>*)S.pos)[k];
     R4<R> v = ((const R4<R>*)S.vel)[k];
@@ -1535,6 +1559,7 @@ __global__ void k_correct(Dev d)
 {
     const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    finish_steps(d);
     const bool valid = k < d.n;
     double moved2 = 0.0;
     uint32_t b = 0;
@@ -1593,7 +1618,9 @@ static void build_impl(const Dev& d, const Launch& L, hipStream_t s)
     hipLaunchKernelGGL(k_rank, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
     hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, d.O[0].ref ? 1 : 0);
     hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d);
-    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n * kNlistLanes, L.block)), dim3(L.block), 0, s, d,
+    // 256-thread blocks: most steps skip the build, and a skipped launch costs in
+    // proportion to its workgroup count
+    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n * kNlistLanes, 256)), dim3(256), 0, s, d,
                        L.xcd_remap);
 }
 
@@ -1616,7 +1643,7 @@ void launch_build(const Dev& d, const Launch& L, hipStream_t s)
 void launch_nlist(const Dev& d, const Launch& L, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n * kNlistLanes, L.block)), dim3(L.block), 0, s, d,
+        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n * kNlistLanes, 256)), dim3(256), 0, s, d,
                            L.xcd_remap);
     }));
 }
@@ -1678,20 +1705,10 @@ void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hip
     })));
 }
 
-void launch_dt(const Dev& d, double dt_override, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_dt, dim3(blocks_for(d.ninst, 256)), dim3(256), 0, s, d, dt_override);
-}
-
-void launch_finish(const Dev& d, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_finish, dim3(blocks_for(d.ninst, 256)), dim3(256), 0, s, d);
-}
-
-void launch_predict(const Dev& d, const Launch&, hipStream_t s)
+void launch_predict(const Dev& d, double dt_override, const Launch&, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_predict<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_predict<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, dt_override);
     }));
 }
 
