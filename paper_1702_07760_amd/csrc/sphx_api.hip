@@ -240,6 +240,7 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.status = c.take<uint32_t>(1);
     d.inter = c.take<unsigned long long>(1);
     d.curp = c.take<int>(1);
+    d.prevp = c.take<int>(1);
     d.flags = c.take<uint32_t>(4);
     d.cnt = c.take<uint32_t>(ncell);
     d.cstart = c.take<uint32_t>((size_t)ncell + 1);
@@ -254,7 +255,6 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.slot = c.take<uint32_t>(un);
     d.tsrc = c.take<uint32_t>(un);
     d.tid = c.take<uint32_t>(un);
-    d.perm = c.take<uint32_t>(un);
     for (int s = 0; s < 2; ++s) {
         d.S[s].pos = c.take<char>(un * 4 * R);
         d.S[s].vel = c.take<char>(un * 4 * R);

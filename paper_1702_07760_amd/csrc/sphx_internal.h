@@ -84,6 +84,7 @@ struct Dev {
     uint32_t* status;
     unsigned long long* inter;
     int* curp;           // which state set (0/1) holds the current sorted state
+    int* prevp;          // during a rebuild: the set being sorted from (the old curp)
     uint32_t* flags;     // [0] rebuild in this step, [1] rebuild requested by the host,
                          // [2] pos.w holds q = (rho - rho0) / rho rather than m P / rho^2
     // build scratch
@@ -94,7 +95,6 @@ struct Dev {
     uint32_t* slot;      // n
     uint32_t* tsrc;      // n
     uint32_t* tid;       // n
-    uint32_t* perm;      // n
     // neighbour list of the current sort order, column-major: entry q of i at q * n + i
     uint32_t* nbl;       // n * cap entries (index | cell-offset code << 26)
     uint32_t* nbc;       // n counts (> cap: overflowed, the passes walk the stencil)

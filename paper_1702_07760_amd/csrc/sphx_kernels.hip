@@ -595,7 +595,20 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
 template <class R, int DIM>
 __global__ void k_hash(Dev d)
 {
-    if (!d.flags[0]) return;
+    // Start of a step (or of a rate evaluation): rebuild the sort and the list when the
+    // host asked for it or some particle moved more than a quarter of the skin since the
+    // last build.  Every block takes the decision from the same inputs (nothing changes
+    // them during this launch); block 0 publishes it for the later build launches, and
+    // the scan's middle pass resets the inputs.
+    __shared__ int any;
+    if (threadIdx.x == 0) any = d.flags[1] ? 1 : 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x)
+        if (__longlong_as_double((long long)d.run[b].disp2) > d.inst[b].rebuild_d2) atomicOr(&any, 1);
+    __syncthreads();
+    const bool rebuild = any != 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) d.flags[0] = rebuild ? 1u : 0u;
+    if (!rebuild) return;
     const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = k < d.n;
@@ -658,9 +671,22 @@ __global__ void k_scan_reduce(const uint32_t* __restrict__ gate, const uint32_t*
     if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ void k_scan_top(const uint32_t* __restrict__ gate, uint32_t* __restrict__ sums, uint32_t ntiles)
+__global__ void k_scan_top(Dev d, uint32_t* __restrict__ sums, uint32_t ntiles)
 {
-    if (!*gate) return;
+    if (!d.flags[0]) return;
+    // every hash block has taken the decision: the gathered copy becomes the current
+    // state set (the rest of the build reads the old one through prevp), and the
+    // decision's inputs are reset
+    if (threadIdx.x == 0) {
+        *d.prevp = *d.curp;
+        *d.curp = 1 - *d.curp;
+        d.flags[1] = 0u;
+        *d.icount = 0u;   // the list build appends the colour-pass particles
+    }
+    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) {
+        d.run[b].disp2 = 0ull;
+        d.run[b].builds += 1;
+    }
     // one block; each thread owns a run of ceil(ntiles / 256) tile sums
     const uint32_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint32_t a = threadIdx.x * per;
@@ -706,7 +732,7 @@ __global__ void k_scan_down(const uint32_t* __restrict__ gate, uint32_t* __restr
 __global__ void k_scatter(Dev d)
 {
     if (!d.flags[0]) return;
-    const int cur = *d.curp;
+    const int cur = *d.prevp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.n) return;
     const uint32_t p = d.cstart[d.newkey[k]] + d.slot[k];
@@ -714,8 +740,10 @@ __global__ void k_scatter(Dev d)
     d.tid[p] = d.O[cur].id[k];
 }
 
-// a2 made unique: within a cell, order by original id (rank = number of smaller ids).
-__global__ void k_rank(Dev d)
+// a2 made unique, a3: within a cell, order by original id (rank = number of smaller
+// ids), and copy the particle's state from the old set into its slot of the new one.
+template <class R>
+__global__ void k_rank(Dev d, int with_ref)
 {
     if (!d.flags[0]) return;
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -726,67 +754,22 @@ __global__ void k_rank(Dev d)
     const uint32_t me = d.tid[s];
     uint32_t r = 0;
     for (uint32_t t = a; t < b; ++t) r += d.tid[t] < me ? 1u : 0u;
-    d.perm[a + r] = src;
-}
-
-// a3: permute the state into the new order (S[cur] -> S[1-cur]).
-template <class R>
-__global__ void k_gather(Dev d, int with_ref)
-{
-    if (!d.flags[0]) return;
-    const int cur = *d.curp;
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d.n) return;
-    const uint32_t src = d.perm[k];
-    const int nxt = 1 - cur;
-    const Sorted& A = d.O[cur];
-    const Sorted& B = d.O[nxt];
-    const uint32_t key = d.newkey[src];
+    const uint32_t k = a + r;
+    const int old = *d.prevp;
+    const Sorted& A = d.O[old];
+    const Sorted& B = d.O[1 - old];
     B.key[k] = key;
-    B.id[k] = A.id[src];
+    B.id[k] = me;
     B.info[k] = A.info[src];
     if (with_ref) B.ref[k] = A.ref[src];
-    const StateSet& SA = d.S[cur];
-    const StateSet& SB = d.S[nxt];
+    const StateSet& SA = d.S[old];
+    const StateSet& SB = d.S[1 - old];
     ((R4<R>*)SB.pos)[k] = ((const R4<R>*)SA.pos)[src];
     ((R4<R>*)SB.vel)[k] = ((const R4<R>*)SA.vel)[src];
     ((R4<R>*)SB.aux)[k] = ((const R4<R>*)SA.aux)[src];
     if constexpr (sizeof(R) == 4) {
         SB.plo[k] = SA.plo[src];
         SB.vlo[k] = SA.vlo[src];
-    }
-}
-
-// After a rebuild the gathered copy becomes the current state set.
-__global__ void k_flip(Dev d)
-{
-    if (d.flags[0] && threadIdx.x == 0 && blockIdx.x == 0) *d.curp = 1 - *d.curp;
-}
-
-// Start of a step (or of a rate evaluation): rebuild the sort and the list when the
-// host asked for it or some particle moved more than a quarter of the skin since the
-// last build; reset the per-instance maxima of the time step.  One block.
-__global__ void k_decide(Dev d)
-{
-    __shared__ int any;
-    if (threadIdx.x == 0) any = d.flags[1] ? 1 : 0;
-    __syncthreads();
-    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x)
-        if (__longlong_as_double((long long)d.run[b].disp2) > d.inst[b].rebuild_d2) atomicOr(&any, 1);
-    __syncthreads();
-    const int rebuild = any;
-    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) {
-        d.run[b].umax2 = 0ull;
-        d.run[b].amax2 = 0ull;
-        if (rebuild) {
-            d.run[b].disp2 = 0ull;
-            d.run[b].builds += 1;
-        }
-    }
-    if (threadIdx.x == 0) {
-        d.flags[0] = (uint32_t)rebuild;
-        d.flags[1] = 0u;
-        if (rebuild) *d.icount = 0u;   // the list build appends the colour-pass particles
     }
 }
 
@@ -1408,6 +1391,8 @@ __device__ __forceinline__ void finish_steps(const Dev& d)
     for (uint32_t b = t0; b < (uint32_t)d.ninst; b += stride) {
         d.run[b].t = d.run[b].t_next;
         d.run[b].step += 1;
+        d.run[b].umax2 = 0ull;   // the predictor has taken this step's dt from them
+        d.run[b].amax2 = 0ull;
     }
 }
 
@@ -1607,17 +1592,15 @@ template <class R, int DIM>
 static void build_impl(const Dev& d, const Launch& L, hipStream_t s)
 {
     const int B = 256;
+    // seven launches, each returning at once on the (usual) steps without a rebuild
     const uint32_t* gate = d.flags;
-    hipLaunchKernelGGL(k_decide, dim3(1), dim3(256), 0, s, d);
     hipLaunchKernelGGL((k_hash<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
     const uint32_t ntiles = (d.ncell + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(SCAN_THREADS), 0, s, gate, d.cnt, d.ncell, d.scan_tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, gate, d.scan_tmp, ntiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, d, d.scan_tmp, ntiles);
     hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(SCAN_THREADS), 0, s, gate, d.cnt, d.ncell, d.scan_tmp, d.cstart);
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
-    hipLaunchKernelGGL(k_rank, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
-    hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, d.O[0].ref ? 1 : 0);
-    hipLaunchKernelGGL(k_flip, dim3(1), dim3(64), 0, s, d);
+    hipLaunchKernelGGL((k_rank<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, d.O[0].ref ? 1 : 0);
     // 256-thread blocks: most steps skip the build, and a skipped launch costs in
     // proportion to its workgroup count
     hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n * kNlistLanes, 256)), dim3(256), 0, s, d,
