@@ -222,12 +222,6 @@ struct Carver {
 };
 
 // Lays every device array out in the workspace (or only measures when base is null).
-// Neighbour-list capacity per particle (lattice: 20 / 80 neighbours within 2h in 2D / 3D).
-// Neighbour-list capacity per particle.  The list walk reads whole batches of
-// (entries per batch) x (lanes per particle) <= 16 entries, so the capacity must be a
-// multiple of 16 for those reads to stay inside the list.
-constexpr uint32_t kListCap2 = 48u, kListCap3 = 128u;
-static_assert(kListCap2 % 16u == 0 && kListCap3 % 16u == 0, "list capacity must be a multiple of 16");
 uint32_t list_cap(int dim) { return dim == 3 ? kListCap3 : kListCap2; }
 
 size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t ncell, int ninst)

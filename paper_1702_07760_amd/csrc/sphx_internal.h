@@ -22,6 +22,12 @@ __host__ __device__ inline uint32_t make_info(uint32_t phase, uint32_t kind, uin
 enum : uint32_t { K_FLUID = 0, K_WALL = 1, K_MOVING = 2 };
 
 // Per-instance constants, built on the host from sphx_params + sphx_phase.
+// Neighbour-list capacity per particle (lattice: 20 / 80 neighbours within 2h in 2D /
+// 3D).  The list walk reads whole batches of (entries per batch) x (lanes per particle)
+// entries, which must divide the capacity for those reads to stay inside the list (the
+// walk checks this at compile time).
+constexpr uint32_t kListCap2 = 48u, kListCap3 = 128u;
+
 struct InstDev {
     double lo[3], hi[3], span[3], cs[3];
     int32_t nc[3];

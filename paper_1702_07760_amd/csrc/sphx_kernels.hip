@@ -256,7 +256,7 @@ __device__ __forceinline__ double min_image(double v, const IC& I, int d)
 // list-entry offset code (unused in FP64).
 template <int DIM, class IC>
 __device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<double>& L, const Row<double>&,
-                                           const double4& pj, uint32_t, double r[3])
+                                           const double4& pj, int, double r[3])
 {
     r[0] = min_image(L.x[0] - pj.x, I, 0);
     r[1] = min_image(L.x[1] - pj.y, I, 1);
@@ -264,13 +264,11 @@ __device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<double>& L, c
     return 0u;
 }
 
-// r_ij for a stencil candidate (FP32: cell offsets; keyj is j's cell key).
+// r_ij for a stencil candidate (FP32: cell offsets; dcx = c_i - c_j along x).
 template <int DIM, class IC>
 __device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<float>& L, const Row<float>& row,
-                                           const float4& pj, uint32_t keyj, float r[3])
+                                           const float4& pj, int dcx, float r[3])
 {
-    int dcx = L.c[0] - (int)(keyj - row.base);
-    if (I.periodic[0]) dcx = dcx > 1 ? dcx - I.nc[0] : (dcx < -1 ? dcx + I.nc[0] : dcx);
     r[0] = fmaf((float)dcx, I.f_cs[0], L.o[0] - pj.x);
     r[1] = fmaf(row.dy, I.f_cs[1], L.o[1] - pj.y);
     r[2] = DIM == 3 ? fmaf(row.dz, I.f_cs[2], L.o[2] - pj.z) : 0.0f;
@@ -320,8 +318,10 @@ template <class R> struct StencilBatch { static constexpr int U = 8; };
 template <> struct StencilBatch<double> { static constexpr int U = 4; };
 
 // Visit every j != i with |r_ij|^2 < cut2 among the 3^d cells around i's cell:
-// body(j, r_ij, |r_ij|^2, record of j, phase of j, list code).  The candidate's cell
-// key (FP32) and phase come from the sorted key and info arrays.  When P lanes share particle i,
+// body(j, r_ij, |r_ij|^2, record of j, phase of j, list code).  A row of the stencil is
+// one or two runs of consecutive sorted particles; a candidate's x cell offset follows
+// from its index against the starts of i's cell and the next (FP32), its phase from
+// the sorted info array.  When P lanes share particle i,
 // lane `sub` takes every P-th candidate of each cell run.  U candidates are loaded per
 // batch.  With ALL, the lanes of a group step through each run together and the body
 // is called for every candidate slot with a flag `in` (a candidate j != i within the
@@ -331,7 +331,6 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
                                               const Sorted& O, const R4<R>* __restrict__ pos, uint32_t i,
                                               const Lane<R>& L, R cut2, uint32_t sub, Body&& body)
 {
-    const uint32_t* __restrict__ keys = O.key;
     const uint32_t* __restrict__ infos = O.info;
     const int nx = I.nc[0];
     const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
@@ -350,45 +349,60 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
             row.code = 3u * (uint32_t)(1 - dy) + 9u * (uint32_t)(1 - dz);
             row.dy = (float)(-dy);
             row.dz = (float)(-dz);
-            uint32_t a0, b0, a1 = 0, b1 = 0;
+            // runs [a, b) and, per run, dcx = db - (k >= m0) - (k >= m1): m0 and m1 are
+            // the starts of i's cell and the next where the run reaches them
+            uint32_t a0, b0, a1 = 0, b1 = 0, m00, m01 = ~0u, m10 = ~0u, m11 = ~0u;
+            int db0 = 1, db1 = 0;
             const int x0 = L.c[0] - 1, x1 = L.c[0] + 1;
             if (!I.periodic[0]) {
                 a0 = cstart[row.base + (uint32_t)max(x0, 0)];
                 b0 = cstart[row.base + (uint32_t)min(x1, nx - 1) + 1];
+                m00 = cstart[row.base + (uint32_t)L.c[0]];
+                m01 = cstart[row.base + (uint32_t)L.c[0] + 1];
             } else if (x0 < 0) {
+                // cell nx - 1 (dcx = 1), then cells 0 and 1 (dcx = 0, -1)
                 a0 = cstart[row.base + (uint32_t)(nx - 1)];
                 b0 = cstart[row.base + (uint32_t)nx];
+                m00 = ~0u;
                 a1 = cstart[row.base];
                 b1 = cstart[row.base + (uint32_t)x1 + 1];
+                m10 = cstart[row.base + 1];
             } else if (x1 >= nx) {
+                // cells nx - 2 and nx - 1 (dcx = 1, 0), then cell 0 (dcx = -1)
                 a0 = cstart[row.base + (uint32_t)x0];
                 b0 = cstart[row.base + (uint32_t)nx];
+                m00 = cstart[row.base + (uint32_t)(nx - 1)];
                 a1 = cstart[row.base];
                 b1 = cstart[row.base + 1];
+                db1 = -1;
             } else {
                 a0 = cstart[row.base + (uint32_t)x0];
                 b0 = cstart[row.base + (uint32_t)x1 + 1];
+                m00 = cstart[row.base + (uint32_t)L.c[0]];
+                m01 = cstart[row.base + (uint32_t)L.c[0] + 1];
             }
             for (int seg = 0; seg < 2; ++seg) {
                 const uint32_t a = seg ? a1 : a0, b = seg ? b1 : b0;
+                const uint32_t m0 = seg ? m10 : m00, m1 = seg ? m11 : m01;
+                const int db = seg ? db1 : db0;
                 if constexpr (ALL) {
                     // group-uniform trip count: every lane of the group sees every slot
                     for (uint32_t kb = a; kb < b; kb += U * P) {
                         const uint32_t k0 = kb + sub;
                         R4<R> pj[U];
-                        uint32_t kj[U], fj[U];
+                        uint32_t fj[U];
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const uint32_t kk = min(k0 + (uint32_t)(u * P), b - 1);
                             pj[u] = pos[kk];
-                            kj[u] = sizeof(R) == 4 ? keys[kk] : 0u;
                             fj[u] = infos[kk];
                         }
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const uint32_t k = k0 + (uint32_t)(u * P);
                             R r[3];
-                            const uint32_t code = pair_r<DIM>(I, L, row, pj[u], kj[u], r);
+                            const int dcx = db - (int)(k >= m0) - (int)(k >= m1);
+                            const uint32_t code = pair_r<DIM>(I, L, row, pj[u], dcx, r);
                             const R r2 = dist2<DIM>(r[0], r[1], r[2]);
                             body(k, r, r2, pj[u], info_phase(fj[u]), code, k < b && k != i && r2 < cut2);
                         }
@@ -396,12 +410,11 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
                 } else {
                     for (uint32_t k0 = a + sub; k0 < b; k0 += U * P) {
                         R4<R> pj[U];
-                        uint32_t kj[U], fj[U];
+                        uint32_t fj[U];
 #pragma unroll
                         for (int u = 0; u < U; ++u) {
                             const uint32_t kk = min(k0 + (uint32_t)(u * P), b - 1);
                             pj[u] = pos[kk];
-                            kj[u] = sizeof(R) == 4 ? keys[kk] : 0u;
                             fj[u] = infos[kk];
                         }
 #pragma unroll
@@ -409,7 +422,8 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
                             const uint32_t k = k0 + (uint32_t)(u * P);
                             if (k < b && k != i) {
                                 R r[3];
-                                const uint32_t code = pair_r<DIM>(I, L, row, pj[u], kj[u], r);
+                                const int dcx = db - (int)(k >= m0) - (int)(k >= m1);
+                                const uint32_t code = pair_r<DIM>(I, L, row, pj[u], dcx, r);
                                 const R r2 = dist2<DIM>(r[0], r[1], r[2]);
                                 if (r2 < cut2) body(k, r, r2, pj[u], info_phase(fj[u]), code);
                             }
@@ -441,6 +455,8 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
                                          uint32_t i, const Lane<R>& L, uint32_t cnt, uint32_t sub,
                                          Load&& load, Body&& body)
 {
+    static_assert(kListCap2 % (U * P) == 0 && kListCap3 % (U * P) == 0,
+                  "a batch of U entries on P lanes must divide the list capacity");
     using X = decltype(load(0u));
     const uint32_t n = (uint32_t)d.n;
     const char* __restrict__ base = (const char*)d.nbl;
@@ -1081,10 +1097,12 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
         per_instance(d, info_inst(info), [&](const InstU& I) {
             Lane<R> L;
             L.load(I, pi, O.key[i]);
-            for_each_neighbor<R, DIM, kColourBatch, P>(d, I, O, pos, i, L, sub, [](uint32_t) { return NoExtra{}; },
-                [&](uint32_t k, const R* r, R r2, const R4<R>&, uint32_t phj, NoExtra) {
+            // V_k is requested with the position, not after it: one wait per batch
+            for_each_neighbor<R, DIM, kColourBatch, P>(d, I, O, pos, i, L, sub,
+                [&](uint32_t k) { return fabs(vel[k].w); },
+                [&](uint32_t, const R* r, R r2, const R4<R>&, uint32_t phj, R vk) {
                     if (phj == ph) return;                       // C_j^y = 1 only for the other phase
-                    const R vk = vel[k].w;                       // 1 / sigma_k
+                    // vk = V_k = 1 / sigma_k
                     const R f = kernel_f<R>(I, r2) * (vk * vk);
                     s[0] += f * r[0];
                     s[1] += f * r[1];
@@ -1123,8 +1141,13 @@ __device__ __forceinline__ void tension_dot(R c, const R g[3], R gn2, const R w[
 #ifndef SPHX_FORCE_BATCH
 #define SPHX_FORCE_BATCH 4
 #endif
-template <class R> struct ForceBatch { static constexpr int U = SPHX_FORCE_BATCH; };
-template <> struct ForceBatch<double> { static constexpr int U = 2; };
+#ifndef SPHX_FORCE_BATCH64
+#define SPHX_FORCE_BATCH64 4
+#endif
+template <class R, int P> struct ForceBatch {
+    static constexpr int B = sizeof(R) == 8 ? SPHX_FORCE_BATCH64 : SPHX_FORCE_BATCH;
+    static constexpr int U = B * P <= 16 ? B : 16 / P;
+};
 
 // Per-lane state of the force pass for particle i: its own quantities, the sums of
 // Eqs. (6), (8), (10)/(11), (17) over its neighbours, and the epilogue that turns them
@@ -1323,7 +1346,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
             // one loop per case, so that the walk carries no per-neighbour branch on it
             auto walk = [&](auto uniform) {
                 constexpr bool UM = decltype(uniform)::value;
-                for_each_neighbor<R, DIM, ForceBatch<R>::U, P>(d, I, O, pos, i, L, sub,
+                for_each_neighbor<R, DIM, ForceBatch<R, P>::U, P>(d, I, O, pos, i, L, sub,
                     [&](uint32_t k) {
                         VM x;
                         x.v = vel[k];
