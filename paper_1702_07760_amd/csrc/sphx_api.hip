@@ -31,7 +31,8 @@ struct sphx_ctx {
     bool bound = false, inited = false, rates_valid = false;
     bool has_moving = false;
     bool use_graph = true;
-    hipGraphExec_t graph = nullptr;   // one step; the state parity lives on the device
+    hipGraphExec_t graph = nullptr;    // one step; the state parity lives on the device
+    hipGraphExec_t graph_k = nullptr;  // kGraphSteps steps: one replay, fewer launch gaps
     bool profile = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;   // (group, start/stop)
     double phase_ms[SPHX_NPH] = {0, 0, 0, 0, 0};
@@ -398,6 +399,10 @@ int device_cur(sphx_ctx* c)
 
 void drop_graphs(sphx_ctx* c)
 {
+    if (c->graph_k) {
+        (void)hipGraphExecDestroy(c->graph_k);
+        c->graph_k = nullptr;
+    }
     if (c->graph) {
         (void)hipGraphExecDestroy(c->graph);
         c->graph = nullptr;
@@ -466,6 +471,31 @@ std::vector<Span> state_spans(sphx_ctx* c, int s)
     }
     if (d.O[s].ref) v.push_back({d.O[s].ref, n * 32});
     return v;
+}
+
+// Full steps per replay of the long step graph: each replay of a graph leaves a launch
+// gap of several microseconds before its first kernel.
+constexpr int32_t kGraphSteps = 8;
+
+// Captures `steps` full steps into an executable graph; on failure turns graphs off
+// for this context and returns null (the steps then run eagerly).
+hipGraphExec_t capture_steps(sphx_ctx* c, int32_t steps)
+{
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        for (int32_t k = 0; k < steps; ++k) enqueue_step(c);
+        ok = hipStreamEndCapture(c->stream, &graph) == hipSuccess && graph &&
+             hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+    if (!ok) {
+        exec = nullptr;
+        c->use_graph = false;
+        (void)hipGetLastError();
+    }
+    return exec;
 }
 } // namespace
 
@@ -764,24 +794,21 @@ sphx_status sphx_step(sphx_ctx* c, int32_t nsteps)
     if (!c) return SPHX_E_ARG;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
     if (nsteps < 0) return fail(c, SPHX_E_ARG, "nsteps must be >= 0");
-    for (int32_t k = 0; k < nsteps; ++k) {
-        if (c->use_graph && !c->profile && !c->graph) {
-            hipGraph_t graph = nullptr;
-            bool ok = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-            if (ok) {
-                enqueue_step(c);
-                ok = hipStreamEndCapture(c->stream, &graph) == hipSuccess && graph &&
-                     hipGraphInstantiate(&c->graph, graph, nullptr, nullptr, 0) == hipSuccess;
-                if (graph) (void)hipGraphDestroy(graph);
-            }
-            if (!ok) {
-                c->graph = nullptr;
-                c->use_graph = false;
-                (void)hipGetLastError();
+    int32_t k = 0;
+    while (k < nsteps) {
+        const bool graphs = c->use_graph && !c->profile;
+        if (graphs && nsteps - k >= kGraphSteps) {
+            if (!c->graph_k) c->graph_k = capture_steps(c, kGraphSteps);
+            if (c->graph_k) {
+                HIP_OK(c, hipGraphLaunch(c->graph_k, c->stream));
+                k += kGraphSteps;
+                continue;
             }
         }
+        if (c->use_graph && !c->profile && !c->graph) c->graph = capture_steps(c, 1);
         if (c->use_graph && !c->profile && c->graph) HIP_OK(c, hipGraphLaunch(c->graph, c->stream));
         else enqueue_step(c);
+        ++k;
     }
     c->rates_valid = false;
     HIP_OK(c, hipGetLastError());

@@ -187,6 +187,23 @@ def test_steps_are_deterministic_and_graph_matches_eager(prec, lanes):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_multi_step_graph_replays_match_eager_steps(prec):
+    # chunks of 8 run as one replay of the eight-step graph, the rest step by step; the
+    # fields are read (eager copies, a synchronisation) between replays, and every
+    # chunk is checked against the eager context
+    s = inputs.drop2d(perturb=True)
+    a = binding.Sim(s, precision=prec)
+    c = binding.Sim(s, precision=prec, graph=False)
+    for chunk in (8, 3, 8, 9, 16):
+        a.step(chunk)
+        c.step(chunk)
+        for f in (binding.F_X, binding.F_U, binding.F_RHO):
+            assert np.array_equal(a.get_field(f), c.get_field(f)), (chunk, f)
+    assert a.stats()["steps"] == c.stats()["steps"] == 44
+    assert a.stats()["builds"] == c.stats()["builds"] > 1
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_checkpoint_round_trip_is_bit_identical(prec):
     s = inputs.drop2d(perturb=True)
     a = binding.Sim(s, precision=prec)
