@@ -106,8 +106,14 @@ enum {
                                  neighbour and the partial sums are combined in-wave (the colour
                                  pass always runs 8 lanes per particle) */
     SPHX_OPT_FORCE_LANES = 7, /* the same for the force pass (default: 1 in FP32, 2 in FP64) */
-    SPHX_OPT_PROFILE = 6      /* 1: no graphs; every kernel group is bracketed by HIP events on the
+    SPHX_OPT_PROFILE = 6,     /* 1: no graphs; every kernel group is bracketed by HIP events on the
                                  context stream and its time is reported in sphx_stats */
+    SPHX_OPT_ONE_LAUNCH_BUILD = 8 /* 1 (default): the neighbour build (cell sort and list) is one
+                                 launch, sized to the blocks the device holds at once, whose phases
+                                 meet at grid barriers; without a rebuild it ends after the
+                                 decision.  0: seven launches.  A barrier that waits too long (its
+                                 blocks were not all resident, e.g. other work shared the device)
+                                 makes the next sphx_sync return SPHX_E_HIP and stops rebuilds */
 };
 
 /* Kernel groups timed under SPHX_OPT_PROFILE. */

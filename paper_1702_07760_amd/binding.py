@@ -23,6 +23,7 @@ F_X, F_U, F_RHO, F_A, F_DRHO, F_AP, F_AV, F_AS, F_P, F_GRADC = 0, 1, 2, 3, 4, 5,
 _VEC = {F_X, F_U, F_A, F_AP, F_AV, F_AS, F_GRADC}
 OPT_DEBUG_TERMS, OPT_BLOCK, OPT_XCD_REMAP, OPT_GRAPH, OPT_LANES, OPT_PROFILE = 1, 2, 3, 4, 5, 6
 OPT_FORCE_LANES = 7
+OPT_ONE_LAUNCH_BUILD = 8
 PHASES = ("build", "renorm", "colour", "force", "integrate")
 STATUS = {0: "SPHX_OK", 1: "SPHX_E_ARG", 2: "SPHX_E_NODEV", 3: "SPHX_E_HIP", 4: "SPHX_E_WORKSPACE",
           5: "SPHX_E_STATE", 6: "SPHX_E_NONFINITE", 7: "SPHX_E_DOMAIN", 8: "SPHX_E_DT"}

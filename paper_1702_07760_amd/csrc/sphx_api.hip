@@ -236,6 +236,7 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.inter = c.take<unsigned long long>(1);
     d.curp = c.take<int>(1);
     d.prevp = c.take<int>(1);
+    d.bar = c.take<unsigned>(512 + 4096);   // the one-launch build's barrier words and slots
     d.flags = c.take<uint32_t>(4);
     d.cnt = c.take<uint32_t>(ncell);
     d.cstart = c.take<uint32_t>((size_t)ncell + 1);
@@ -290,6 +291,8 @@ bool setup_cells(const sphx_params* per, int ninst, std::vector<uint32_t>& base,
 
 // ---------------------------------------------------------------- stepping
 
+void drop_graphs(sphx_ctx* c);
+
 sphx_status status_of(sphx_ctx* c)
 {
     uint32_t st = 0;
@@ -302,6 +305,15 @@ sphx_status status_of(sphx_ctx* c)
     if (st & ST_NONFINITE) return fail(c, SPHX_E_NONFINITE, "a rate or state value became non-finite");
     if (st & ST_DOMAIN) return fail(c, SPHX_E_DOMAIN, "a particle left a non-periodic domain");
     if (st & ST_DT) return fail(c, SPHX_E_DT, "dt * max|u| exceeded half the neighbour skin");
+    if (st & ST_STALL) {
+        // the barrier words may hold a half-finished launch's epochs: clear them and
+        // build with seven launches from now on
+        HIP_OK(c, hipMemset(c->dev.bar, 0, (512 + 4096) * sizeof(unsigned)));
+        c->launch.one_launch_build = false;
+        drop_graphs(c);
+        return fail(c, SPHX_E_HIP, "a grid barrier of the one-launch build timed out (its blocks were not all "
+                                   "resident); the context now builds with seven launches");
+    }
     return SPHX_OK;
 }
 
@@ -703,6 +715,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemsetAsync(d.status, 0, sizeof(uint32_t), s));
     HIP_OK(c, hipMemsetAsync(d.inter, 0, sizeof(unsigned long long), s));
     HIP_OK(c, hipMemsetAsync(d.icount, 0, sizeof(uint32_t), s));
+    HIP_OK(c, hipMemsetAsync(d.bar, 0, (512 + 4096) * sizeof(unsigned), s));
     HIP_OK(c, hipMemsetAsync(d.cnt, 0, sizeof(uint32_t) * c->ncell, s));
     HIP_OK(c, hipMemsetAsync(d.acc, 0, n * 4 * R, s));
     HIP_OK(c, hipMemsetAsync(d.gc, 0, n * 4 * R, s));
@@ -835,6 +848,7 @@ sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
         (option == SPHX_OPT_LANES ? c->launch.lanes : c->launch.force_lanes) = (int)value;
         break;
     case SPHX_OPT_GRAPH: c->use_graph = value != 0 && c->stream != nullptr; break;
+    case SPHX_OPT_ONE_LAUNCH_BUILD: c->launch.one_launch_build = value != 0; break;
     case SPHX_OPT_PROFILE:
         c->profile = value != 0;
         for (int q = 0; q < SPHX_NPH; ++q) {

@@ -9,7 +9,7 @@ namespace sphx {
 constexpr int kMaxPiston = 16;
 
 // Status word bits (sticky, set by kernels with atomicOr).
-enum : uint32_t { ST_NONFINITE = 1u, ST_DOMAIN = 2u, ST_DT = 4u };
+enum : uint32_t { ST_NONFINITE = 1u, ST_DOMAIN = 2u, ST_DT = 4u, ST_STALL = 8u };
 
 // Particle info word: phase in bit 0, kind in bits 1-2, instance in bits 8-31.
 __host__ __device__ inline uint32_t info_phase(uint32_t w) { return w & 1u; }
@@ -91,6 +91,8 @@ struct Dev {
     unsigned long long* inter;
     int* curp;           // which state set (0/1) holds the current sorted state
     int* prevp;          // during a rebuild: the set being sorted from (the old curp)
+    unsigned* bar;       // the one-launch build's grid barrier: epoch base, release words,
+                         // arrival slots (512 + 4096 words)
     uint32_t* flags;     // [0] rebuild in this step, [1] rebuild requested by the host,
                          // [2] pos.w holds q = (rho - rho0) / rho rather than m P / rho^2
     // build scratch
@@ -123,6 +125,7 @@ struct Launch {
     int xcd_remap = 1;   // 0 dispatch order, 1 XCD-contiguous tiles, K >= 2 also K tiles per CU
     int lanes = 4;       // lanes per particle in the renormalisation pass (1, 2, 4)
     int force_lanes = 1; // lanes per particle in the force pass (1, 2, 4)
+    bool one_launch_build = true;   // the build as one launch with grid barriers (else seven)
     bool debug_terms = false;
 };
 

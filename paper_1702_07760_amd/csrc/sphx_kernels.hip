@@ -18,6 +18,7 @@
 
 #include <math.h>
 #include <type_traits>
+#include <algorithm>
 
 namespace sphx {
 
@@ -608,25 +609,28 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
 }
 
 
-template <class R, int DIM>
-__global__ void k_hash(Dev d)
+// Start of a step (or of a rate evaluation): rebuild the sort and the list when the host
+// asked for it or some particle moved more than a quarter of the skin since the last
+// build.  Every block takes the decision from the same inputs (nothing changes them
+// before the scan's middle pass, which resets them); block 0 publishes it in flag 0.
+// No rebuild either after a grid barrier of the one-launch build stalled.
+__device__ __forceinline__ bool build_decision(const Dev& d)
 {
-    // Start of a step (or of a rate evaluation): rebuild the sort and the list when the
-    // host asked for it or some particle moved more than a quarter of the skin since the
-    // last build.  Every block takes the decision from the same inputs (nothing changes
-    // them during this launch); block 0 publishes it for the later build launches, and
-    // the scan's middle pass resets the inputs.
     __shared__ int any;
     if (threadIdx.x == 0) any = d.flags[1] ? 1 : 0;
     __syncthreads();
     for (int b = threadIdx.x; b < d.ninst; b += blockDim.x)
         if (__longlong_as_double((long long)d.run[b].disp2) > d.inst[b].rebuild_d2) atomicOr(&any, 1);
     __syncthreads();
-    const bool rebuild = any != 0;
+    const bool rebuild = any != 0 && !(*d.status & ST_STALL);
     if (blockIdx.x == 0 && threadIdx.x == 0) d.flags[0] = rebuild ? 1u : 0u;
-    if (!rebuild) return;
-    const int cur = *d.curp;
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    return rebuild;
+}
+
+// a1 for slot k of a wave (k >= n: an idle lane; the whole wave takes part).
+template <class R, int DIM>
+__device__ __forceinline__ void hash_phase(const Dev& d, int cur, uint32_t k)
+{
     const bool valid = k < d.n;
     uint32_t key = 0;
     if (valid) key = hash_one<R, DIM>(d, cur, k);
@@ -648,6 +652,13 @@ __global__ void k_hash(Dev d)
         d.newkey[k] = key;
         d.slot[k] = slot;
     }
+}
+
+template <class R, int DIM>
+__global__ void k_hash(Dev d)
+{
+    if (!build_decision(d)) return;
+    hash_phase<R, DIM>(d, *d.curp, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // a4 (cell start table): exclusive scan of the per-cell counts in three passes.
@@ -674,22 +685,29 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t& t
     return base + incl - v;
 }
 
-__global__ void k_scan_reduce(const uint32_t* __restrict__ gate, const uint32_t* __restrict__ in, uint32_t n,
-                              uint32_t* __restrict__ sums)
+// Pass 1 for one tile (the whole block takes part): its sum into sums[tile].
+__device__ __forceinline__ void scan_reduce_tile(const uint32_t* __restrict__ in, uint32_t n,
+                                                 uint32_t* __restrict__ sums, uint32_t tile)
 {
-    if (!*gate) return;
-    const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    const uint32_t base = tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     uint32_t s = 0;
     for (int j = 0; j < SCAN_ITEMS; ++j)
         if (base + j < n) s += in[base + j];
     uint32_t total;
     block_exclusive_scan(s, total);
-    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+    if (threadIdx.x == 0) sums[tile] = total;
 }
 
-__global__ void k_scan_top(Dev d, uint32_t* __restrict__ sums, uint32_t ntiles)
+__global__ void k_scan_reduce(const uint32_t* __restrict__ gate, const uint32_t* __restrict__ in, uint32_t n,
+                              uint32_t* __restrict__ sums)
 {
-    if (!d.flags[0]) return;
+    if (!*gate) return;
+    scan_reduce_tile(in, n, sums, blockIdx.x);
+}
+
+// Pass 2 (one block): exclusive scan of the tile sums.
+__device__ __forceinline__ void scan_top_block(const Dev& d, uint32_t* __restrict__ sums, uint32_t ntiles)
+{
     // every hash block has taken the decision: the gathered copy becomes the current
     // state set (the rest of the build reads the old one through prevp), and the
     // decision's inputs are reset
@@ -719,12 +737,18 @@ __global__ void k_scan_top(Dev d, uint32_t* __restrict__ sums, uint32_t ntiles)
         }
 }
 
-// Writes cstart[0..n] and clears the counters for the next build.
-__global__ void k_scan_down(const uint32_t* __restrict__ gate, uint32_t* __restrict__ cnt, uint32_t n,
-                            const uint32_t* __restrict__ sums, uint32_t* __restrict__ out)
+__global__ void k_scan_top(Dev d, uint32_t* __restrict__ sums, uint32_t ntiles)
 {
-    if (!*gate) return;
-    const uint32_t base = blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
+    if (!d.flags[0]) return;
+    scan_top_block(d, sums, ntiles);
+}
+
+// Pass 3 for one tile: writes cstart[0..n] and clears the counters for the next build.
+__device__ __forceinline__ void scan_down_tile(uint32_t* __restrict__ cnt, uint32_t n,
+                                               const uint32_t* __restrict__ sums, uint32_t* __restrict__ out,
+                                               uint32_t tile)
+{
+    const uint32_t base = tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
     uint32_t s = 0;
     for (int j = 0; j < SCAN_ITEMS; ++j) {
@@ -732,7 +756,7 @@ __global__ void k_scan_down(const uint32_t* __restrict__ gate, uint32_t* __restr
         s += v[j];
     }
     uint32_t total;
-    uint32_t run = block_exclusive_scan(s, total) + sums[blockIdx.x];
+    uint32_t run = block_exclusive_scan(s, total) + sums[tile];
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         const uint32_t idx = base + j;
         if (idx < n) {
@@ -744,33 +768,45 @@ __global__ void k_scan_down(const uint32_t* __restrict__ gate, uint32_t* __restr
     }
 }
 
-// Provisional scatter into the cell's segment.
+__global__ void k_scan_down(const uint32_t* __restrict__ gate, uint32_t* __restrict__ cnt, uint32_t n,
+                            const uint32_t* __restrict__ sums, uint32_t* __restrict__ out)
+{
+    if (!*gate) return;
+    scan_down_tile(cnt, n, sums, out, blockIdx.x);
+}
+
+// Provisional scatter into the cell's segment (a slot outside [0, n) can only follow a
+// stalled barrier, whose build is abandoned: it is skipped).
+__device__ __forceinline__ void scatter_one(const Dev& d, uint32_t k)
+{
+    if (k >= d.n) return;
+    const uint32_t p = d.cstart[d.newkey[k]] + d.slot[k];
+    if (p >= d.n) return;
+    d.tsrc[p] = k;
+    d.tid[p] = d.O[*d.prevp].id[k];
+}
+
 __global__ void k_scatter(Dev d)
 {
     if (!d.flags[0]) return;
-    const int cur = *d.prevp;
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= d.n) return;
-    const uint32_t p = d.cstart[d.newkey[k]] + d.slot[k];
-    d.tsrc[p] = k;
-    d.tid[p] = d.O[cur].id[k];
+    scatter_one(d, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // a2 made unique, a3: within a cell, order by original id (rank = number of smaller
 // ids), and copy the particle's state from the old set into its slot of the new one.
 template <class R>
-__global__ void k_rank(Dev d, int with_ref)
+__device__ __forceinline__ void rank_one(const Dev& d, uint32_t s, int with_ref)
 {
-    if (!d.flags[0]) return;
-    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= d.n) return;
     const uint32_t src = d.tsrc[s];
+    if (src >= d.n) return;
     const uint32_t key = d.newkey[src];
-    const uint32_t a = d.cstart[key], b = d.cstart[key + 1];
+    const uint32_t a = d.cstart[key], b = min(d.cstart[key + 1], (uint32_t)d.n);
     const uint32_t me = d.tid[s];
     uint32_t r = 0;
     for (uint32_t t = a; t < b; ++t) r += d.tid[t] < me ? 1u : 0u;
     const uint32_t k = a + r;
+    if (k >= d.n) return;
     const int old = *d.prevp;
     const Sorted& A = d.O[old];
     const Sorted& B = d.O[1 - old];
@@ -789,6 +825,13 @@ __global__ void k_rank(Dev d, int with_ref)
     }
 }
 
+template <class R>
+__global__ void k_rank(Dev d, int with_ref)
+{
+    if (!d.flags[0]) return;
+    rank_one<R>(d, blockIdx.x * blockDim.x + threadIdx.x, with_ref);
+}
+
 // Neighbour list at the current positions: every j within the cell size (2 + skin) h
 // (with a rounding margin).  Together with the rebuild rule this holds every pair within
 // 2h at any state evaluated before the next rebuild.  kNlistLanes lanes share a particle
@@ -800,14 +843,10 @@ __global__ void k_rank(Dev d, int with_ref)
 constexpr int kNlistLanes = 4;
 
 template <class R, int DIM>
-__global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
+__device__ __forceinline__ void nlist_one(const Dev& d, uint32_t i, uint32_t sub)
 {
     constexpr int P = kNlistLanes;
-    if (!d.flags[0]) return;
     const int cur = *d.curp;
-    uint32_t i, sub;
-    lane_split<P>(remap, i, sub);
-    if (i >= d.n) return;
     const Sorted& O = d.O[cur];
     const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
     const R4<R> pi = pos[i];
@@ -851,6 +890,106 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
             *vw = fabs(*vw);
         }
     });
+}
+
+template <class R, int DIM>
+__global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
+{
+    if (!d.flags[0]) return;
+    uint32_t i, sub;
+    lane_split<kNlistLanes>(remap, i, sub);
+    if (i >= d.n) return;
+    nlist_one<R, DIM>(d, i, sub);
+}
+
+// Grid-wide barrier of the one-launch build, whose grid is sized so that all its blocks
+// are resident together.  Nothing is contended: each block stores the barrier's epoch
+// into its own arrival slot, block 0's threads wait for all slots together, then block
+// 0 stores the epoch into eight release words on separate cache lines, each polled by
+// one eighth of the blocks.  Epochs grow across launches (word 0 holds the next base),
+// so no slot needs clearing.  Every wait is bounded: a block that waits too long
+// records ST_STALL and returns false (later builds are then skipped and the host
+// reports the error), as do the blocks that wait on it after.
+constexpr uint32_t kBarrierSpins = 1u << 20;
+constexpr uint32_t kBarRelease = 32;     // release word r at bar[kBarRelease * (1 + r)], r < 8
+constexpr uint32_t kBarSlots = 512;      // arrival slot of block b at bar[kBarSlots + b]
+constexpr uint32_t kBarMaxBlocks = 4096; // the one-launch build uses at most this many blocks
+
+// Polls with relaxed loads (coherent, without the cache invalidation an acquire load
+// carries on every iteration); the caller fences once after the wait.
+__device__ __forceinline__ bool bar_wait(unsigned* w, unsigned epoch)
+{
+    uint32_t spins = 0;
+    while ((int)(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - epoch) < 0) {
+        __builtin_amdgcn_s_sleep(4);
+        if (++spins >= kBarrierSpins) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool grid_sync(const Dev& d, unsigned epoch)
+{
+    __shared__ int ok;
+    unsigned* bar = d.bar;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ok = 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the block's writes, then its arrival
+        __hip_atomic_store(&bar[kBarSlots + blockIdx.x], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (blockIdx.x == 0) {
+        __syncthreads();
+        bool good = true;
+        for (uint32_t b = threadIdx.x; b < gridDim.x && good; b += blockDim.x) good = bar_wait(&bar[kBarSlots + b], epoch);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // what the arrivals this lane saw released
+        if (!good) ok = 0;
+        __syncthreads();
+        if (threadIdx.x == 0 && ok) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            for (uint32_t r = 0; r < 8; ++r)
+                __hip_atomic_store(&bar[kBarRelease * (1 + r)], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (threadIdx.x == 0) {
+        if (!bar_wait(&bar[kBarRelease * (1 + (blockIdx.x & 7))], epoch)) ok = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // everything released before the epoch
+    }
+    __syncthreads();
+    if (!ok && threadIdx.x == 0) atomicOr(d.status, ST_STALL);
+    return ok != 0;
+}
+
+// The whole build in one launch.  Every block takes the rebuild decision; on the steps
+// without a rebuild (most of them) the launch ends there, where the seven-launch form
+// pays for seven launches.  On a rebuild the phases above run grid-stride, separated by
+// grid barriers.
+template <class R, int DIM>
+__global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_ref)
+{
+    if (!build_decision(d)) return;
+    const uint32_t n = d.n, T = gridDim.x * blockDim.x;
+    const int old = *d.curp;   // the scan's middle pass flips the current set
+    // this launch's barrier epochs are base + 1 .. base + 6; block 0 advances the base
+    // after the last barrier, when every block has read it
+    const unsigned base = __hip_atomic_load(&d.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n; b0 += T) hash_phase<R, DIM>(d, old, b0 + threadIdx.x);
+    if (!grid_sync(d, base + 1)) return;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) scan_reduce_tile(d.cnt, d.ncell, d.scan_tmp, t);
+    if (!grid_sync(d, base + 2)) return;
+    if (blockIdx.x == 0) scan_top_block(d, d.scan_tmp, ntiles);
+    if (!grid_sync(d, base + 3)) return;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) scan_down_tile(d.cnt, d.ncell, d.scan_tmp, d.cstart, t);
+    if (!grid_sync(d, base + 4)) return;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) scatter_one(d, k);
+    if (!grid_sync(d, base + 5)) return;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) rank_one<R>(d, k, with_ref);
+    if (!grid_sync(d, base + 6)) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        __hip_atomic_store(&d.bar[0], base + 6, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t lanes = n * (uint32_t)kNlistLanes;
+    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < lanes; b0 += T) {
+        const uint32_t t = b0 + threadIdx.x;
+        if (t < lanes) nlist_one<R, DIM>(d, t / kNlistLanes, t % kNlistLanes);
+    }
 }
 
 // ------------------------------------------------------ per-particle state
@@ -1611,14 +1750,42 @@ __global__ void k_export(Dev d, int pass, const uint32_t* __restrict__ off, uint
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Blocks of the one-launch build: as many as the device holds at once (all must be
+// resident for the grid barriers), no more than the largest phase can use.
+template <class R, int DIM>
+static unsigned build_grid(const Dev& d, uint32_t ntiles)
+{
+    static int per_cu = -1;   // depends on the kernel and the architecture only
+    if (per_cu < 0) {
+        int v = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_build<R, DIM>, 256, 0) != hipSuccess) v = 0;
+        per_cu = v;
+    }
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                 hipSuccess)
+        ncu = 0;
+    const uint64_t resident = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ncu, kBarMaxBlocks);
+    uint64_t need = std::max<uint64_t>(blocks_for(d.n * kNlistLanes, 256), ntiles);
+    if (need < 1) need = 1;
+    return (unsigned)std::min<uint64_t>(resident, need);
+}
+
 template <class R, int DIM>
 static void build_impl(const Dev& d, const Launch& L, hipStream_t s)
 {
     const int B = 256;
+    const uint32_t ntiles = (d.ncell + SCAN_TILE - 1) / SCAN_TILE;
+    if (L.one_launch_build) {
+        const unsigned g = build_grid<R, DIM>(d, ntiles);
+        if (g > 0) {
+            hipLaunchKernelGGL((k_build<R, DIM>), dim3(g), dim3(256), 0, s, d, ntiles, d.O[0].ref ? 1 : 0);
+            return;
+        }
+    }
     // seven launches, each returning at once on the (usual) steps without a rebuild
     const uint32_t* gate = d.flags;
     hipLaunchKernelGGL((k_hash<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
-    const uint32_t ntiles = (d.ncell + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3(ntiles), dim3(SCAN_THREADS), 0, s, gate, d.cnt, d.ncell, d.scan_tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, d, d.scan_tmp, ntiles);
     hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(SCAN_THREADS), 0, s, gate, d.cnt, d.ncell, d.scan_tmp, d.cstart);

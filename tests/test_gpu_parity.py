@@ -204,6 +204,30 @@ def test_multi_step_graph_replays_match_eager_steps(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["drop2d", "periodic3d", "batch"])
+def test_one_launch_build_matches_seven_launches(name, prec):
+    # the neighbour build as one launch with grid barriers against the seven-launch form:
+    # same states and lists, bit for bit, across steps with rebuilds
+    if name == "batch":
+        s = inputs.concat("batch", [inputs.drop2d(perturb=True, dx=dx) for dx in (2.5e-3, 4e-3)])
+    else:
+        s = SCENES[name]()
+    print(f"case one-launch build {name} precision={prec} n={s.n}", flush=True)
+    a = binding.Sim(s, precision=prec)
+    b = binding.Sim(s, precision=prec)
+    b.set_option(binding.OPT_ONE_LAUNCH_BUILD, 0)
+    for chunk in (1, 12, 20):
+        a.step(chunk)
+        b.step(chunk)
+        for f in (binding.F_X, binding.F_U, binding.F_RHO):
+            assert np.array_equal(a.get_field(f), b.get_field(f)), (chunk, f)
+        oa, ia = a.get_neighbors()
+        ob, ib = b.get_neighbors()
+        assert np.array_equal(oa, ob) and np.array_equal(ia, ib)
+    assert a.stats()["builds"] == b.stats()["builds"] > 1
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_checkpoint_round_trip_is_bit_identical(prec):
     s = inputs.drop2d(perturb=True)
     a = binding.Sim(s, precision=prec)
