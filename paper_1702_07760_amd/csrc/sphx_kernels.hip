@@ -207,11 +207,11 @@ template <> struct Lane<double> {
 };
 
 template <> struct Lane<float> {
-    float o[3];
+    float om[3];   // offset minus one cell size: r = (c_i - c_j + 1) s + om - o_j
     int c[3];
     template <class IC> __device__ void load(const IC& I, const float4& p, uint32_t key)
     {
-        o[0] = p.x; o[1] = p.y; o[2] = p.z;
+        om[0] = p.x - I.f_cs[0]; om[1] = p.y - I.f_cs[1]; om[2] = p.z - I.f_cs[2];
         cell_of_key(I, key, c);
     }
 };
@@ -220,7 +220,7 @@ template <> struct Lane<float> {
 template <class R> struct Row {
     uint32_t base;   // key of the row's first cell
     uint32_t code;   // 3 (delta_y + 1) + 9 (delta_z + 1), delta = c_i - c_j
-    float dy, dz;    // delta_y, delta_z as floats
+    float dy1, dz1;  // delta_y + 1, delta_z + 1 as floats
 };
 
 // Neighbour-list entry: particle index j in the low 26 bits; in FP32 the cell offset
@@ -270,9 +270,9 @@ template <int DIM, class IC>
 __device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<float>& L, const Row<float>& row,
                                            const float4& pj, int dcx, float r[3])
 {
-    r[0] = fmaf((float)dcx, I.f_cs[0], L.o[0] - pj.x);
-    r[1] = fmaf(row.dy, I.f_cs[1], L.o[1] - pj.y);
-    r[2] = DIM == 3 ? fmaf(row.dz, I.f_cs[2], L.o[2] - pj.z) : 0.0f;
+    r[0] = fmaf((float)(dcx + 1), I.f_cs[0], L.om[0] - pj.x);
+    r[1] = fmaf(row.dy1, I.f_cs[1], L.om[1] - pj.y);
+    r[2] = DIM == 3 ? fmaf(row.dz1, I.f_cs[2], L.om[2] - pj.z) : 0.0f;
     return (uint32_t)(dcx + 1) + row.code;
 }
 
@@ -291,16 +291,13 @@ __device__ __forceinline__ void list_pair_r(const IC& I, const Lane<float>& L, c
                                             uint32_t e, float r[3])
 {
     // c = (dx + 1) + 3 (dy + 1) + 9 (dz + 1) < 27: c / 9 = (57 c) >> 9 and, for the
-    // remainder m < 9, m / 3 = (11 m) >> 5 (exact on these ranges)
+    // remainder m < 9, m / 3 = (11 m) >> 5 (exact on these ranges; 24-bit multiplies)
     const uint32_t c = (e >> kIdxBits) & kCodeMask;
-    const uint32_t cz = (c * 57u) >> 9, m = c - 9u * cz;
-    const uint32_t cy = (m * 11u) >> 5, cx = m - 3u * cy;
-    const float dx = (float)((int)cx - 1);
-    const float dy = (float)((int)cy - 1);
-    const float dz = (float)((int)cz - 1);
-    r[0] = fmaf(dx, I.f_cs[0], L.o[0] - pj.x);
-    r[1] = fmaf(dy, I.f_cs[1], L.o[1] - pj.y);
-    r[2] = DIM == 3 ? fmaf(dz, I.f_cs[2], L.o[2] - pj.z) : 0.0f;
+    const uint32_t cz = __umul24(c, 57u) >> 9, m = c - __umul24(cz, 9u);
+    const uint32_t cy = __umul24(m, 11u) >> 5, cx = m - __umul24(cy, 3u);
+    r[0] = fmaf((float)cx, I.f_cs[0], L.om[0] - pj.x);
+    r[1] = fmaf((float)cy, I.f_cs[1], L.om[1] - pj.y);
+    r[2] = DIM == 3 ? fmaf((float)cz, I.f_cs[2], L.om[2] - pj.z) : 0.0f;
 }
 
 template <class R, class IC> __device__ __forceinline__ R cut2_of(const IC& I)
@@ -348,8 +345,8 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
             Row<R> row;
             row.base = I.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)I.nc[1] * (uint32_t)cz);
             row.code = 3u * (uint32_t)(1 - dy) + 9u * (uint32_t)(1 - dz);
-            row.dy = (float)(-dy);
-            row.dz = (float)(-dz);
+            row.dy1 = (float)(1 - dy);
+            row.dz1 = (float)(1 - dz);
             // runs [a, b) and, per run, dcx = db - (k >= m0) - (k >= m1): m0 and m1 are
             // the starts of i's cell and the next where the run reaches them
             uint32_t a0, b0, a1 = 0, b1 = 0, m00, m01 = ~0u, m10 = ~0u, m11 = ~0u;
