@@ -356,9 +356,9 @@ void enqueue_build(sphx_ctx* c)
     launch_build(c->dev, c->launch, c->stream);
 }
 
-void enqueue_rates(sphx_ctx* c, bool star, bool reduce)
+void enqueue_rates(sphx_ctx* c, bool star, bool reduce, bool colour = true)
 {
-    {
+    if (colour) {
         Timed t(c, SPHX_PH_COLOUR);
         launch_colour(c->dev, star, c->launch, c->stream);
     }
@@ -388,8 +388,12 @@ void enqueue_renorm(sphx_ctx* c, bool force)
 void enqueue_step(sphx_ctx* c)
 {
     enqueue_build(c);
-    enqueue_renorm(c, false);
-    enqueue_rates(c, false, true);
+    {
+        // Eq. (7) when due, then the derive pass and the colour pass at S^n in one launch
+        Timed t(c, SPHX_PH_RENORM);
+        launch_renorm_colour(c->dev, c->launch, c->stream);
+    }
+    enqueue_rates(c, false, true, false);
     enqueue_integrate(c, 0.0);
 }
 

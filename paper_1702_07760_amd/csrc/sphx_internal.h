@@ -11,7 +11,9 @@ constexpr int kMaxPiston = 16;
 // Status word bits (sticky, set by kernels with atomicOr).
 enum : uint32_t { ST_NONFINITE = 1u, ST_DOMAIN = 2u, ST_DT = 4u, ST_STALL = 8u };
 
-// Particle info word: phase in bit 0, kind in bits 1-2, instance in bits 8-31.
+// Particle info word: phase in bit 0, kind in bits 1-2, instance in bits 8-31; bit 7
+// marks, from one list build to the next, a particle of the colour-pass list.
+constexpr uint32_t kInfoColour = 0x80u;
 __host__ __device__ inline uint32_t info_phase(uint32_t w) { return w & 1u; }
 __host__ __device__ inline uint32_t info_kind(uint32_t w) { return (w >> 1) & 3u; }
 __host__ __device__ inline uint32_t info_inst(uint32_t w) { return w >> 8; }
@@ -137,10 +139,11 @@ void launch_nlist(const Dev& d, const Launch& L, hipStream_t s);     // list of 
 void launch_renorm(const Dev& d, bool force, const Launch& L, hipStream_t s);
 void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s);
 void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hipStream_t s);
-void launch_predict(const Dev& d, double dt_override, const Launch& L, hipStream_t s);   // with a9
 void launch_correct(const Dev& d, const Launch& L, hipStream_t s);
 void launch_derive(const Dev& d, const Launch& L, hipStream_t s);
 void launch_restore(const Dev& d, hipStream_t s);
+void launch_renorm_colour(const Dev& d, const Launch& L, hipStream_t s);   // Eq. (7), derive + colour at S^n
+void launch_predict(const Dev& d, double dt_override, const Launch& L, hipStream_t s);   // a9 and S*
 // neighbour export: counts (pass 0) or ids (pass 1) in sorted order
 void launch_export(const Dev& d, int pass, const uint32_t* off, uint32_t* out,
                    const Launch& L, hipStream_t s);

@@ -324,9 +324,9 @@ template <> struct StencilBatch<double> { static constexpr int U = 4; };
 // batch.  With ALL, the lanes of a group step through each run together and the body
 // is called for every candidate slot with a flag `in` (a candidate j != i within the
 // cutoff), so that the group can rank its accepted candidates with a ballot.
-template <class R, int DIM, int P = 1, int U = StencilBatch<R>::U, bool ALL = false, class IC, class Body>
+template <class R, int DIM, int P = 1, int U = StencilBatch<R>::U, bool ALL = false, class IC, class PS, class Body>
 __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __restrict__ cstart,
-                                              const Sorted& O, const R4<R>* __restrict__ pos, uint32_t i,
+                                              const Sorted& O, const PS& pos, uint32_t i,
                                               const Lane<R>& L, R cut2, uint32_t sub, Body&& body)
 {
     const uint32_t* __restrict__ infos = O.info;
@@ -440,7 +440,8 @@ struct NoExtra {};
 // cap of a 1024-thread block (128) makes the force pass spill.
 template <class R> struct MaxBlock { static constexpr int value = 256; };
 
-// Visit the entries of i's neighbour list with |r_ij|^2 < 4h^2 at the positions `pos`:
+// Visit the entries of i's neighbour list with |r_ij|^2 < 4h^2 at the positions `pos`
+// (an array of records, or anything that gives particle k's record as pos[k]):
 // body(j, r_ij, |r_ij|^2, record of j, phase of j, load(j)).  Entries are stored column-major
 // (entry q of particle i at q * n + i), so a wave reads them coalesced; U entries are
 // fetched per batch so that their loads are in flight together.  With P lanes per
@@ -448,10 +449,12 @@ template <class R> struct MaxBlock { static constexpr int value = 256; };
 // same for all lanes and the lane part sub n + i is fixed.  A batch may read entries
 // past cnt (never past the capacity, a multiple of U P); they are replaced by a valid
 // index and skipped.
-template <class R, int DIM, int U, int P, class IC, class Load, class Body>
-__device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>* __restrict__ pos,
+// With SKIP, entries of phase skip_phase (known from the entry) are passed over before
+// anything of them is read.
+template <class R, int DIM, int U, int P, bool SKIP = false, class IC, class PS, class Load, class Body>
+__device__ __forceinline__ void for_list(const Dev& d, const IC& I, const PS& pos,
                                          uint32_t i, const Lane<R>& L, uint32_t cnt, uint32_t sub,
-                                         Load&& load, Body&& body)
+                                         Load&& load, Body&& body, uint32_t skip_phase = 0)
 {
     static_assert(kListCap2 % (U * P) == 0 && kListCap3 % (U * P) == 0,
                   "a batch of U entries on P lanes must divide the list capacity");
@@ -472,15 +475,22 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
     }
     for (uint32_t t0 = 0; t0 * P + sub < cnt; t0 += U) {
         uint32_t e[U];
+        bool ok[U];
         R4<R> pj[U];
         X x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) e[u] = (t0 + (uint32_t)u) * P + sub < cnt ? nxt[u] : 0u;
+        for (int u = 0; u < U; ++u) {
+            const bool in = (t0 + (uint32_t)u) * P + sub < cnt;
+            e[u] = in ? nxt[u] : 0u;
+            ok[u] = SKIP ? in && entry_phase(e[u]) != skip_phase : in;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t k = e[u] & kIdxMask;
-            pj[u] = pos[k];
-            x[u] = load(k);
+            if (!SKIP || ok[u]) {
+                pj[u] = pos[k];
+                x[u] = load(k);
+            }
         }
         if ((t0 + U) * P + sub < cnt) {
 #pragma unroll
@@ -488,7 +498,7 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if ((t0 + (uint32_t)u) * P + sub < cnt) {
+            if (ok[u]) {
                 R r[3];
                 list_pair_r<DIM>(I, L, pj[u], e[u], r);
                 const R r2 = dist2<DIM>(r[0], r[1], r[2]);
@@ -501,14 +511,14 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const R4<R>*
 // Either the list (normal case) or, for a particle whose list overflowed, the stencil.
 // The stencil fallback is rare and walks one candidate at a time: batching it would
 // raise the register count, and so lower the occupancy, of the common list path.
-template <class R, int DIM, int U, int P, class IC, class Load, class Body>
+template <class R, int DIM, int U, int P, bool SKIP = false, class IC, class PS, class Load, class Body>
 __device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, const Sorted& O,
-                                                  const R4<R>* __restrict__ pos, uint32_t i, const Lane<R>& L,
-                                                  uint32_t sub, Load&& load, Body&& body)
+                                                  const PS& pos, uint32_t i, const Lane<R>& L,
+                                                  uint32_t sub, Load&& load, Body&& body, uint32_t skip_phase = 0)
 {
     const uint32_t cnt = d.nbc[i];
     if (cnt <= d.cap) {
-        for_list<R, DIM, U, P>(d, I, pos, i, L, cnt, sub, load, body);
+        for_list<R, DIM, U, P, SKIP>(d, I, pos, i, L, cnt, sub, load, body, skip_phase);
     } else {
         for_neighbors<R, DIM, P, 1>(I, d.cstart, O, pos, i, L, cut2_of<R>(I), sub,
                                  [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t phj, uint32_t) {
@@ -702,12 +712,11 @@ __global__ void k_scan_reduce(const uint32_t* __restrict__ gate, const uint32_t*
     scan_reduce_tile(in, n, sums, blockIdx.x);
 }
 
-// Pass 2 (one block): exclusive scan of the tile sums.
-__device__ __forceinline__ void scan_top_block(const Dev& d, uint32_t* __restrict__ sums, uint32_t ntiles)
+// After every hash block has taken the decision (one block): the gathered copy becomes
+// the current state set (the rest of the build reads the old one through prevp), and
+// the decision's inputs are reset.
+__device__ __forceinline__ void flip_and_reset(const Dev& d)
 {
-    // every hash block has taken the decision: the gathered copy becomes the current
-    // state set (the rest of the build reads the old one through prevp), and the
-    // decision's inputs are reset
     if (threadIdx.x == 0) {
         *d.prevp = *d.curp;
         *d.curp = 1 - *d.curp;
@@ -718,6 +727,22 @@ __device__ __forceinline__ void scan_top_block(const Dev& d, uint32_t* __restric
         d.run[b].disp2 = 0ull;
         d.run[b].builds += 1;
     }
+}
+
+// Sum of the tile sums before tile t (the whole block takes part).
+__device__ __forceinline__ uint32_t tile_prefix(const uint32_t* __restrict__ sums, uint32_t t)
+{
+    uint32_t v = 0;
+    for (uint32_t u = threadIdx.x; u < t; u += blockDim.x) v += sums[u];
+    uint32_t total;
+    block_exclusive_scan(v, total);
+    return total;
+}
+
+// Pass 2 (one block): exclusive scan of the tile sums, in place.
+__device__ __forceinline__ void scan_top_block(const Dev& d, uint32_t* __restrict__ sums, uint32_t ntiles)
+{
+    flip_and_reset(d);
     // one block; each thread owns a run of ceil(ntiles / 256) tile sums
     const uint32_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint32_t a = threadIdx.x * per;
@@ -740,10 +765,10 @@ __global__ void k_scan_top(Dev d, uint32_t* __restrict__ sums, uint32_t ntiles)
     scan_top_block(d, sums, ntiles);
 }
 
-// Pass 3 for one tile: writes cstart[0..n] and clears the counters for the next build.
-__device__ __forceinline__ void scan_down_tile(uint32_t* __restrict__ cnt, uint32_t n,
-                                               const uint32_t* __restrict__ sums, uint32_t* __restrict__ out,
-                                               uint32_t tile)
+// Pass 3 for one tile, whose cells start at `prefix`: writes cstart[0..n] and clears
+// the counters for the next build.
+__device__ __forceinline__ void scan_down_tile(uint32_t* __restrict__ cnt, uint32_t n, uint32_t prefix,
+                                               uint32_t* __restrict__ out, uint32_t tile)
 {
     const uint32_t base = tile * SCAN_TILE + threadIdx.x * SCAN_ITEMS;
     uint32_t v[SCAN_ITEMS];
@@ -753,7 +778,7 @@ __device__ __forceinline__ void scan_down_tile(uint32_t* __restrict__ cnt, uint3
         s += v[j];
     }
     uint32_t total;
-    uint32_t run = block_exclusive_scan(s, total) + sums[tile];
+    uint32_t run = block_exclusive_scan(s, total) + prefix;
     for (int j = 0; j < SCAN_ITEMS; ++j) {
         const uint32_t idx = base + j;
         if (idx < n) {
@@ -769,7 +794,7 @@ __global__ void k_scan_down(const uint32_t* __restrict__ gate, uint32_t* __restr
                             const uint32_t* __restrict__ sums, uint32_t* __restrict__ out)
 {
     if (!*gate) return;
-    scan_down_tile(cnt, n, sums, out, blockIdx.x);
+    scan_down_tile(cnt, n, sums[blockIdx.x], out, blockIdx.x);
 }
 
 // Provisional scatter into the cell's segment (a slot outside [0, n) can only follow a
@@ -870,7 +895,11 @@ __device__ __forceinline__ void nlist_one(const Dev& d, uint32_t i, uint32_t sub
                 cnt += (uint32_t)__popc(grp);
             });
         const bool gother = ((uint32_t)(__ballot(other) >> gbase) & gmask) != 0u;
-        if (sub == 0) d.nbc[i] = cnt;
+        if (sub == 0) {
+            d.nbc[i] = cnt;
+            const uint32_t f = O.info[i];
+            O.info[i] = gother ? (f | kInfoColour) : (f & ~kInfoColour);
+        }
         const bool append = sub == 0 && gother;
         const unsigned long long m = __ballot(append);
         const int leader = __ffsll((long long)m) - 1;
@@ -965,23 +994,24 @@ __global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_
     if (!build_decision(d)) return;
     const uint32_t n = d.n, T = gridDim.x * blockDim.x;
     const int old = *d.curp;   // the scan's middle pass flips the current set
-    // this launch's barrier epochs are base + 1 .. base + 6; block 0 advances the base
+    // this launch's barrier epochs are base + 1 .. base + 5; block 0 advances the base
     // after the last barrier, when every block has read it
     const unsigned base = __hip_atomic_load(&d.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n; b0 += T) hash_phase<R, DIM>(d, old, b0 + threadIdx.x);
     if (!grid_sync(d, base + 1)) return;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) scan_reduce_tile(d.cnt, d.ncell, d.scan_tmp, t);
     if (!grid_sync(d, base + 2)) return;
-    if (blockIdx.x == 0) scan_top_block(d, d.scan_tmp, ntiles);
+    // each tile sums the tile sums before it (few), so the scan needs no middle pass
+    if (blockIdx.x == 0) flip_and_reset(d);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x)
+        scan_down_tile(d.cnt, d.ncell, tile_prefix(d.scan_tmp, t), d.cstart, t);
     if (!grid_sync(d, base + 3)) return;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) scan_down_tile(d.cnt, d.ncell, d.scan_tmp, d.cstart, t);
-    if (!grid_sync(d, base + 4)) return;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) scatter_one(d, k);
-    if (!grid_sync(d, base + 5)) return;
+    if (!grid_sync(d, base + 4)) return;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) rank_one<R>(d, k, with_ref);
-    if (!grid_sync(d, base + 6)) return;
+    if (!grid_sync(d, base + 5)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0)
-        __hip_atomic_store(&d.bar[0], base + 6, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&d.bar[0], base + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t lanes = n * (uint32_t)kNlistLanes;
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < lanes; b0 += T) {
         const uint32_t t = b0 + threadIdx.x;
@@ -1211,6 +1241,98 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
 // capacity.
 constexpr int kColourLanes = 8, kColourBatch = 2;
 
+template <class R, class IC>
+__device__ __forceinline__ R v_of(const IC& I, uint32_t phase, R m, R stored)
+{
+    return (R)((double)m / rho_of<R>(I, phase, stored));
+}
+
+template <class R> struct MV { R a, b; };
+
+// Where the colour pass takes its state.  A source gives the positions (src.pos[k]),
+// what V_k needs, requested with the position (src.load(k)), V_k from that for a
+// neighbour of phase ph (src.vk), and V_i (src.vi).
+//
+// At a state whose derive pass has run: V from the velocity record (|w|).
+template <class R> struct ColourFromVel {
+    const R4<R>* pos;
+    const R4<R>* vel;
+    __device__ MV<R> load(uint32_t k) const { return MV<R>{fabs(vel[k].w), (R)0}; }
+    template <class IC> __device__ R vk(const IC&, uint32_t, const MV<R>& x) const { return x.a; }
+    template <class IC> __device__ R vi(const IC&, uint32_t i, uint32_t) const { return fabs(vel[i].w); }
+};
+
+// In the derive pass's own launch: V = m / rho from the density that pass derives from
+// (the renormalised one in rho_tmp, or the stored one in aux.w), with its arithmetic.
+template <class R> struct ColourFromRho {
+    const R4<R>* pos;
+    const R* aux;      // records of 4
+    const R* dens;     // density of k at dens[k * stride]
+    uint32_t stride;
+    bool umass;
+    __device__ MV<R> load(uint32_t k) const
+    {
+        return MV<R>{umass ? (R)0 : aux[4 * (size_t)k], dens[(size_t)k * stride]};
+    }
+    template <class IC> __device__ R vk(const IC& I, uint32_t ph, const MV<R>& x) const
+    {
+        R m;
+        if constexpr (sizeof(R) == 8) m = umass ? (ph ? I.mass[1] : I.mass[0]) : x.a;
+        else m = umass ? (ph ? I.f_mass[1] : I.f_mass[0]) : x.a;
+        return v_of<R>(I, ph, m, x.b);
+    }
+    template <class IC> __device__ R vi(const IC& I, uint32_t i, uint32_t ph) const
+    {
+        return v_of<R>(I, ph, aux[4 * (size_t)i], dens[(size_t)i * stride]);
+    }
+};
+
+// Eq. (16) for colour-list entry g on the P lanes of its group; writes the gradient and
+// the interface flag (the sign of V in the velocity record `vel_out`).  make_src(I)
+// gives the source for i's instance.
+template <class R, int DIM, class MakeSrc>
+__device__ __forceinline__ void colour_one(const Dev& d, int cur, uint32_t g, uint32_t sub, R4<R>* vel_out,
+                                           MakeSrc&& make_src)
+{
+    constexpr int P = kColourLanes;
+    const Sorted& O = d.O[cur];
+    R4<R>* gc = (R4<R>*)d.gc;
+    const uint32_t i = d.ilist[g];
+    const uint32_t info = O.info[i];
+    const uint32_t ph = info_phase(info);
+    R s[3] = {0, 0, 0};
+    R vi = 0;
+    per_instance(d, info_inst(info), [&](const InstU& I) {
+        const auto src = make_src(I, info);
+        Lane<R> L;
+        L.load(I, src.pos[i], O.key[i]);
+        vi = src.vi(I, i, ph);
+        // C_j^y = 1 only for the other phase: the list walk skips i's own phase
+        for_each_neighbor<R, DIM, kColourBatch, P, true>(d, I, O, src.pos, i, L, sub,
+            [&](uint32_t k) { return src.load(k); },
+            [&](uint32_t, const R* r, R r2, const R4<R>&, uint32_t phj, const MV<R>& x) {
+                if (phj == ph) return;                           // (the stencil fallback)
+                const R vk = src.vk(I, phj, x);                  // V_k = 1 / sigma_k
+                const R f = kernel_f<R>(I, r2) * (vk * vk);
+                s[0] += f * r[0];
+                s[1] += f * r[1];
+                s[2] += f * r[2];
+            }, ph);
+    });
+    R g3[3];                                                     // sigma_i = 1 / V_i
+    g3[0] = group_sum<P>(s[0]) / vi;
+    g3[1] = group_sum<P>(s[1]) / vi;
+    g3[2] = group_sum<P>(s[2]) / vi;
+    const R gn = sqrt(g3[0] * g3[0] + g3[1] * g3[1] + g3[2] * g3[2]);
+    if (sub == 0) {
+        R4<R> out;
+        out.x = g3[0]; out.y = g3[1]; out.z = g3[2]; out.w = gn;
+        gc[i] = out;
+        R* vw = (R*)vel_out + 4 * (size_t)i + 3;
+        *vw = gn > 0 ? -vi : vi;          // interface flag: the sign of V in the velocity record
+    }
+}
+
 template <class R, int DIM>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
 {
@@ -1219,46 +1341,59 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
     const uint32_t count = *d.icount;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t sub = t % P, stride = gridDim.x * blockDim.x / P;
-    const Sorted& O = d.O[cur];
     const StateSet& S = star ? d.star : d.S[cur];
-    R4<R>* gc = (R4<R>*)d.gc;
-    const R4<R>* pos = (const R4<R>*)S.pos;
-    R4<R>* vel = (R4<R>*)S.vel;
-    for (uint32_t g = t / P; g < count; g += stride) {
-        const uint32_t i = d.ilist[g];
-        const R4<R> pi = pos[i];
-        const uint32_t info = O.info[i];
-        const uint32_t ph = info_phase(info);
-        R s[3] = {0, 0, 0};
-        per_instance(d, info_inst(info), [&](const InstU& I) {
-            Lane<R> L;
-            L.load(I, pi, O.key[i]);
-            // V_k is requested with the position, not after it: one wait per batch
-            for_each_neighbor<R, DIM, kColourBatch, P>(d, I, O, pos, i, L, sub,
-                [&](uint32_t k) { return fabs(vel[k].w); },
-                [&](uint32_t, const R* r, R r2, const R4<R>&, uint32_t phj, R vk) {
-                    if (phj == ph) return;                       // C_j^y = 1 only for the other phase
-                    // vk = V_k = 1 / sigma_k
-                    const R f = kernel_f<R>(I, r2) * (vk * vk);
-                    s[0] += f * r[0];
-                    s[1] += f * r[1];
-                    s[2] += f * r[2];
-                });
+    for (uint32_t g = t / P; g < count; g += stride)
+        colour_one<R, DIM>(d, cur, g, sub, (R4<R>*)S.vel, [&](const InstU&, uint32_t) {
+            return ColourFromVel<R>{(const R4<R>*)S.pos, (const R4<R>*)S.vel};
         });
-        const R vi = fabs(vel[i].w);                             // sigma_i = 1 / V_i
-        R g3[3];
-        g3[0] = group_sum<P>(s[0]) / vi;
-        g3[1] = group_sum<P>(s[1]) / vi;
-        g3[2] = group_sum<P>(s[2]) / vi;
-        const R gn = sqrt(g3[0] * g3[0] + g3[1] * g3[1] + g3[2] * g3[2]);
-        if (sub == 0) {
-            R4<R> out;
-            out.x = g3[0]; out.y = g3[1]; out.z = g3[2]; out.w = gn;
-            gc[i] = out;
-            R* vw = (R*)vel + 4 * (size_t)i + 3;
-            *vw = gn > 0 ? -vi : vi;          // interface flag: the sign of V in the velocity record
-        }
+}
+
+// The derive pass after Eq. (7) and the colour pass at S^n in one launch: the first
+// cblocks blocks walk the colour list (their V values come from the density the derive
+// pass reads, so they need none of its writes), the rest derive.  Only the colour
+// blocks write V, with its sign, for the particles of the colour list.
+template <class R, int DIM>
+__global__ void __launch_bounds__(256) k_derive_colour(Dev d, int force, uint32_t cblocks)
+{
+    const int cur = *d.curp;
+    const bool fresh = force || renorm_due(d);
+    if (blockIdx.x < cblocks) {
+        constexpr int P = kColourLanes;
+        const uint32_t count = *d.icount;
+        const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+        const uint32_t sub = t % P, stride = cblocks * blockDim.x / P;
+        const StateSet& S = d.S[cur];
+        const R* aux = (const R*)S.aux;
+        // the density derived from: renormalised (rho_tmp) or stored (aux.w)
+        const R* dens = fresh ? (const R*)d.rho_tmp : aux + 3;
+        const uint32_t dstride = fresh ? 1u : 4u;
+        for (uint32_t g = t / P; g < count; g += stride)
+            colour_one<R, DIM>(d, cur, g, sub, (R4<R>*)S.vel, [&](const InstU& I, uint32_t) {
+                return ColourFromRho<R>{(const R4<R>*)S.pos, aux, dens, dstride, I.umass != 0};
+            });
+        return;
     }
+    const uint32_t k = (blockIdx.x - cblocks) * blockDim.x + threadIdx.x;
+    if (k == 0) d.flags[2] = 0u;
+    if (k >= d.n) return;
+    const StateSet& S = d.S[cur];
+    if (!fresh) {
+        ((R*)S.pos)[4 * (size_t)k + 3] = ((const R*)S.aux)[4 * (size_t)k + 1];
+        return;
+    }
+    const uint32_t info = d.O[cur].info[k];
+    const InstDev& I = d.inst[info_inst(info)];
+    R4<R> aux = ((R4<R>*)S.aux)[k];
+    const R r = ((const R*)d.rho_tmp)[k];
+    R V, mA;
+    derive_values<R>(I, info_phase(info), r, aux.x, V, mA);
+    ((R*)S.pos)[4 * (size_t)k + 3] = mA;
+    if (!(info & kInfoColour)) ((R*)S.vel)[4 * (size_t)k + 3] = V;
+    aux.y = mA;
+    aux.z = V;
+    aux.w = r;
+    ((R4<R>*)S.aux)[k] = aux;
+    if constexpr (sizeof(R) == 4) S.plo[k].w = 0.0f;
 }
 
 // ------------------------------------------ Eqs. (6), (8), (10)/(11), (17) (pass B)
@@ -1526,11 +1661,11 @@ __device__ __forceinline__ double step_dt(const Dev& d, uint32_t b, double dt_ov
     return dt;
 }
 
-// Store each instance's step (grid-stride over instances; run by the predictor).
-__device__ __forceinline__ void store_steps(const Dev& d, double dt_override)
+// Store each instance's step (run by the predictor's threads t0 of nthr, stride over
+// instances).
+__device__ __forceinline__ void store_steps(const Dev& d, double dt_override, uint32_t t0, uint32_t nthr)
 {
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < (uint32_t)d.ninst; b += stride) {
+    for (uint32_t b = t0; b < (uint32_t)d.ninst; b += nthr) {
         double umax;
         const double dt = step_dt(d, b, dt_override, umax);
         // the corrector reuses the cells of S^n: every pair within 2h at the predicted
@@ -1596,41 +1731,67 @@ __device__ __forceinline__ void kahan_add(float& s, float& e, float y)
     s = t;
 }
 
+// The predictor's position update of particle k (kind from its info word): fluid
+// particles move by hdt u, moving ones follow the piston, walls stay.
+template <class R, int DIM>
+__device__ __forceinline__ void advance_pos(const Dev& d, int cur, uint32_t k, uint32_t kind, const InstDev& I,
+                                            uint32_t b, double hdt, R4<R>& p, R4<R>& v)
+{
+    if (kind == K_FLUID) {
+        if constexpr (sizeof(R) == 8) {
+            p.x = wrap_coord(fma(hdt, v.x, p.x), I, 0);
+            p.y = wrap_coord(fma(hdt, v.y, p.y), I, 1);
+            p.z = DIM == 3 ? wrap_coord(fma(hdt, v.z, p.z), I, 2) : p.z;
+        } else {
+            const R h = (R)hdt;
+            p.x = fmaf(h, v.x, p.x); p.y = fmaf(h, v.y, p.y); p.z = fmaf(h, v.z, p.z);
+        }
+    } else if (kind == K_MOVING) {
+        moving_state<R>(I, d.O[cur].ref[k], d.O[cur].key[k], d.run[b].t + hdt, p, v);
+    }
+}
+
+// Density (stored form) at S*: rho^n + (dt/2) D rho^n.
+template <class R>
+__device__ __forceinline__ R pred_rho(R stored, double hdt, R rate)
+{
+    return fma((R)hdt, rate, stored);
+}
+
+// S* for particle k (no writes).
+template <class R, int DIM>
+__device__ __forceinline__ void predict_state(const Dev& d, int cur, uint32_t k, uint32_t info, const InstDev& I,
+                                              double hdt, R4<R>& p, R4<R>& v, R4<R>& x)
+{
+    const StateSet& S = d.S[cur];
+    const uint32_t b = info_inst(info);
+    p = ((const R4<R>*)S.pos)[k];
+    v = ((const R4<R>*)S.vel)[k];
+    x = ((const R4<R>*)S.aux)[k];
+    const R4<R> a = ((const R4<R>*)d.acc)[k];
+    const uint32_t kind = info_kind(info);
+    advance_pos<R, DIM>(d, cur, k, kind, I, b, hdt, p, v);
+    if (kind == K_FLUID) {
+        const R h = (R)hdt;
+        v.x += h * a.x; v.y += h * a.y; v.z += h * a.z;
+    }
+    derive_one<R>(I, info_phase(info), pred_rho<R>(x.w, hdt, a.w), p, v, x, false);
+}
+
 // S* = S^n + dt/2 R(S^n)
 template <class R, int DIM>
 __global__ void k_predict(Dev d, double dt_override)
 {
-    store_steps(d, dt_override);
     const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    store_steps(d, dt_override, k, gridDim.x * blockDim.x);
     if (k >= d.n) return;
-    const Sorted& O = d.O[cur];
-    const StateSet& S = d.S[cur];
-    const uint32_t info = O.info[k];
+    const uint32_t info = d.O[cur].info[k];
     const uint32_t b = info_inst(info);
-    const InstDev& I = d.inst[b];
     double umax;
     const double hdt = 0.5 * step_dt(d, b, dt_override, umax);
-    const uint32_t kind = info_kind(info);
-    R4<R> p = ((const R4<R>*)S.pos)[k];
-    R4<R> v = ((const R4<R>*)S.vel)[k];
-    R4<R> x = ((const R4<R>*)S.aux)[k];
-    const R4<R> a = ((const R4<R>*)d.acc)[k];
-    const R h = (R)hdt;
-    if (kind == K_FLUID) {
-        if constexpr (sizeof(R) == 8) {
-            p.x = wrap_coord(p.x + hdt * v.x, I, 0);
-            p.y = wrap_coord(p.y + hdt * v.y, I, 1);
-            p.z = DIM == 3 ? wrap_coord(p.z + hdt * v.z, I, 2) : p.z;
-        } else {
-            p.x += h * v.x; p.y += h * v.y; p.z += h * v.z;
-        }
-        v.x += h * a.x; v.y += h * a.y; v.z += h * a.z;
-    } else if (kind == K_MOVING) {
-        moving_state<R>(I, O.ref[k], O.key[k], d.run[b].t + hdt, p, v);
-    }
-    const R r = x.w + h * a.w;
-    derive_one<R>(I, info_phase(info), r, p, v, x, false);
+    R4<R> p, v, x;
+    predict_state<R, DIM>(d, cur, k, info, d.inst[b], hdt, p, v, x);
     ((R4<R>*)d.star.pos)[k] = p;
     ((R4<R>*)d.star.vel)[k] = v;
     ((R4<R>*)d.star.aux)[k] = x;
@@ -1850,6 +2011,18 @@ void launch_restore(const Dev& d, hipStream_t s)
     }));
 }
 
+void launch_renorm_colour(const Dev& d, const Launch& L, hipStream_t s)
+{
+    const dim3 grid(blocks_for(d.n * L.lanes, L.block)), block(L.block);
+    // colour blocks: the list length is known only on the device (grid-stride)
+    const unsigned cb = std::min<unsigned>(blocks_for(d.n * kColourLanes, 256), 1024u);
+    const unsigned db = blocks_for(d.n, 256);
+    SPHX_DISPATCH(d.precision, d.dim, ({
+        SPHX_LANES(L.lanes, ({ hipLaunchKernelGGL((k_renorm<R, D, P>), grid, block, 0, s, d, L.xcd_remap, 0); }));
+        hipLaunchKernelGGL((k_derive_colour<R, D>), dim3(cb + db), dim3(256), 0, s, d, 0, cb);
+    }));
+}
+
 void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s)
 {
     // grid-stride over the colour list, whose length is known only on the device
@@ -1881,6 +2054,7 @@ void launch_predict(const Dev& d, double dt_override, const Launch&, hipStream_t
         hipLaunchKernelGGL((k_predict<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, dt_override);
     }));
 }
+
 
 void launch_correct(const Dev& d, const Launch&, hipStream_t s)
 {
