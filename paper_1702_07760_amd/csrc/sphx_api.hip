@@ -356,6 +356,8 @@ void enqueue_build(sphx_ctx* c)
     launch_build(c->dev, c->launch, c->stream);
 }
 
+// The rates at S^n (colour unless done already, force with the time-step maxima) or at
+// S* (colour, force and, in the same launch, the corrector that ends the step).
 void enqueue_rates(sphx_ctx* c, bool star, bool reduce, bool colour = true)
 {
     if (colour) {
@@ -363,7 +365,7 @@ void enqueue_rates(sphx_ctx* c, bool star, bool reduce, bool colour = true)
         launch_colour(c->dev, star, c->launch, c->stream);
     }
     Timed t(c, SPHX_PH_FORCE);
-    launch_force(c->dev, star, reduce, c->launch, c->stream);
+    launch_force(c->dev, star, reduce, star, c->launch, c->stream);
 }
 
 void enqueue_integrate(sphx_ctx* c, double dt_override)
@@ -372,9 +374,7 @@ void enqueue_integrate(sphx_ctx* c, double dt_override)
         Timed t(c, SPHX_PH_INTEGRATE);
         launch_predict(c->dev, dt_override, c->launch, c->stream);   // a9 inside
     }
-    enqueue_rates(c, true, false);
-    Timed t(c, SPHX_PH_INTEGRATE);
-    launch_correct(c->dev, c->launch, c->stream);   // ends the step
+    enqueue_rates(c, true, false);   // the corrector runs in the force launch at S*
 }
 
 void enqueue_renorm(sphx_ctx* c, bool force)

@@ -138,8 +138,7 @@ void launch_build(const Dev& d, const Launch& L, hipStream_t s);     // decide, 
 void launch_nlist(const Dev& d, const Launch& L, hipStream_t s);     // list of the current order
 void launch_renorm(const Dev& d, bool force, const Launch& L, hipStream_t s);
 void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s);
-void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hipStream_t s);
-void launch_correct(const Dev& d, const Launch& L, hipStream_t s);
+void launch_force(const Dev& d, bool star, bool reduce_max, bool correct, const Launch& L, hipStream_t s);
 void launch_derive(const Dev& d, const Launch& L, hipStream_t s);
 void launch_restore(const Dev& d, hipStream_t s);
 void launch_renorm_colour(const Dev& d, const Launch& L, hipStream_t s);   // Eq. (7), derive + colour at S^n

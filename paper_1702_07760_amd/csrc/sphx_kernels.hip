@@ -1582,7 +1582,27 @@ __device__ __forceinline__ void force_reduce(const Dev& d, bool valid, uint32_t 
     }
 }
 
-template <class R, int DIM, int P, bool REDUCE, bool TERMS>
+template <class R, int DIM>
+__device__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst);
+__device__ void finish_steps(const Dev& d);
+
+// Running maximum, per instance, of the displacement since the last build (one atomic
+// per wave when the wave lies in one instance).
+__device__ __forceinline__ void disp_reduce(const Dev& d, bool mine, uint32_t b, double moved2)
+{
+    const uint32_t b0 = __shfl(b, 0, 64);
+    if (__all(!mine || b == b0)) {
+        const double m = wave_max(moved2);
+        if ((threadIdx.x & 63) == 0) max_update(&d.run[b0].disp2, m);
+    } else if (mine) {
+        max_update(&d.run[b].disp2, moved2);
+    }
+}
+
+// With CORRECT (the pass at S*), each particle's corrector follows its rates in the same
+// launch: it reads and writes only that particle's records of S^n and reads its own
+// S* velocity and rates, while the force pass at S* reads S* records only.
+template <class R, int DIM, int P, bool REDUCE, bool TERMS, bool CORRECT>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, int remap)
 {
     const int cur = *d.curp;
@@ -1636,6 +1656,14 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
         });
     }
     force_reduce<REDUCE>(d, valid, inst, nint, umag2, amag2);
+    if constexpr (CORRECT) {
+        finish_steps(d);
+        const bool mine = valid && sub == 0;
+        double moved2 = 0.0;
+        uint32_t b = 0;
+        if (mine) moved2 = correct_one<R, DIM>(d, cur, i, b);
+        disp_reduce(d, mine, b, moved2);
+    }
 }
 
 // ----------------------------------------------------------- time step (a9)
@@ -1678,7 +1706,7 @@ __device__ __forceinline__ void store_steps(const Dev& d, double dt_override, ui
 
 // End of a step (grid-stride over instances; run by the corrector, whose particle
 // updates read dt and t_next only).
-__device__ __forceinline__ void finish_steps(const Dev& d)
+__device__ void finish_steps(const Dev& d)
 {
     const uint32_t t0 = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
     if (t0 == 0) d.flags[2] = 1u;   // the corrector leaves q in pos.w
@@ -1800,7 +1828,7 @@ __global__ void k_predict(Dev d, double dt_override)
 // S^{n+1} = S^n + dt R(S*), in place
 // Corrector for one particle; returns |x - x_build|^2 and its instance.
 template <class R, int DIM>
-__device__ __forceinline__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst)
+__device__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst)
 {
     const Sorted& O = d.O[cur];
     const StateSet& S = d.S[cur];
@@ -1858,26 +1886,6 @@ __device__ __forceinline__ double correct_one(const Dev& d, int cur, uint32_t k,
     return ex * ex + ey * ey + ez * ez;
 }
 
-
-template <class R, int DIM>
-__global__ void k_correct(Dev d)
-{
-    const int cur = *d.curp;
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    finish_steps(d);
-    const bool valid = k < d.n;
-    double moved2 = 0.0;
-    uint32_t b = 0;
-    if (valid) moved2 = correct_one<R, DIM>(d, cur, k, b);
-    // running maximum of the displacement since the last build, per instance
-    const uint32_t b0 = __shfl(b, 0, 64);
-    if (__all(!valid || b == b0)) {
-        const double m = wave_max(moved2);
-        if ((threadIdx.x & 63) == 0) max_update(&d.run[b0].disp2, m);
-    } else if (valid) {
-        max_update(&d.run[b].disp2, moved2);
-    }
-}
 
 // ------------------------------------------------------- neighbour export
 
@@ -2033,17 +2041,22 @@ void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s)
     }));
 }
 
-void launch_force(const Dev& d, bool star, bool reduce_max, const Launch& L, hipStream_t s)
+// The rates at S^n (with the time-step maxima) or, with `correct`, at S* followed by
+// the corrector.
+void launch_force(const Dev& d, bool star, bool reduce_max, bool correct, const Launch& L, hipStream_t s)
 {
     const int st = star ? 1 : 0;
     const dim3 grid(blocks_for(d.n * L.force_lanes, L.block)), block(L.block);
     SPHX_DISPATCH(d.precision, d.dim, SPHX_LANES(L.force_lanes, ({
-        if (L.debug_terms) {
-            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, P, true, true>), grid, block, 0, s, d, st, L.xcd_remap);
-            else hipLaunchKernelGGL((k_force<R, D, P, false, true>), grid, block, 0, s, d, st, L.xcd_remap);
+        if (correct) {
+            if (L.debug_terms) hipLaunchKernelGGL((k_force<R, D, P, false, true, true>), grid, block, 0, s, d, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, P, false, false, true>), grid, block, 0, s, d, st, L.xcd_remap);
+        } else if (L.debug_terms) {
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, P, true, true, false>), grid, block, 0, s, d, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, P, false, true, false>), grid, block, 0, s, d, st, L.xcd_remap);
         } else {
-            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, P, true, false>), grid, block, 0, s, d, st, L.xcd_remap);
-            else hipLaunchKernelGGL((k_force<R, D, P, false, false>), grid, block, 0, s, d, st, L.xcd_remap);
+            if (reduce_max) hipLaunchKernelGGL((k_force<R, D, P, true, false, false>), grid, block, 0, s, d, st, L.xcd_remap);
+            else hipLaunchKernelGGL((k_force<R, D, P, false, false, false>), grid, block, 0, s, d, st, L.xcd_remap);
         }
     })));
 }
@@ -2056,12 +2069,6 @@ void launch_predict(const Dev& d, double dt_override, const Launch&, hipStream_t
 }
 
 
-void launch_correct(const Dev& d, const Launch&, hipStream_t s)
-{
-    SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_correct<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d);
-    }));
-}
 
 void launch_export(const Dev& d, int pass, const uint32_t* off, uint32_t* out, const Launch&, hipStream_t s)
 {
