@@ -121,8 +121,10 @@ enum {
     SPHX_PH_BUILD = 0,        /* hash, scan, sort, gather, cell flags */
     SPHX_PH_RENORM = 1,       /* Eq. (7) and the state derivation after it */
     SPHX_PH_COLOUR = 2,       /* Eq. (16) pass */
-    SPHX_PH_FORCE = 3,        /* Eqs. (6), (8), (10)/(11), (17) pass */
-    SPHX_PH_INTEGRATE = 4,    /* time step, predictor, corrector */
+    SPHX_PH_FORCE = 3,        /* Eqs. (6), (8), (10)/(11), (17) pass at S^n (compute_forces, first
+                                 rate evaluation of a step) */
+    SPHX_PH_INTEGRATE = 4,    /* time step, predictor, and the launch that holds the rates at S*
+                                 and the corrector */
     SPHX_NPH = 5
 };
 

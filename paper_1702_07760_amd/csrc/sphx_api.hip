@@ -364,7 +364,9 @@ void enqueue_rates(sphx_ctx* c, bool star, bool reduce, bool colour = true)
         Timed t(c, SPHX_PH_COLOUR);
         launch_colour(c->dev, star, c->launch, c->stream);
     }
-    Timed t(c, SPHX_PH_FORCE);
+    // the launch at S* also holds the corrector: it is timed with the integrator, so the
+    // force group holds the pure force pass at S^n
+    Timed t(c, star ? SPHX_PH_INTEGRATE : SPHX_PH_FORCE);
     launch_force(c->dev, star, reduce, star, c->launch, c->stream);
 }
 
