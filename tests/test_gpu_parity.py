@@ -227,6 +227,21 @@ def test_one_launch_build_matches_seven_launches(name, prec):
     assert a.stats()["builds"] == b.stats()["builds"] > 1
 
 
+@pytest.mark.parametrize("every", [0, 3])
+@pytest.mark.parametrize("prec", PRECS)
+def test_steps_without_renormalisation_match_oracle(prec, every):
+    # Eq. (7) never (0) or every third step: the steps between take the derive and
+    # colour passes from the stored density and put m P / rho^2 back in the position record
+    s = inputs.drop2d(perturb=True).with_params(renorm_every=every)
+    print(f"case renorm_every={every} precision={prec}", flush=True)
+    o, sim = _one_step(s, prec, nsteps=5)
+    tol = TOL[prec]
+    assert rel_to(sim.get_field(binding.F_X), o.get(oracle.X), s.dx[0]) < tol
+    assert rel_to(sim.get_field(binding.F_RHO), o.get(oracle.RHO), 1000.0) < tol
+    umax = np.abs(o.get(oracle.U)).max()
+    assert rel_to(sim.get_field(binding.F_U), o.get(oracle.U), umax) < 10 * tol
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_checkpoint_round_trip_is_bit_identical(prec):
     s = inputs.drop2d(perturb=True)
