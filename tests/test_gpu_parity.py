@@ -243,6 +243,25 @@ def test_steps_without_renormalisation_match_oracle(prec, every):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_rates_after_steps_without_renormalisation(prec):
+    # compute_forces straight after steps: the position record still holds the
+    # renormalisation field and must get m P / rho^2 back before the force pass
+    s = inputs.drop2d(perturb=True)
+    o = oracle.Oracle(s)
+    o.step(3)
+    o.rates()
+    sim = binding.Sim(s, precision=prec)
+    sim.step(3)
+    sim.compute_forces()
+    tol = TOL[prec]
+    scale = o.get(oracle.SAP) + o.get(oracle.SAV) + o.get(oracle.SAS)
+    ea = enorm(sim.get_field(binding.F_A), o.get(oracle.A), scale)
+    ed = enorm(sim.get_field(binding.F_DRHO), o.get(oracle.DRHO), o.get(oracle.SDRHO))
+    print(f"rates after 3 steps: E-norm a {ea:.3e}, Drho {ed:.3e}", flush=True)
+    assert ea < tol and ed < tol
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_checkpoint_round_trip_is_bit_identical(prec):
     s = inputs.drop2d(perturb=True)
     a = binding.Sim(s, precision=prec)
