@@ -45,7 +45,9 @@ typedef enum {
     SPHX_E_STATE = 5,      /* call out of order (e.g. step before init_particles) */
     SPHX_E_NONFINITE = 6,  /* device: a rate or state value became NaN/Inf */
     SPHX_E_DOMAIN = 7,     /* device: a particle left a non-periodic domain */
-    SPHX_E_DT = 8          /* device: dt * max|u| exceeded half the neighbour skin */
+    SPHX_E_DT = 8,         /* device: dt * max|u| exceeded half the neighbour skin */
+    SPHX_E_STALL = 9       /* device: a grid barrier of the one-launch neighbour build timed
+                              out; the state is lost (see SPHX_OPT_ONE_LAUNCH_BUILD) */
 } sphx_status;
 
 typedef enum { SPHX_FP64 = 0, SPHX_FP32_CELLREL = 1 } sphx_precision;
@@ -108,12 +110,18 @@ enum {
     SPHX_OPT_FORCE_LANES = 7, /* the same for the force pass (default: 1 in FP32, 2 in FP64) */
     SPHX_OPT_PROFILE = 6,     /* 1: no graphs; every kernel group is bracketed by HIP events on the
                                  context stream and its time is reported in sphx_stats */
-    SPHX_OPT_ONE_LAUNCH_BUILD = 8 /* 1 (default): the neighbour build (cell sort and list) is one
+    SPHX_OPT_ONE_LAUNCH_BUILD = 8, /* 1 (default): the neighbour build (cell sort and list) is one
                                  launch, sized to the blocks the device holds at once, whose phases
                                  meet at grid barriers; without a rebuild it ends after the
                                  decision.  0: seven launches.  A barrier that waits too long (its
                                  blocks were not all resident, e.g. other work shared the device)
-                                 makes the next sphx_sync return SPHX_E_HIP and stops rebuilds */
+                                 stops that build part-way and every later one until the next
+                                 sphx_sync (or read-back call), which returns SPHX_E_STALL: the
+                                 state is then lost, the calls that step or read it return
+                                 SPHX_E_STATE until sphx_set_state or sphx_init_particles, and the
+                                 context builds with seven launches from then on */
+    SPHX_OPT_FORCE_STALL = 9  /* for tests of that recovery: 1..5 makes grid barrier 1..5 of the next
+                                 one-launch build time out at once (0: none, the default) */
 };
 
 /* Kernel groups timed under SPHX_OPT_PROFILE. */

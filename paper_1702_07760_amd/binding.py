@@ -24,9 +24,10 @@ _VEC = {F_X, F_U, F_A, F_AP, F_AV, F_AS, F_GRADC}
 OPT_DEBUG_TERMS, OPT_BLOCK, OPT_XCD_REMAP, OPT_GRAPH, OPT_LANES, OPT_PROFILE = 1, 2, 3, 4, 5, 6
 OPT_FORCE_LANES = 7
 OPT_ONE_LAUNCH_BUILD = 8
+OPT_FORCE_STALL = 9
 PHASES = ("build", "renorm", "colour", "force", "integrate")
 STATUS = {0: "SPHX_OK", 1: "SPHX_E_ARG", 2: "SPHX_E_NODEV", 3: "SPHX_E_HIP", 4: "SPHX_E_WORKSPACE",
-          5: "SPHX_E_STATE", 6: "SPHX_E_NONFINITE", 7: "SPHX_E_DOMAIN", 8: "SPHX_E_DT"}
+          5: "SPHX_E_STATE", 6: "SPHX_E_NONFINITE", 7: "SPHX_E_DOMAIN", 8: "SPHX_E_DT", 9: "SPHX_E_STALL"}
 
 
 class Params(C.Structure):
@@ -190,14 +191,7 @@ class Sim:
                     "sphx_bind_workspace")
         if not graph:
             self.set_option(OPT_GRAPH, 0)
-        x = np.ascontiguousarray(scene.x, np.float64)
-        u = np.ascontiguousarray(scene.u, np.float64)
-        rho = np.ascontiguousarray(scene.rho, np.float64)
-        m = np.ascontiguousarray(scene.m, np.float64)
-        ph = np.ascontiguousarray(scene.phase, np.uint8)
-        kd = np.ascontiguousarray(scene.kind, np.uint8)
-        self._check(lib().sphx_init_particles(self.ctx, _ptr(x), _ptr(u), _ptr(rho), _ptr(m),
-                                              _ptr(ph), _ptr(kd)), "sphx_init_particles")
+        self.init_particles()
 
     # -- plumbing
     def _check(self, st, where):
@@ -219,6 +213,18 @@ class Sim:
             pass
 
     # -- the C ABI, one method per entry point
+    def init_particles(self, scene=None):
+        """Upload a scene with this context's layout (default: the one it was made for)."""
+        scene = self.scene if scene is None else scene
+        x = np.ascontiguousarray(scene.x, np.float64)
+        u = np.ascontiguousarray(scene.u, np.float64)
+        rho = np.ascontiguousarray(scene.rho, np.float64)
+        m = np.ascontiguousarray(scene.m, np.float64)
+        ph = np.ascontiguousarray(scene.phase, np.uint8)
+        kd = np.ascontiguousarray(scene.kind, np.uint8)
+        self._check(lib().sphx_init_particles(self.ctx, _ptr(x), _ptr(u), _ptr(rho), _ptr(m),
+                                              _ptr(ph), _ptr(kd)), "sphx_init_particles")
+
     def build_neighbors(self):
         self._check(lib().sphx_build_neighbors(self.ctx), "sphx_build_neighbors")
 

@@ -29,6 +29,7 @@ struct sphx_ctx {
     Dev dev{};
     Launch launch{};
     bool bound = false, inited = false, rates_valid = false;
+    bool lost = false;   // a one-launch build stopped part-way: set_state or init_particles next
     bool has_moving = false;
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;    // one step; the state parity lives on the device
@@ -302,18 +303,34 @@ sphx_status status_of(sphx_ctx* c)
         const uint32_t zero = 0;
         HIP_OK(c, hipMemcpy(c->dev.status, &zero, sizeof zero, hipMemcpyHostToDevice));
     }
+    if (st & ST_STALL) {
+        // the build stopped between two phases: the sorted sets, the cell table and the
+        // list no longer agree.  Clear what the next build expects cleared (barrier words
+        // that may hold this launch's epochs, the cell counters) and build with seven
+        // launches from now on.
+        HIP_OK(c, hipMemset(c->dev.bar, 0, (512 + 4096) * sizeof(unsigned)));
+        HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * sizeof(uint32_t)));
+        c->launch.one_launch_build = false;
+        c->launch.stall_at = 0;
+        c->lost = true;
+        c->rates_valid = false;
+        drop_graphs(c);
+        return fail(c, SPHX_E_STALL, "a grid barrier of the one-launch neighbour build timed out (its blocks were "
+                                     "not all resident); the particle state is lost: restore it with set_state "
+                                     "or init_particles (builds use seven launches from now on)");
+    }
     if (st & ST_NONFINITE) return fail(c, SPHX_E_NONFINITE, "a rate or state value became non-finite");
     if (st & ST_DOMAIN) return fail(c, SPHX_E_DOMAIN, "a particle left a non-periodic domain");
     if (st & ST_DT) return fail(c, SPHX_E_DT, "dt * max|u| exceeded half the neighbour skin");
-    if (st & ST_STALL) {
-        // the barrier words may hold a half-finished launch's epochs: clear them and
-        // build with seven launches from now on
-        HIP_OK(c, hipMemset(c->dev.bar, 0, (512 + 4096) * sizeof(unsigned)));
-        c->launch.one_launch_build = false;
-        drop_graphs(c);
-        return fail(c, SPHX_E_HIP, "a grid barrier of the one-launch build timed out (its blocks were not all "
-                                   "resident); the context now builds with seven launches");
-    }
+    return SPHX_OK;
+}
+
+// The calls that step or read the particle state need one that is whole.
+sphx_status have_state(sphx_ctx* c)
+{
+    if (!c) return SPHX_E_ARG;
+    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (c->lost) return fail(c, SPHX_E_STATE, "the state was lost in a stalled build: set_state or init_particles");
     return SPHX_OK;
 }
 
@@ -736,17 +753,20 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemcpyAsync(d.O[0].key, key.data(), n * 4, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(d.O[0].id, id.data(), n * 4, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(d.O[0].info, info.data(), n * 4, hipMemcpyHostToDevice, s));
-    HIP_OK(c, hipMemcpyAsync(d.O[0].ref, ref.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
+    // the reference-position buffers as the workspace lays them out (an earlier init may
+    // have switched them off)
+    Dev lay{};
+    carve(lay, c->ws, c->precision, c->dim, c->n, c->ncell, c->ninst);
+    HIP_OK(c, hipMemcpyAsync(lay.O[0].ref, ref.data(), n * sizeof(double4), hipMemcpyHostToDevice, s));
+    // valid (if stale) contents everywhere a build stopped part-way could leave a kernel
+    // reading: the other sorted set and the list counts
+    HIP_OK(c, hipMemsetAsync(d.O[1].key, 0, n * 4, s));
+    HIP_OK(c, hipMemsetAsync(d.O[1].id, 0, n * 4, s));
+    HIP_OK(c, hipMemsetAsync(d.O[1].info, 0, n * 4, s));
+    HIP_OK(c, hipMemsetAsync(d.nbc, 0, n * 4, s));
     // the gather moves `ref` only when some particle is MOVING
-    if (!moving) {
-        d.O[0].ref = nullptr;
-        d.O[1].ref = nullptr;
-    } else {
-        Dev tmp{};
-        carve(tmp, c->ws, c->precision, c->dim, c->n, c->ncell, c->ninst);
-        d.O[0].ref = tmp.O[0].ref;
-        d.O[1].ref = tmp.O[1].ref;
-    }
+    d.O[0].ref = moving ? lay.O[0].ref : nullptr;
+    d.O[1].ref = moving ? lay.O[1].ref : nullptr;
     const int zero = 0;
     // the first build is requested; the set-up derive leaves q in pos.w
     const uint32_t flags[3] = {0u, 1u, 1u};
@@ -755,16 +775,16 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     launch_derive(d, c->launch, s);
     enqueue_build(c);
     c->inited = true;
+    c->lost = false;
     c->rates_valid = false;
     HIP_OK(c, hipGetLastError());
-    HIP_OK(c, hipStreamSynchronize(s));
-    return SPHX_OK;
+    return status_of(c);   // synchronises; reports a first build that stalled
 }
 
 sphx_status sphx_build_neighbors(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
-    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (const sphx_status st = have_state(c)) return st;
     sphx_status st = request_rebuild(c);
     if (st) return st;
     enqueue_build(c);
@@ -776,7 +796,7 @@ sphx_status sphx_build_neighbors(sphx_ctx* c)
 sphx_status sphx_renormalize_density(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
-    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (const sphx_status st = have_state(c)) return st;
     enqueue_build(c);
     enqueue_renorm(c, true);
     c->rates_valid = false;
@@ -787,7 +807,7 @@ sphx_status sphx_renormalize_density(sphx_ctx* c)
 sphx_status sphx_compute_forces(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
-    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (const sphx_status st = have_state(c)) return st;
     enqueue_build(c);
     launch_restore(c->dev, c->stream);   // m P / rho^2 into pos.w, wherever q was left there
     enqueue_rates(c, false, true);
@@ -799,7 +819,7 @@ sphx_status sphx_compute_forces(sphx_ctx* c)
 sphx_status sphx_integrate_step(sphx_ctx* c, double dt)
 {
     if (!c) return SPHX_E_ARG;
-    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (const sphx_status st = have_state(c)) return st;
     if (!c->rates_valid) return fail(c, SPHX_E_STATE, "compute_forces first");
     if (!std::isfinite(dt)) return fail(c, SPHX_E_ARG, "dt must be finite");
     enqueue_integrate(c, dt > 0 ? dt : 0.0);
@@ -811,7 +831,7 @@ sphx_status sphx_integrate_step(sphx_ctx* c, double dt)
 sphx_status sphx_step(sphx_ctx* c, int32_t nsteps)
 {
     if (!c) return SPHX_E_ARG;
-    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (const sphx_status st = have_state(c)) return st;
     if (nsteps < 0) return fail(c, SPHX_E_ARG, "nsteps must be >= 0");
     int32_t k = 0;
     while (k < nsteps) {
@@ -855,6 +875,10 @@ sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
         break;
     case SPHX_OPT_GRAPH: c->use_graph = value != 0 && c->stream != nullptr; break;
     case SPHX_OPT_ONE_LAUNCH_BUILD: c->launch.one_launch_build = value != 0; break;
+    case SPHX_OPT_FORCE_STALL:
+        if (value < 0 || value > 5) return fail(c, SPHX_E_ARG, "force_stall must be 0..5");
+        c->launch.stall_at = (int)value;
+        break;
     case SPHX_OPT_PROFILE:
         c->profile = value != 0;
         for (int q = 0; q < SPHX_NPH; ++q) {
@@ -909,7 +933,7 @@ sphx_status sphx_reset_interactions(sphx_ctx* c)
 sphx_status sphx_get_field(sphx_ctx* c, int32_t field, double* out)
 {
     if (!c || !out) return SPHX_E_ARG;
-    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (const sphx_status st = have_state(c)) return st;
     const sphx_status st = status_of(c);
     const int64_t n = c->n;
     const bool f32 = c->precision == 1;
@@ -1031,7 +1055,7 @@ sphx_status sphx_get_field(sphx_ctx* c, int32_t field, double* out)
 sphx_status sphx_get_neighbors(sphx_ctx* c, int64_t* off, int32_t* ids, int64_t cap, int64_t* need)
 {
     if (!c || !off || !need) return SPHX_E_ARG;
-    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (const sphx_status st = have_state(c)) return st;
     enqueue_build(c);
     const int cur = device_cur(c);
     const int64_t n = c->n;
@@ -1084,7 +1108,7 @@ sphx_status sphx_get_neighbors(sphx_ctx* c, int64_t* off, int32_t* ids, int64_t 
 sphx_status sphx_get_state(sphx_ctx* c, void* blob, size_t cap, size_t* need)
 {
     if (!c || !need) return SPHX_E_ARG;
-    if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
+    if (const sphx_status st = have_state(c)) return st;
     const int cur = device_cur(c);
     auto spans = state_spans(c, cur);
     size_t total = sizeof(BlobHeader);
@@ -1138,6 +1162,40 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
             if (info_inst(f) >= (uint32_t)c->ninst || info_phase(f) >= (uint32_t)c->nphase)
                 return fail(c, SPHX_E_ARG, "blob: particle %lld has a bad instance or phase", (long long)i);
         }
+        // every index the kernels follow must stay in range
+        std::vector<const char*> at(spans.size());
+        const char* q = p;
+        for (size_t k = 0; k < spans.size(); ++k) {
+            at[k] = q;
+            q += spans[k].bytes;
+        }
+        auto u32 = [](const char* base, size_t i) {
+            uint32_t v;
+            std::memcpy(&v, base + 4 * i, 4);
+            return v;
+        };
+        const uint32_t n = (uint32_t)c->n, nc = c->ncell, cap = c->dev.cap;
+        const char *key = at[3], *id = at[4], *cst = at[6], *nbl = at[10], *nbc = at[11], *il = at[12];
+        for (uint32_t i = 0; i < n; ++i) {
+            const InstDev& I = c->inst[info_inst(info_at(i))];
+            const uint32_t k = u32(key, i);
+            if (k < I.cell_base || k >= I.cell_base + I.ncell || u32(id, i) >= n)
+                return fail(c, SPHX_E_ARG, "blob: particle %u has a bad cell key or id", i);
+        }
+        if (u32(cst, 0) != 0 || u32(cst, nc) != n)
+            return fail(c, SPHX_E_ARG, "blob: cell table does not span the particles");
+        for (uint32_t k = 0; k < nc; ++k)
+            if (u32(cst, k + 1) < u32(cst, k)) return fail(c, SPHX_E_ARG, "blob: cell table not ascending");
+        for (uint32_t i = 0; i < n; ++i) {
+            const uint32_t m = std::min(u32(nbc, i), cap);
+            for (uint32_t e = 0; e < m; ++e)
+                if ((u32(nbl, (size_t)e * n + i) & kIdxMask) >= n)
+                    return fail(c, SPHX_E_ARG, "blob: neighbour list of particle %u out of range", i);
+        }
+        const uint32_t ni = u32(at[13], 0);
+        if (ni > n) return fail(c, SPHX_E_ARG, "blob: colour-pass count out of range");
+        for (uint32_t e = 0; e < ni; ++e)
+            if (u32(il, e) >= n) return fail(c, SPHX_E_ARG, "blob: colour-pass index out of range");
         mass_table(c, c->n, [&](int64_t i, uint32_t& b, uint32_t& q, double& mi) {
             const uint32_t f = info_at(i);
             b = info_inst(f);
@@ -1161,7 +1219,12 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
     HIP_OK(c, hipMemcpy(c->dev.curp, &cur, sizeof cur, hipMemcpyHostToDevice));
     HIP_OK(c, hipMemcpy(c->dev.flags, flags, sizeof flags, hipMemcpyHostToDevice));
     HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * 4));
+    const Sorted& other = c->dev.O[1 - cur];   // valid (if stale) for a build that stops part-way
+    HIP_OK(c, hipMemset(other.key, 0, (size_t)c->n * 4));
+    HIP_OK(c, hipMemset(other.id, 0, (size_t)c->n * 4));
+    HIP_OK(c, hipMemset(other.info, 0, (size_t)c->n * 4));
     c->rates_valid = h.rates_valid != 0;
+    c->lost = false;
     return SPHX_OK;
 }
 

@@ -30,6 +30,11 @@ enum : uint32_t { K_FLUID = 0, K_WALL = 1, K_MOVING = 2 };
 // walk checks this at compile time).
 constexpr uint32_t kListCap2 = 48u, kListCap3 = 128u;
 
+// Neighbour-list entry: particle index j in the low 26 bits; in FP32 the cell offset
+// delta = c_i - c_j (components in {-1, 0, 1}) as (dx + 1) + 3 (dy + 1) + 9 (dz + 1) in
+// bits 26-30; the phase of j in bit 31 (phases never change, so the list carries them).
+constexpr uint32_t kIdxBits = 26, kIdxMask = (1u << kIdxBits) - 1u, kCodeMask = 31u, kPhaseShift = 31;
+
 struct InstDev {
     double lo[3], hi[3], span[3], cs[3];
     int32_t nc[3];
@@ -128,6 +133,7 @@ struct Launch {
     int lanes = 4;       // lanes per particle in the renormalisation pass (1, 2, 4)
     int force_lanes = 1; // lanes per particle in the force pass (1, 2, 4)
     bool one_launch_build = true;   // the build as one launch with grid barriers (else seven)
+    int stall_at = 0;    // test hook: barrier of the one-launch build forced to time out (0: none)
     bool debug_terms = false;
 };
 

@@ -223,10 +223,7 @@ template <class R> struct Row {
     float dy1, dz1;  // delta_y + 1, delta_z + 1 as floats
 };
 
-// Neighbour-list entry: particle index j in the low 26 bits; in FP32 the cell offset
-// delta = c_i - c_j (components in {-1, 0, 1}) as (dx + 1) + 3 (dy + 1) + 9 (dz + 1) in
-// bits 26-30; the phase of j in bit 31 (phases never change, so the list carries them).
-constexpr uint32_t kIdxBits = 26, kIdxMask = (1u << kIdxBits) - 1u, kCodeMask = 31u, kPhaseShift = 31;
+// Neighbour-list entries (layout with the list constants): the phase of j is bit 31.
 __device__ __forceinline__ uint32_t entry_phase(uint32_t e) { return e >> kPhaseShift; }
 
 template <int DIM>
@@ -934,8 +931,10 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
 // 0 stores the epoch into eight release words on separate cache lines, each polled by
 // one eighth of the blocks.  Epochs grow across launches (word 0 holds the next base),
 // so no slot needs clearing.  Every wait is bounded: a block that waits too long
-// records ST_STALL and returns false (later builds are then skipped and the host
-// reports the error), as do the blocks that wait on it after.
+// records ST_STALL and returns false, as do the blocks that wait on it after; later
+// builds are then skipped and the host declares the state lost (the build stopped
+// part-way).  `forced` makes every wait of this barrier time out at once, so that
+// tests can take the stall path without waiting.
 constexpr uint32_t kBarrierSpins = 1u << 20;
 constexpr uint32_t kBarRelease = 32;     // release word r at bar[kBarRelease * (1 + r)], r < 8
 constexpr uint32_t kBarSlots = 512;      // arrival slot of block b at bar[kBarSlots + b]
@@ -953,7 +952,7 @@ __device__ __forceinline__ bool bar_wait(unsigned* w, unsigned epoch)
     return true;
 }
 
-__device__ __forceinline__ bool grid_sync(const Dev& d, unsigned epoch)
+__device__ __forceinline__ bool grid_sync(const Dev& d, unsigned epoch, bool forced)
 {
     __shared__ int ok;
     unsigned* bar = d.bar;
@@ -966,7 +965,8 @@ __device__ __forceinline__ bool grid_sync(const Dev& d, unsigned epoch)
     if (blockIdx.x == 0) {
         __syncthreads();
         bool good = true;
-        for (uint32_t b = threadIdx.x; b < gridDim.x && good; b += blockDim.x) good = bar_wait(&bar[kBarSlots + b], epoch);
+        for (uint32_t b = threadIdx.x; b < gridDim.x && good; b += blockDim.x)
+            good = !forced && bar_wait(&bar[kBarSlots + b], epoch);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // what the arrivals this lane saw released
         if (!good) ok = 0;
         __syncthreads();
@@ -976,7 +976,7 @@ __device__ __forceinline__ bool grid_sync(const Dev& d, unsigned epoch)
                 __hip_atomic_store(&bar[kBarRelease * (1 + r)], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     } else if (threadIdx.x == 0) {
-        if (!bar_wait(&bar[kBarRelease * (1 + (blockIdx.x & 7))], epoch)) ok = 0;
+        if (forced || !bar_wait(&bar[kBarRelease * (1 + (blockIdx.x & 7))], epoch)) ok = 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // everything released before the epoch
     }
     __syncthreads();
@@ -987,9 +987,9 @@ __device__ __forceinline__ bool grid_sync(const Dev& d, unsigned epoch)
 // The whole build in one launch.  Every block takes the rebuild decision; on the steps
 // without a rebuild (most of them) the launch ends there, where the seven-launch form
 // pays for seven launches.  On a rebuild the phases above run grid-stride, separated by
-// grid barriers.
+// grid barriers.  stall_at = b in 1..5 forces barrier b to time out (0: none).
 template <class R, int DIM>
-__global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_ref)
+__global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_ref, int stall_at)
 {
     if (!build_decision(d)) return;
     const uint32_t n = d.n, T = gridDim.x * blockDim.x;
@@ -998,18 +998,18 @@ __global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_
     // after the last barrier, when every block has read it
     const unsigned base = __hip_atomic_load(&d.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n; b0 += T) hash_phase<R, DIM>(d, old, b0 + threadIdx.x);
-    if (!grid_sync(d, base + 1)) return;
+    if (!grid_sync(d, base + 1, stall_at == 1)) return;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) scan_reduce_tile(d.cnt, d.ncell, d.scan_tmp, t);
-    if (!grid_sync(d, base + 2)) return;
+    if (!grid_sync(d, base + 2, stall_at == 2)) return;
     // each tile sums the tile sums before it (few), so the scan needs no middle pass
     if (blockIdx.x == 0) flip_and_reset(d);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x)
         scan_down_tile(d.cnt, d.ncell, tile_prefix(d.scan_tmp, t), d.cstart, t);
-    if (!grid_sync(d, base + 3)) return;
+    if (!grid_sync(d, base + 3, stall_at == 3)) return;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) scatter_one(d, k);
-    if (!grid_sync(d, base + 4)) return;
+    if (!grid_sync(d, base + 4, stall_at == 4)) return;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) rank_one<R>(d, k, with_ref);
-    if (!grid_sync(d, base + 5)) return;
+    if (!grid_sync(d, base + 5, stall_at == 5)) return;
     if (blockIdx.x == 0 && threadIdx.x == 0)
         __hip_atomic_store(&d.bar[0], base + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t lanes = n * (uint32_t)kNlistLanes;
@@ -1945,7 +1945,8 @@ static void build_impl(const Dev& d, const Launch& L, hipStream_t s)
     if (L.one_launch_build) {
         const unsigned g = build_grid<R, DIM>(d, ntiles);
         if (g > 0) {
-            hipLaunchKernelGGL((k_build<R, DIM>), dim3(g), dim3(256), 0, s, d, ntiles, d.O[0].ref ? 1 : 0);
+            hipLaunchKernelGGL((k_build<R, DIM>), dim3(g), dim3(256), 0, s, d, ntiles, d.O[0].ref ? 1 : 0,
+                               L.stall_at);
             return;
         }
     }

@@ -227,6 +227,133 @@ def test_one_launch_build_matches_seven_launches(name, prec):
     assert a.stats()["builds"] == b.stats()["builds"] > 1
 
 
+def _expect(code, call):
+    with pytest.raises(binding.SphxError) as e:
+        call()
+    assert e.value.code == code, str(e.value)
+
+
+def _lost_until_restored(a):
+    # a stalled build leaves no whole state: the calls that step or read it refuse
+    for call in (lambda: a.step(1), a.compute_forces, a.build_neighbors,
+                 lambda: a.get_field(binding.F_X), a.get_neighbors, a.get_state):
+        _expect(5, call)
+
+
+def _same_course(a, b, chunks=(1, 12, 20)):
+    for chunk in chunks:
+        a.step(chunk)
+        b.step(chunk)
+        for f in (binding.F_X, binding.F_U, binding.F_RHO):
+            assert np.array_equal(a.get_field(f), b.get_field(f)), (chunk, f)
+    oa, ia = a.get_neighbors()
+    ob, ib = b.get_neighbors()
+    assert np.array_equal(oa, ob) and np.array_equal(ia, ib)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("barrier", [1, 2, 3, 4, 5])
+def test_stalled_build_loses_the_state_until_set_state(barrier, prec):
+    # a grid barrier of the one-launch build forced to time out (the host-side test hook,
+    # so every wave exits at once): the build stops part-way, the next sync reports it,
+    # and after set_state the context steps on with seven-launch builds exactly as a
+    # context that never stalled
+    s = inputs.drop2d(perturb=True)
+    print(f"case stalled build barrier={barrier} precision={prec}", flush=True)
+    a = binding.Sim(s, precision=prec)
+    a.step(3)
+    blob = a.get_state()
+    a.set_option(binding.OPT_FORCE_STALL, barrier)
+    a.build_neighbors()
+    _expect(9, a.sync)
+    _lost_until_restored(a)
+    a.set_state(blob)
+    b = binding.Sim(s, precision=prec)
+    b.set_option(binding.OPT_ONE_LAUNCH_BUILD, 0)
+    b.set_state(blob)
+    _same_course(a, b)
+    assert a.stats()["builds"] == b.stats()["builds"]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_stall_inside_step_graphs_is_reported(prec):
+    # the stall during replayed step graphs (a rebuild falls due on its own): the later
+    # steps of the replay run on and the next sync reports the lost state
+    s = inputs.drop2d(perturb=True)
+    print(f"case stall in step graphs precision={prec}", flush=True)
+    a = binding.Sim(s, precision=prec)
+    b = binding.Sim(s, precision=prec)
+    blob = a.get_state()
+    builds0 = b.stats()["builds"]
+    b.step(40)
+    assert b.stats()["builds"] > builds0   # a rebuild falls due within the 40 steps
+    a.set_option(binding.OPT_FORCE_STALL, 3)
+    a.step(40)
+    _expect(9, a.sync)
+    _lost_until_restored(a)
+    a.set_state(blob)
+    c = binding.Sim(s, precision=prec)
+    c.set_option(binding.OPT_ONE_LAUNCH_BUILD, 0)
+    _same_course(a, c)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_stall_in_the_first_build_of_init(prec):
+    s = inputs.drop2d(perturb=True)
+    print(f"case stalled first build precision={prec}", flush=True)
+    a = binding.Sim(s, precision=prec)
+    a.set_option(binding.OPT_FORCE_STALL, 4)
+    _expect(9, a.init_particles)
+    _lost_until_restored(a)
+    a.init_particles()
+    b = binding.Sim(s, precision=prec)
+    b.set_option(binding.OPT_ONE_LAUNCH_BUILD, 0)
+    _same_course(a, b)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["drop2d", "flume2d"])
+def test_init_particles_again_matches_a_fresh_context(name, prec):
+    # a second upload into a context that has stepped starts it over exactly; the
+    # flume's piston particles need the reference positions, which a first upload
+    # without them would have switched off
+    s = SCENES["drop2d"]() if name == "drop2d" else small_flume2d()
+    print(f"case init twice {name} precision={prec} n={s.n}", flush=True)
+    a = binding.Sim(s, precision=prec)
+    a.step(5)
+    a.init_particles()
+    b = binding.Sim(s, precision=prec)
+    _same_course(a, b)
+
+
+def test_set_state_rejects_out_of_range_indices():
+    # the state blob's layout (header, then the spans of state_spans in the library):
+    # a 48-byte header holding n at byte 24 and the cell count at byte 32, then in FP32
+    # pos, vel, aux (16 B per particle each), key, id, info (4 B), the cell table
+    # (4 B per cell + 1), the run block (64 B per instance), acc and gc (16 B) and the
+    # list, entry e of particle i at 4 (e n + i)
+    s = inputs.drop2d(perturb=True)
+    print("case set_state validation", flush=True)
+    a = binding.Sim(s, precision=binding.FP32_CELLREL)
+    a.step(2)
+    good = a.get_state()
+    n = int(np.frombuffer(good, np.int64, 1, 24)[0])
+    ncell = int(np.frombuffer(good, np.uint32, 1, 32)[0])
+    assert n == s.n and ncell == a.stats()["ncells"]
+    key_at = 48 + 48 * n
+    nbl_at = key_at + 12 * n + 4 * (ncell + 1) + 64 * s.ninst + 32 * n
+    assert np.frombuffer(good, np.uint32, 1, key_at)[0] < ncell
+    assert (np.frombuffer(good, np.uint32, 1, nbl_at)[0] & ((1 << 26) - 1)) < n
+    for at, bad in ((nbl_at, n), (key_at, ncell)):
+        blob = bytearray(good)
+        blob[at:at + 4] = np.uint32(bad).tobytes()
+        _expect(1, lambda: a.set_state(bytes(blob)))
+    x = a.get_field(binding.F_X)
+    a.set_state(good)          # the rejected blobs changed nothing
+    assert np.array_equal(a.get_field(binding.F_X), x)
+    a.step(1)
+
+
 @pytest.mark.parametrize("every", [0, 3])
 @pytest.mark.parametrize("prec", PRECS)
 def test_steps_without_renormalisation_match_oracle(prec, every):
