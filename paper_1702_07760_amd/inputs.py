@@ -207,6 +207,27 @@ def drop3d(k_seed: int = 1, *, dx=1e-3, scale=1.0, perturb=False, **kw) -> Scene
                 name="drop3d", **kw)
 
 
+def paper_drop(shape: str = "sphere", k_seed: int = 5, *, dx=5e-3, perturb=False, **kw) -> Scene:
+    """The paper's two drop tests (Sec. III): a still water tank 0.2 m on a side filled
+    to 0.2 m, particle size 5 mm (40^3 = 64,000 fluid particles), interfacial tension
+    0.05 N/m, an oil sphere of diameter 0.04 m or an oil cube of side 0.04 m whose
+    centre lies 0.16 m below the free surface.  Oil density and viscosity are not
+    given there; the tank's defaults stand in for them."""
+    side, depth, size = 0.2, 0.2, 0.04
+    H = int(round(depth / dx)) * dx
+    c = np.array([side / 2, side / 2, H - 0.16])
+    if shape == "sphere":
+        oil = drop(3, c, size / 2)
+    elif shape == "cube":
+        def oil(pts):
+            return np.all(np.abs(pts - c[None, :3]) < size / 2, axis=1)
+    else:
+        raise ValueError("shape must be 'sphere' or 'cube'")
+    kw.setdefault("alpha_s", 0.05)
+    return tank(3, (side, side), depth, dx, seed=SEED_BASE + k_seed, oil=oil, perturb=perturb,
+                name=f"paper_{shape}", **kw)
+
+
 def still_tank(dim=2, *, dx=2.5e-3, width=0.1, height=0.1, seed=SEED_BASE, **kw) -> Scene:
     """Single-phase still water tank (hydrostatic column)."""
     wd = width if dim == 2 else (width, width)

@@ -2,7 +2,7 @@
 launch configuration the benchmark times (default options, graph-replayed steps).
 
 The 3D drop (335,728 particles) and the 2D flume (165,538) are compared whole after one
-step; the 3D periodic flume (3,222,950) in the FP32 form the benchmark reports; the
+step, the paper's sphere and cube drop tests (95,116) after three; the 3D periodic flume (3,222,950) in the FP32 form the benchmark reports; the
 256-tank batch (5,961,716 particles) runs whole on the GPU and a sample of 8 tanks is
 stepped by the oracle, one tank at a time (tanks are independent).
 """
@@ -43,6 +43,23 @@ def test_full_size_step_matches_oracle(name, prec):
     o.step(1)
     sim = binding.Sim(s, precision=prec)
     sim.step(1)
+    sim.sync()
+    assert abs(sim.stats()["t"] - o.t) <= 1e-6 * o.t
+    _compare(s, sim, o, prec)
+
+
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32_CELLREL])
+@pytest.mark.parametrize("shape", ["sphere", "cube"])
+def test_paper_drop_cases_match_oracle(shape, prec):
+    # the paper's two drop tests (64,000 fluid particles) with seeded velocity and
+    # density perturbations, three steps
+    s = inputs.paper_drop(shape, perturb=True)
+    print(f"case paper drop {shape} n={s.n} precision={prec}", flush=True)
+    o = oracle.Oracle(s)
+    o.set_neighbor_method(2)
+    o.step(3)
+    sim = binding.Sim(s, precision=prec)
+    sim.step(3)
     sim.sync()
     assert abs(sim.stats()["t"] - o.t) <= 1e-6 * o.t
     _compare(s, sim, o, prec)
