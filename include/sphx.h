@@ -169,7 +169,9 @@ sphx_status sphx_bind_workspace(sphx_ctx* ctx, void* dev_ptr, size_t bytes);
 /* Copy the particle state from host arrays in original order (n = sum of counts):
  * x, u: n x 3 FP64 row-major; rho, m: n FP64; phase, kind: n uint8.  Validates every
  * value (finite, inside the box, positive density and mass, phase < nphase, boundary
- * particles in phase 0) and then builds the neighbour structure. */
+ * particles in phase 0), then builds the neighbour structure and waits for it.  May be
+ * called again to start over with the same layout.  Returns SPHX_E_STALL if that first
+ * build stalled (call it again: the build then takes seven launches). */
 sphx_status sphx_init_particles(sphx_ctx* ctx, const double* x, const double* u, const double* rho,
                                 const double* m, const uint8_t* phase, const uint8_t* kind);
 
@@ -214,7 +216,9 @@ sphx_status sphx_get_neighbors(sphx_ctx* ctx, int64_t* off, int32_t* ids, int64_
                                int64_t* need);
 
 /* Opaque snapshot of the full state (including compensation terms, time, step count
- * and the time step); a restored context continues bit-identically. */
+ * and the time step); a restored context continues bit-identically.  sphx_set_state
+ * takes a blob from a context of the same layout, checks that every index in it is in
+ * range (SPHX_E_ARG and no change otherwise) and clears a state lost to SPHX_E_STALL. */
 sphx_status sphx_get_state(sphx_ctx* ctx, void* host_blob, size_t cap, size_t* need);
 sphx_status sphx_set_state(sphx_ctx* ctx, const void* host_blob, size_t bytes);
 

@@ -92,3 +92,13 @@ def test_null_context_calls_are_argument_errors():
     assert L.sphx_sync(None) == 1
     assert L.sphx_compute_forces(None) == 1
     assert L.sphx_last_error(None) == b"null context"
+
+
+def test_binding_constants_match_the_header():
+    # status codes and option ids of the binding against the enums of include/sphx.h
+    import re
+    text = open(binding.HEADER).read()
+    codes = {int(v): f"SPHX_{k}" for k, v in re.findall(r"SPHX_(OK|E_[A-Z]+)\s*=\s*(\d+)", text)}
+    assert codes == binding.STATUS
+    opts = {k: int(v) for k, v in re.findall(r"SPHX_OPT_([A-Z_]+)\s*=\s*(\d+)", text)}
+    assert opts and all(getattr(binding, f"OPT_{k}") == v for k, v in opts.items())
