@@ -65,6 +65,38 @@ def test_paper_drop_cases_match_oracle(shape, prec):
     _compare(s, sim, o, prec)
 
 
+@pytest.mark.parametrize("shape", ["sphere", "cube"])
+def test_paper_drops_rise_at_the_added_mass_acceleration(shape):
+    # Sec. III: once released, the oil drop rises.  From rest, a body of density rho_o in
+    # water accelerates at (rho_w - rho_o) g / (rho_o + C_a rho_w), C_a = 1/2 for a sphere
+    # in potential flow: 0.70 m/s^2 here.  After the first ~0.02 s (the start-up pressure
+    # waves) the oil's mean vertical velocity grows at that rate within a factor 1.5, the
+    # centroid rises in every sample, and the FP32 form follows the FP64 one.
+    s = inputs.paper_drop(shape)
+    oil = s.phase == inputs.OIL
+    rho_w, rho_o = s.phases[0][0][0], s.phases[0][1][0]
+    a_est = (rho_w - rho_o) * 9.81 / (rho_o + 0.5 * rho_w)
+    print(f"case paper drop rise {shape} n={s.n} a_est={a_est:.3f}", flush=True)
+    track = {}
+    for prec in (binding.FP64, binding.FP32_CELLREL):
+        sim = binding.Sim(s, precision=prec)
+        rows = []
+        for _ in range(12):
+            sim.step(100)
+            x, u = sim.get_field(binding.F_X), sim.get_field(binding.F_U)
+            rows.append((sim.stats()["t"], x[oil, 2].mean(), u[oil, 2].mean()))
+        sim.close()
+        track[prec] = np.array(rows)
+    t, z, w = track[binding.FP64].T
+    print("  t " + " ".join(f"{v:.3f}" for v in t), flush=True)
+    print("  dz_mm " + " ".join(f"{(v - z[0]) * 1e3:.3f}" for v in z), flush=True)
+    assert np.all(np.diff(z[1:]) > 0)
+    a = (w[4] - w[1]) / (t[4] - t[1])
+    print(f"  mean acceleration {a:.3f} m/s^2 between t = {t[1]:.3f} and {t[4]:.3f} s", flush=True)
+    assert a_est / 1.5 < a < a_est * 1.5
+    assert np.allclose(track[binding.FP32_CELLREL][:, 1], z, rtol=0, atol=1e-5 * 0.005)
+
+
 def test_full_size_periodic_flume3d_fp32():
     s = inputs.flume3d()
     print(f"case full flume3d n={s.n}", flush=True)
