@@ -128,7 +128,7 @@ struct Dev {
 };
 
 struct Launch {
-    int block = 64;      // threads per block of the neighbour passes (autotuned on the 3D drop)
+    int block = 64;      // threads per block of the neighbour passes (per-form defaults at create)
     int xcd_remap = 1;   // 0 dispatch order, 1 XCD-contiguous tiles, K >= 2 also K tiles per CU
     int lanes = 4;       // lanes per particle in the renormalisation pass (1, 2, 4)
     int force_lanes = 1; // lanes per particle in the force pass (1, 2, 4)

@@ -68,9 +68,13 @@ def tune(scene, precision=binding.FP32_CELLREL, steps=20, warmup=3, skins=SKINS,
          blocks=BLOCKS, remaps=REMAPS, lanes=LANES, save=True, log=print) -> dict:
     """Coordinate descent over the options; returns (and caches) the fastest set."""
     grid = {"skin": skins, "block": blocks, "xcd_remap": remaps, "lanes": lanes, "force_lanes": lanes}
+    # start from the library's own defaults for this precision, dimension and size
     best = dict(DEFAULTS)
-    best["force_lanes"] = 1 if precision == binding.FP32_CELLREL else 2
-    best["xcd_remap"] = 4 if precision == binding.FP32_CELLREL else 1
+    fp32 = precision == binding.FP32_CELLREL
+    best["force_lanes"] = 1 if fp32 else 2
+    best["xcd_remap"] = (0 if scene.dim == 3 else 4) if fp32 else 1
+    best["block"] = 256 if fp32 and scene.dim == 3 else 64
+    best["lanes"] = 1 if fp32 and scene.dim == 2 and scene.n >= 1 << 20 else 4
     results = []
     best_ms = 1e3 * _time(scene, precision, best, steps, warmup)
     results.append(dict(best, ms_per_step=best_ms))
