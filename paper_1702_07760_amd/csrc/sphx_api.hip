@@ -591,13 +591,13 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
 
     sphx_ctx* c = new sphx_ctx();
     c->precision = precision;
-    // measured on the 3D drop (336k particles) and the 3D flume (3.2 M): FP32 3D runs
-    // 256-thread blocks in dispatch order (1 % faster on the drop, 3-4 % from 1 M
-    // particles); FP64 and 2D keep 64-thread blocks, consecutive tiles per XCD in FP64
-    // and four per CU in FP32 2D
+    // measured: 64-thread blocks with consecutive tiles per XCD (FP64) or four per CU
+    // (FP32); large FP32 3D scenes run 256-thread blocks in dispatch order instead, 3-4 %
+    // faster from 1 M particles, within the box-to-box spread at 336k, slower below
+    const bool big3d = precision == 1 && per_inst[0].dim == 3 && n >= (1 << 19);
     c->launch.force_lanes = precision == 0 ? 2 : 1;
-    c->launch.xcd_remap = precision == 0 ? 1 : (per_inst[0].dim == 3 ? 0 : 4);
-    if (precision == 1 && per_inst[0].dim == 3) c->launch.block = 256;
+    c->launch.xcd_remap = precision == 0 ? 1 : (big3d ? 0 : 4);
+    if (big3d) c->launch.block = 256;
     // 2D lists hold about 20 entries: once a million particles fill the device, one lane
     // per particle in Eq. (7) beats four (256 FP32 tanks, 6 M particles: 2.98 against
     // 3.18 ms per step); smaller scenes need the parallelism of four

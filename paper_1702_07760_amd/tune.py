@@ -72,8 +72,9 @@ def tune(scene, precision=binding.FP32_CELLREL, steps=20, warmup=3, skins=SKINS,
     best = dict(DEFAULTS)
     fp32 = precision == binding.FP32_CELLREL
     best["force_lanes"] = 1 if fp32 else 2
-    best["xcd_remap"] = (0 if scene.dim == 3 else 4) if fp32 else 1
-    best["block"] = 256 if fp32 and scene.dim == 3 else 64
+    big3d = fp32 and scene.dim == 3 and scene.n >= 1 << 19
+    best["xcd_remap"] = (0 if big3d else 4) if fp32 else 1
+    best["block"] = 256 if big3d else 64
     best["lanes"] = 1 if fp32 and scene.dim == 2 and scene.n >= 1 << 20 else 4
     results = []
     best_ms = 1e3 * _time(scene, precision, best, steps, warmup)
