@@ -202,6 +202,17 @@ sphx_status sphx_integrate_step(sphx_ctx* ctx, double dt);
  * stream allows it (both decisions are taken on the device). */
 sphx_status sphx_step(sphx_ctx* ctx, int32_t nsteps);
 
+/* Prescribe the motion of instance inst's MOVING particles from now on (the wavemaker
+ * of Sec. IV driven from outside, in place of the piston series of sphx_params): each
+ * sits at its reference position + disp + vel (t - t_call) with velocity vel, t_call
+ * being the instance's time at the call (read from the device: the call synchronises the
+ * stream).  disp, vel: 3 doubles, m and m/s; components beyond the dimension are
+ * ignored.  The steps take the motion at t, t + dt/2 and t + dt like the series.
+ * SPHX_E_ARG for a bad instance, non-finite values or motion along a periodic axis;
+ * SPHX_E_STATE if the scene has no MOVING particles.  sphx_init_particles returns the
+ * particles to the series; sphx_set_state keeps the motion last set. */
+sphx_status sphx_set_moving(sphx_ctx* ctx, int32_t inst, const double* disp, const double* vel);
+
 sphx_status sphx_set_option(sphx_ctx* ctx, int32_t option, int64_t value);
 
 /* Wait for the stream; map the device status word to a status and clear it. */

@@ -57,6 +57,8 @@ def lib():
         L.so_eos.argtypes = [d, d, d, d]
         L.so_piston.restype = None
         L.so_piston.argtypes = [C.POINTER(_Params), d, C.POINTER(d), C.POINTER(d)]
+        L.so_set_moving.restype = None
+        L.so_set_moving.argtypes = [vp, vp, vp]
         L.so_create.restype = vp
         L.so_create.argtypes = [C.POINTER(_Params), C.POINTER(_Phase), i32, i64] + [vp] * 6
         L.so_destroy.argtypes = [vp]
@@ -192,6 +194,12 @@ class Oracle:
 
     def step(self, nsteps: int = 1) -> int:
         return int(lib().so_step(self.ctx, int(nsteps)))
+
+    def set_moving(self, disp, vel):
+        """MOVING particles at x0 + disp + vel (t - t_now) from now on."""
+        dv = np.ascontiguousarray(disp, np.float64).reshape(3)
+        vv = np.ascontiguousarray(vel, np.float64).reshape(3)
+        lib().so_set_moving(self.ctx, _ptr(dv), _ptr(vv))
 
     @property
     def t(self) -> float:

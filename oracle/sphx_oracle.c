@@ -40,6 +40,10 @@ struct so_ctx {
     uint8_t *phase, *kind;
     double t;
     int64_t step;
+    /* motion of the MOVING particles set from outside (so_set_moving): displacement
+     * mv_disp + mv_vel (t - mv_t0) and velocity mv_vel, in place of the piston */
+    int mv_host;
+    double mv_disp[3], mv_vel[3], mv_t0;
     int32_t nb_method;
     int nb_valid;                 /* neighbour list matches the current positions */
     int64_t *nb_off;
@@ -586,8 +590,16 @@ static void wrap_periodic(so_ctx* c, int64_t i)
 static void advance(so_ctx* c, const double* xn, const double* un, const double* rhon,
                     double fdt, double t_new)
 {
-    double dpis = 0.0, vpis = 0.0;
-    so_piston(&c->p, t_new, &dpis, &vpis);
+    /* displacement and velocity of the MOVING particles at t_new */
+    double dmv[3] = {0.0, 0.0, 0.0}, vmv[3] = {0.0, 0.0, 0.0};
+    if (c->mv_host) {
+        for (int d = 0; d < 3; ++d) {
+            dmv[d] = c->mv_disp[d] + c->mv_vel[d] * (t_new - c->mv_t0);
+            vmv[d] = c->mv_vel[d];
+        }
+    } else {
+        so_piston(&c->p, t_new, &dmv[0], &vmv[0]);
+    }
     const int64_t n = c->n;
     for (int64_t i = 0; i < n; ++i) {
         double xi[3], ui[3];
@@ -598,8 +610,8 @@ static void advance(so_ctx* c, const double* xn, const double* un, const double*
             }
         } else if (c->kind[i] == SO_MOVING) {
             for (int d = 0; d < 3; ++d) {
-                xi[d] = c->x0[3 * i + d] + (d == 0 ? dpis : 0.0);
-                ui[d] = d == 0 ? vpis : 0.0;
+                xi[d] = c->x0[3 * i + d] + dmv[d];
+                ui[d] = vmv[d];
             }
         } else {
             for (int d = 0; d < 3; ++d) {
@@ -616,6 +628,16 @@ static void advance(so_ctx* c, const double* xn, const double* un, const double*
     }
     c->nb_valid = 0;
     c->have_rates = 0;
+}
+
+void so_set_moving(so_ctx* c, const double disp[3], const double vel[3])
+{
+    c->mv_host = 1;
+    for (int d = 0; d < 3; ++d) {
+        c->mv_disp[d] = d < c->p.dim ? disp[d] : 0.0;
+        c->mv_vel[d] = d < c->p.dim ? vel[d] : 0.0;
+    }
+    c->mv_t0 = c->t;
 }
 
 int64_t so_step(so_ctx* c, int32_t nsteps)

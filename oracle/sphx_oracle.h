@@ -68,6 +68,9 @@ so_ctx* so_create(const so_params* p, const so_phase* phases, int32_t nphase, in
                   const double* x, const double* u, const double* rho, const double* m,
                   const uint8_t* phase, const uint8_t* kind);
 void so_destroy(so_ctx* c);
+/* From now on the MOVING particles sit at their initial position + disp + vel (t - t_now)
+ * with velocity vel, in place of the piston (components beyond dim are ignored). */
+void so_set_moving(so_ctx* c, const double disp[3], const double vel[3]);
 void so_set_threads(int32_t nthreads);
 int32_t so_get_threads(void);
 /* method: 0 auto (brute force up to 5000 particles), 1 brute force, 2 cell list */

@@ -86,6 +86,7 @@ def lib():
             "sphx_integrate_step": (i32, [vp, d]),
             "sphx_step": (i32, [vp, i32]),
             "sphx_set_option": (i32, [vp, i32, i64]),
+            "sphx_set_moving": (i32, [vp, i32, vp, vp]),
             "sphx_sync": (i32, [vp]),
             "sphx_get_stats": (i32, [vp, C.POINTER(Stats)]),
             "sphx_reset_interactions": (i32, [vp]),
@@ -239,6 +240,11 @@ class Sim:
 
     def step(self, nsteps: int = 1):
         self._check(lib().sphx_step(self.ctx, int(nsteps)), "sphx_step")
+
+    def set_moving(self, inst: int, disp, vel):
+        dv = np.ascontiguousarray(disp, np.float64).reshape(3)
+        vv = np.ascontiguousarray(vel, np.float64).reshape(3)
+        self._check(lib().sphx_set_moving(self.ctx, int(inst), _ptr(dv), _ptr(vv)), "sphx_set_moving")
 
     def set_option(self, opt: int, value: int):
         self._check(lib().sphx_set_option(self.ctx, int(opt), int(value)), "sphx_set_option")

@@ -689,6 +689,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     }
     c->has_moving = moving;
     drop_graphs(c);
+    for (auto& I : c->inst) I.mv_host = 0;   // MOVING particles follow the piston series again
 
     std::vector<char> pos(n * 4 * R), vel(n * 4 * R), aux(n * 4 * R);
     std::vector<float4> plo(f32 ? n : 0), vlo(f32 ? n : 0);
@@ -860,6 +861,36 @@ sphx_status sphx_step(sphx_ctx* c, int32_t nsteps)
     }
     c->rates_valid = false;
     HIP_OK(c, hipGetLastError());
+    return SPHX_OK;
+}
+
+sphx_status sphx_set_moving(sphx_ctx* c, int32_t inst, const double* disp, const double* vel)
+{
+    if (const sphx_status st = have_state(c)) return st;
+    if (inst < 0 || inst >= c->ninst) return fail(c, SPHX_E_ARG, "instance %d out of range", (int)inst);
+    if (!disp || !vel) return fail(c, SPHX_E_ARG, "null array");
+    if (!c->has_moving) return fail(c, SPHX_E_STATE, "the scene has no MOVING particles");
+    const sphx_params& p = c->params[inst];
+    double dv[3] = {0, 0, 0}, vv[3] = {0, 0, 0};
+    for (int q = 0; q < c->dim; ++q) {
+        if (!std::isfinite(disp[q]) || !std::isfinite(vel[q])) return fail(c, SPHX_E_ARG, "non-finite motion");
+        if (p.periodic[q] && (disp[q] != 0.0 || vel[q] != 0.0))
+            return fail(c, SPHX_E_ARG, "no motion along the periodic axis %d", q);
+        dv[q] = disp[q];
+        vv[q] = vel[q];
+    }
+    // the motion starts from the instance's current time, read from the device
+    InstRun r;
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    HIP_OK(c, hipMemcpy(&r, c->dev.run + inst, sizeof r, hipMemcpyDeviceToHost));
+    InstDev& I = c->inst[inst];
+    I.mv_host = 1;
+    for (int q = 0; q < 3; ++q) {
+        I.mv_disp[q] = dv[q];
+        I.mv_vel[q] = vv[q];
+    }
+    I.mv_t0 = r.t;
+    HIP_OK(c, hipMemcpy((void*)(c->dev.inst + inst), &I, sizeof I, hipMemcpyHostToDevice));
     return SPHX_OK;
 }
 

@@ -50,6 +50,10 @@ struct InstDev {
     int32_t n_piston;
     double piston_t_end;
     double pa[kMaxPiston], pw[kMaxPiston], pphi[kMaxPiston];
+    // host-set motion of the MOVING particles (sphx_set_moving), replacing the piston
+    // series when mv_host = 1: displacement mv_disp + mv_vel (t - mv_t0), velocity mv_vel
+    int32_t mv_host;
+    double mv_disp[3], mv_vel[3], mv_t0;
     // particle mass by phase, valid when umass = 1: every particle of the instance with
     // that phase has this mass (the force pass then reads no mass per neighbour)
     int32_t umass;

@@ -93,15 +93,23 @@ __device__ __forceinline__ double tait(double y, double beta)
     return beta * (y4 * y2 * y - 1.0);
 }
 
-// Piston displacement d(t) and velocity (MOVING particles).
-__device__ inline void piston(const InstDev& I, double t, double& d, double& v)
+// Displacement d(t) and velocity v(t) of the MOVING particles: the piston series along
+// x (Eq. (18) and its sums), or the host-set linear motion.
+__device__ inline void moving_motion(const InstDev& I, double t, double d[3], double v[3])
 {
+    if (I.mv_host) {
+        for (int q = 0; q < 3; ++q) {
+            d[q] = I.mv_disp[q] + I.mv_vel[q] * (t - I.mv_t0);
+            v[q] = I.mv_vel[q];
+        }
+        return;
+    }
     const double te = t < I.piston_t_end ? t : I.piston_t_end;
-    d = 0.0;
-    v = 0.0;
+    d[0] = d[1] = d[2] = 0.0;
+    v[0] = v[1] = v[2] = 0.0;
     for (int k = 0; k < I.n_piston; ++k) {
-        d += I.pa[k] * (cos(I.pw[k] * te + I.pphi[k]) - cos(I.pphi[k]));
-        if (t < I.piston_t_end) v -= I.pa[k] * I.pw[k] * sin(I.pw[k] * t + I.pphi[k]);
+        d[0] += I.pa[k] * (cos(I.pw[k] * te + I.pphi[k]) - cos(I.pphi[k]));
+        if (t < I.piston_t_end) v[0] -= I.pa[k] * I.pw[k] * sin(I.pw[k] * t + I.pphi[k]);
     }
 }
 
@@ -1726,9 +1734,9 @@ template <class R>
 __device__ __forceinline__ void moving_state(const InstDev& I, const double4& x0, uint32_t key, double t,
                                              R4<R>& p, R4<R>& v)
 {
-    double dd, vv;
-    piston(I, t, dd, vv);
-    const double x[3] = {x0.x + dd, x0.y, x0.z};
+    double dd[3], vv[3];
+    moving_motion(I, t, dd, vv);
+    const double x[3] = {x0.x + dd[0], x0.y + dd[1], x0.z + dd[2]};
     if constexpr (sizeof(R) == 8) {
         p.x = x[0]; p.y = x[1]; p.z = x[2];
     } else {
@@ -1738,7 +1746,7 @@ __device__ __forceinline__ void moving_state(const InstDev& I, const double4& x0
         p.y = (float)((x[1] - I.lo[1]) - (double)c[1] * I.cs[1]);
         p.z = (float)((x[2] - I.lo[2]) - (double)c[2] * I.cs[2]);
     }
-    v.x = (R)vv; v.y = 0; v.z = 0;
+    v.x = (R)vv[0]; v.y = (R)vv[1]; v.z = (R)vv[2];
 }
 
 __device__ __forceinline__ double wrap_coord(double x, const InstDev& I, int d)

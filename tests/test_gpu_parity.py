@@ -810,3 +810,51 @@ def test_pairs_exactly_at_the_cutoff_are_not_neighbours():
     goff, gids = sim.get_neighbors()
     assert np.array_equal(goff, off) and np.array_equal(gids, ids)
     assert list(np.diff(goff)) == [0, 0, 1, 1]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["flume2d", "flume3d"])
+def test_set_moving_matches_the_oracle(name, prec):
+    # the wavemaker driven from outside: the same set_moving calls between steps on the
+    # GPU and on the oracle (in 3D the width is periodic, so the motion stays in x-z)
+    s = FLUMES[name]()
+    print(f"case set_moving {name} precision={prec} n={s.n}", flush=True)
+    mov = s.kind == inputs.MOVING
+    x0 = s.x[mov].copy()
+    o = oracle.Oracle(s)
+    sim = binding.Sim(s, precision=prec)
+    calls = [([0.004, 0.0, 0.0], [0.15, 0.0, 0.0]), ([0.006, 0.0, -0.001], [-0.1, 0.0, 0.02])]
+    if s.dim == 2:
+        calls = [(d[:1] + [d[2], 0.0], v[:1] + [v[2], 0.0]) for d, v in calls]
+    for disp, vel in calls:
+        o.step(2)
+        sim.step(2)
+        sim.set_moving(0, disp, vel)
+        o.set_moving(disp, vel)
+    t0 = o.t
+    o.step(3)
+    sim.step(3)
+    sim.sync()
+    tol = TOL[prec]
+    dx = s.dx[0]
+    x = sim.get_field(binding.F_X)
+    assert rel_to(x, o.get(oracle.X), dx) < tol
+    assert rel_to(sim.get_field(binding.F_RHO), o.get(oracle.RHO), 1000.0) < tol
+    ur = np.abs(o.get(oracle.U)).max()
+    assert rel_to(sim.get_field(binding.F_U), o.get(oracle.U), ur) < tol
+    disp, vel = np.array(calls[-1][0]), np.array(calls[-1][1])
+    want = x0 + (disp + vel * (o.t - t0))
+    assert np.abs(x[mov] - want).max() < (1e-12 if prec == binding.FP64 else 1e-6)
+
+
+def test_set_moving_rejects_what_it_cannot_do():
+    s = FLUMES["flume3d"]()
+    sim = binding.Sim(s, precision=binding.FP32_CELLREL)
+    _expect(1, lambda: sim.set_moving(1, [0, 0, 0], [0, 0, 0]))            # no instance 1
+    _expect(1, lambda: sim.set_moving(0, [0, 0, 0], [0, 0.1, 0]))          # periodic width
+    _expect(1, lambda: sim.set_moving(0, [np.nan, 0, 0], [0, 0, 0]))
+    still = binding.Sim(inputs.drop2d(), precision=binding.FP32_CELLREL)
+    _expect(5, lambda: still.set_moving(0, [0, 0, 0], [0.1, 0, 0]))        # nothing MOVING
+    sim.set_moving(0, [0.0, 0.0, 0.0], [0.05, 0.0, 0.0])
+    sim.step(2)
+    sim.sync()

@@ -565,3 +565,29 @@ def test_oracle_is_deterministic():
     b.step(2)
     for f in (oracle.X, oracle.U, oracle.RHO):
         assert np.array_equal(a.get(f), b.get(f))
+
+
+def test_set_moving_prescribes_a_linear_motion():
+    # after so_set_moving(disp, vel) the MOVING particles sit at x0 + disp + vel (t - t_call)
+    # with velocity vel at every later step, whatever the piston series says; the fluid
+    # still moves with its own velocity
+    s = inputs.flume2d(dx=0.02, length=2.0, depth=0.3, x_focus=1.0)
+    mov = s.kind == inputs.MOVING
+    x0 = s.x[mov].copy()
+    o = oracle.Oracle(s)
+    o.step(2)
+    t_call = o.t
+    disp, vel = np.array([0.004, -0.001, 0.0]), np.array([0.15, 0.05, 0.0])
+    o.set_moving(disp, vel)
+    o.step(3)
+    t = o.t
+    x, u = o.get(oracle.X), o.get(oracle.U)
+    want = x0 + (disp + vel * (t - t_call))
+    assert np.allclose(x[mov], want, rtol=0, atol=1e-15)
+    assert np.all(u[mov] == vel)
+    assert not np.allclose(u[~mov], 0.0)
+    # a second call restarts the line from the time of that call
+    t2 = o.t
+    o.set_moving([0.0, 0.0, 0.0], [-0.1, 0.0, 0.0])
+    o.step(2)
+    assert np.allclose(o.get(oracle.X)[mov], x0 + np.array([-0.1, 0.0, 0.0]) * (o.t - t2), rtol=0, atol=1e-15)
