@@ -185,7 +185,19 @@ def main():
             steps_cpu += 1
         cpu = {"value": total / elapsed, "unit": "interactions/s", "cores": threads, "kind": "oracle",
                "sample": f"{steps_cpu} full steps of the same 3D drop ({n} particles), FP64 oracle, "
-                         f"OpenMP over particles, {elapsed:.1f} s"}
+                         f"OpenMP over particles, {elapsed:.1f} s",
+               "particle_steps_per_s": n * steps_cpu / elapsed}
+        # the same oracle on one host core, over a shorter sample
+        oracle.set_threads(1)
+        total1, steps1, elapsed1 = 0, 0, 0.0
+        while steps1 < 1 or (elapsed1 < args.cpu_seconds / 2 and steps1 < 8):
+            t0 = time.perf_counter()
+            total1 += o.step(1)
+            elapsed1 += time.perf_counter() - t0
+            steps1 += 1
+        oracle.set_threads(threads)
+        cpu["single_core"] = {"value": total1 / elapsed1, "unit": "interactions/s", "cores": 1,
+                              "sample": f"{steps1} full steps, {elapsed1:.1f} s"}
         log(f"oracle: {cpu}")
 
     out = {
