@@ -616,7 +616,6 @@ def test_drift_over_1000_steps_is_reported(tmp_path):
     """Drift of both GPU forms against the oracle over 1000 steps of the 2D drop
     (reported, loose bounds: particle trajectories separate chaotically)."""
     import json
-    import os
     s = inputs.drop2d()
     o = oracle.Oracle(s)
     o.set_neighbor_method(2)
@@ -635,10 +634,6 @@ def test_drift_over_1000_steps_is_reported(tmp_path):
             row[f"{tag}_rho_rel"] = rel_to(sim.get_field(binding.F_RHO), ro, 1000.0)
         rows.append(row)
         print(json.dumps(row), flush=True)
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    os.makedirs(out, exist_ok=True)
-    with open(os.path.join(out, "drift_drop2d_1000.json"), "w") as fh:
-        json.dump(rows, fh, indent=1)
     assert rows[0]["fp64_x_over_dx"] < 1e-9
     assert rows[-1]["fp32_x_over_dx"] < 0.5
 
