@@ -612,7 +612,7 @@ def test_flume3d_neighbours_bit_exact_across_the_periodic_width():
     assert wrapped > 0
 
 
-def test_drift_over_1000_steps_is_reported(tmp_path):
+def test_drift_over_1000_steps_is_reported():
     """Drift of both GPU forms against the oracle over 1000 steps of the 2D drop
     (reported, loose bounds: particle trajectories separate chaotically)."""
     import json
