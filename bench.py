@@ -89,8 +89,8 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "decomposition is a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
