@@ -853,3 +853,35 @@ def test_set_moving_rejects_what_it_cannot_do():
     sim.set_moving(0, [0.0, 0.0, 0.0], [0.05, 0.0, 0.0])
     sim.step(2)
     sim.sync()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_set_moving_acts_on_its_instance_only(prec):
+    # two flumes in one context: instance 1 gets a motion from outside, instance 0 keeps
+    # its piston series; each is compared with an oracle of its own
+    a = small_flume2d()
+    b = inputs.flume2d(dx=0.025, length=2.0, depth=0.3, x_focus=1.0)
+    s = inputs.concat("two_flumes", [a, b])
+    print(f"case set_moving batched precision={prec} n={s.n}", flush=True)
+    sim = binding.Sim(s, precision=prec)
+    oa, ob = oracle.Oracle(a), oracle.Oracle(b)
+    disp, vel = [0.003, 0.0, 0.0], [0.12, 0.0, 0.0]
+    sim.step(2)
+    oa.step(2)
+    ob.step(2)
+    sim.set_moving(1, disp, vel)
+    ob.set_moving(disp, vel)
+    sim.step(3)
+    oa.step(3)
+    ob.step(3)
+    sim.sync()
+    x = sim.get_field(binding.F_X)
+    u = sim.get_field(binding.F_U)
+    tol = TOL[prec]
+    for o, part, (lo, hi) in ((oa, a, s.inst_offsets[0:2]), (ob, b, s.inst_offsets[1:3])):
+        assert rel_to(x[lo:hi], o.get(oracle.X), part.dx[0]) < tol
+        ur = np.abs(o.get(oracle.U)).max()
+        assert rel_to(u[lo:hi], o.get(oracle.U), ur) < tol
+    mov_b = b.kind == inputs.MOVING
+    lo = int(s.inst_offsets[1])
+    assert np.allclose(u[lo:][mov_b][:, 0], vel[0], rtol=0, atol=1e-6)
