@@ -595,7 +595,9 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
     // (FP32); large FP32 3D scenes run 256-thread blocks in dispatch order instead, 3-4 %
     // faster from 1 M particles, within the box-to-box spread at 336k, slower below
     const bool big3d = precision == 1 && per_inst[0].dim == 3 && n >= (1 << 19);
-    c->launch.force_lanes = 1;   // FP64 too: 3D drop 2 % faster, 2D flume 23 % faster than 2
+    // one force lane per particle, except large FP64 3D scenes: two there (3D flume
+    // 4.29 against 4.99 ms per step; 2 % slower on the 336k drop, 23 % on the 2D flume)
+    c->launch.force_lanes = precision == 0 && per_inst[0].dim == 3 && n >= (1 << 19) ? 2 : 1;
     c->launch.xcd_remap = precision == 0 ? 1 : (big3d ? 0 : 4);
     if (big3d) c->launch.block = 256;
     // 2D lists hold about 20 entries: once a million particles fill the device, one lane
