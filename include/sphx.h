@@ -105,7 +105,7 @@ enum {
                                  particles, else 4 in FP32 and 1 in FP64) */
     SPHX_OPT_GRAPH = 4,       /* 1: sphx_step replays a captured hipGraph per step (default 1) */
     SPHX_OPT_LANES = 5,       /* lanes that share one particle's neighbour loop in the renormalisation
-                                 pass: 1, 2 or 4 (default 4; 1 for FP32 2D contexts of 2^20
+                                 pass: 1, 2 or 4 (default 4; 1 for 2D contexts of 2^20
                                  particles or more); each lane takes every lanes-th
                                  neighbour and the partial sums are combined in-wave (the colour
                                  pass always runs 8 lanes per particle) */

@@ -603,7 +603,7 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
     // 2D lists hold about 20 entries: once a million particles fill the device, one lane
     // per particle in Eq. (7) beats four (256 FP32 tanks, 6 M particles: 2.98 against
     // 3.18 ms per step); smaller scenes need the parallelism of four
-    if (per_inst[0].dim == 2 && precision == 1 && n >= (1 << 20)) c->launch.lanes = 1;
+    if (per_inst[0].dim == 2 && n >= (1 << 20)) c->launch.lanes = 1;   // FP64: 3.43 against 3.49 ms
     c->dim = per_inst[0].dim;
     c->ninst = ninst;
     c->nphase = nphase;

@@ -75,7 +75,7 @@ def tune(scene, precision=binding.FP32_CELLREL, steps=20, warmup=3, skins=SKINS,
     big3d = fp32 and scene.dim == 3 and scene.n >= 1 << 19
     best["xcd_remap"] = (0 if big3d else 4) if fp32 else 1
     best["block"] = 256 if big3d else 64
-    best["lanes"] = 1 if fp32 and scene.dim == 2 and scene.n >= 1 << 20 else 4
+    best["lanes"] = 1 if scene.dim == 2 and scene.n >= 1 << 20 else 4
     results = []
     best_ms = 1e3 * _time(scene, precision, best, steps, warmup)
     results.append(dict(best, ms_per_step=best_ms))
