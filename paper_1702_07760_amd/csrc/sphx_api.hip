@@ -234,7 +234,7 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.inst = c.take<InstDev>(ninst);
     d.run = c.take<InstRun>(ninst);
     d.status = c.take<uint32_t>(1);
-    d.inter = c.take<unsigned long long>(1);
+    d.inter = c.take<unsigned long long>((size_t)kInterSlots * kInterStride);
     d.curp = c.take<int>(1);
     d.prevp = c.take<int>(1);
     d.bar = c.take<unsigned>(512 + 4096);   // the one-launch build's barrier words and slots
@@ -748,7 +748,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     std::memset(run.data(), 0, sizeof(InstRun) * c->ninst);
     HIP_OK(c, hipMemcpyAsync(d.run, run.data(), sizeof(InstRun) * c->ninst, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemsetAsync(d.status, 0, sizeof(uint32_t), s));
-    HIP_OK(c, hipMemsetAsync(d.inter, 0, sizeof(unsigned long long), s));
+    HIP_OK(c, hipMemsetAsync(d.inter, 0, sizeof(unsigned long long) * kInterSlots * kInterStride, s));
     HIP_OK(c, hipMemsetAsync(d.icount, 0, sizeof(uint32_t), s));
     HIP_OK(c, hipMemsetAsync(d.bar, 0, (512 + 4096) * sizeof(unsigned), s));
     HIP_OK(c, hipMemsetAsync(d.cnt, 0, sizeof(uint32_t) * c->ncell, s));
@@ -949,7 +949,9 @@ sphx_status sphx_get_stats(sphx_ctx* c, sphx_stats* out)
     InstRun r;
     unsigned long long inter = 0;
     HIP_OK(c, hipMemcpy(&r, c->dev.run, sizeof r, hipMemcpyDeviceToHost));
-    HIP_OK(c, hipMemcpy(&inter, c->dev.inter, sizeof inter, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> slots((size_t)kInterSlots * kInterStride);
+    HIP_OK(c, hipMemcpy(slots.data(), c->dev.inter, slots.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    for (uint32_t q = 0; q < kInterSlots; ++q) inter += slots[(size_t)q * kInterStride];
     out->steps = r.step;
     out->t = r.t;
     out->dt = r.dt;
@@ -968,7 +970,7 @@ sphx_status sphx_reset_interactions(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
     if (!c->bound) return fail(c, SPHX_E_STATE, "no workspace");
-    HIP_OK(c, hipMemsetAsync(c->dev.inter, 0, sizeof(unsigned long long), c->stream));
+    HIP_OK(c, hipMemsetAsync(c->dev.inter, 0, sizeof(unsigned long long) * kInterSlots * kInterStride, c->stream));
     return SPHX_OK;
 }
 

@@ -30,6 +30,11 @@ enum : uint32_t { K_FLUID = 0, K_WALL = 1, K_MOVING = 2 };
 // walk checks this at compile time).
 constexpr uint32_t kListCap2 = 48u, kListCap3 = 128u;
 
+// Interaction count: kInterSlots 64-bit counters, kInterStride words (128 bytes) apart.
+// Wave w of a force launch adds into counter w mod kInterSlots, so the adds of
+// concurrent waves land on different cache lines; the host sums the counters.
+constexpr uint32_t kInterSlots = 256u, kInterStride = 16u;
+
 // Neighbour-list entry: particle index j in the low 26 bits; in FP32 the cell offset
 // delta = c_i - c_j (components in {-1, 0, 1}) as (dx + 1) + 3 (dy + 1) + 9 (dz + 1) in
 // bits 26-30; the phase of j in bit 31 (phases never change, so the list carries them).
