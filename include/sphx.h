@@ -109,8 +109,7 @@ enum {
                                  particles or more); each lane takes every lanes-th
                                  neighbour and the partial sums are combined in-wave (the colour
                                  pass always runs 8 lanes per particle) */
-    SPHX_OPT_FORCE_LANES = 7, /* the same for the force pass (default 1; 2 for FP64 3D contexts
-                                 of 2^19 particles or more) */
+    SPHX_OPT_FORCE_LANES = 7, /* the same for the force pass (default 2 in 3D, 1 in 2D) */
     SPHX_OPT_PROFILE = 6,     /* 1: no graphs; every kernel group is bracketed by HIP events on the
                                  context stream and its time is reported in sphx_stats */
     SPHX_OPT_ONE_LAUNCH_BUILD = 8, /* 1 (default): the neighbour build (cell sort and list) is one

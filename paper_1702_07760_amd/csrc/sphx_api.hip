@@ -595,9 +595,9 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
     // (FP32); large FP32 3D scenes run 256-thread blocks in dispatch order instead, 3-4 %
     // faster from 1 M particles, within the box-to-box spread at 336k, slower below
     const bool big3d = precision == 1 && per_inst[0].dim == 3 && n >= (1 << 19);
-    // one force lane per particle, except large FP64 3D scenes: two there (3D flume
-    // 4.29 against 4.99 ms per step; 2 % slower on the 336k drop, 23 % on the 2D flume)
-    c->launch.force_lanes = precision == 0 && per_inst[0].dim == 3 && n >= (1 << 19) ? 2 : 1;
+    // two force lanes per particle in 3D, one in 2D (3D drop 0.281 -> 0.256 ms per FP32
+    // step, 3D flume 2.62 -> 2.18 ms; the 2D flume and tanks are fastest with one)
+    c->launch.force_lanes = per_inst[0].dim == 3 ? 2 : 1;
     c->launch.xcd_remap = precision == 0 ? 1 : (big3d ? 0 : 4);
     if (big3d) c->launch.block = 256;
     // 2D lists hold about 20 entries: once a million particles fill the device, one lane

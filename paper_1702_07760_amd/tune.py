@@ -71,7 +71,7 @@ def tune(scene, precision=binding.FP32_CELLREL, steps=20, warmup=3, skins=SKINS,
     # start from the library's own defaults for this precision, dimension and size
     best = dict(DEFAULTS)
     fp32 = precision == binding.FP32_CELLREL
-    best["force_lanes"] = 2 if not fp32 and scene.dim == 3 and scene.n >= 1 << 19 else 1
+    best["force_lanes"] = 2 if scene.dim == 3 else 1
     big3d = fp32 and scene.dim == 3 and scene.n >= 1 << 19
     best["xcd_remap"] = (0 if big3d else 4) if fp32 else 1
     best["block"] = 256 if big3d else 64
