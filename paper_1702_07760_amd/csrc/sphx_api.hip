@@ -591,15 +591,15 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
 
     sphx_ctx* c = new sphx_ctx();
     c->precision = precision;
-    // measured: 64-thread blocks with consecutive tiles per XCD (FP64) or four per CU
-    // (FP32); large FP32 3D scenes run 256-thread blocks in dispatch order instead, 3-4 %
-    // faster from 1 M particles, within the box-to-box spread at 336k, slower below
-    const bool big3d = precision == 1 && per_inst[0].dim == 3 && n >= (1 << 19);
-    // two force lanes per particle in 3D, one in 2D (3D drop 0.281 -> 0.256 ms per FP32
-    // step, 3D flume 2.62 -> 2.18 ms; the 2D flume and tanks are fastest with one)
-    c->launch.force_lanes = per_inst[0].dim == 3 ? 2 : 1;
-    c->launch.xcd_remap = precision == 0 ? 1 : (big3d ? 0 : 4);
-    if (big3d) c->launch.block = 256;
+    // launch shape, measured (alternating runs, ms per step): 3D runs two force lanes per
+    // particle and tiles in plain dispatch order, in 128-thread blocks (3D drop, FP32:
+    // 0.247 against 0.258 for 64 threads with four tiles per CU) or 256 from 2^19
+    // particles (3D flume 2.39 against 2.44); 2D keeps one lane and 64-thread blocks,
+    // consecutive tiles per XCD in FP64 and four per CU in FP32
+    const bool d3 = per_inst[0].dim == 3;
+    c->launch.force_lanes = d3 ? 2 : 1;
+    c->launch.xcd_remap = d3 ? 0 : (precision == 0 ? 1 : 4);
+    c->launch.block = d3 ? (n >= (1 << 19) ? 256 : 128) : 64;
     // 2D lists hold about 20 entries: once a million particles fill the device, one lane
     // per particle in Eq. (7) beats four (256 FP32 tanks, 6 M particles: 2.98 against
     // 3.18 ms per step); smaller scenes need the parallelism of four

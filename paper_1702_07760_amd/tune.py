@@ -72,9 +72,9 @@ def tune(scene, precision=binding.FP32_CELLREL, steps=20, warmup=3, skins=SKINS,
     best = dict(DEFAULTS)
     fp32 = precision == binding.FP32_CELLREL
     best["force_lanes"] = 2 if scene.dim == 3 else 1
-    big3d = fp32 and scene.dim == 3 and scene.n >= 1 << 19
-    best["xcd_remap"] = (0 if big3d else 4) if fp32 else 1
-    best["block"] = 256 if big3d else 64
+    d3 = scene.dim == 3
+    best["xcd_remap"] = 0 if d3 else (4 if fp32 else 1)
+    best["block"] = (256 if scene.n >= 1 << 19 else 128) if d3 else 64
     best["lanes"] = 1 if scene.dim == 2 and scene.n >= 1 << 20 else 4
     results = []
     best_ms = 1e3 * _time(scene, precision, best, steps, warmup)
