@@ -97,12 +97,13 @@ enum {
 enum {
     SPHX_OPT_DEBUG_TERMS = 1, /* 1: compute_forces also stores the three acceleration terms */
     SPHX_OPT_BLOCK = 2,       /* threads per block of the neighbour passes: 64, 128, 192 or 256
-                                 (default: 3D 128, or 256 from 2^19 particles; 2D 64) */
+                                 (default: 3D 128, or 256 from 2^19 particles; 2D 64, or 128
+                                 from 2^16 particles except FP64 from 2^20) */
     SPHX_OPT_XCD_REMAP = 3,   /* tile order of the neighbour passes: 0 dispatch order; 1 consecutive
                                  tiles on one XCD; K = 2, 4, ..., 64 also gives the K workgroups
                                  a CU holds at once K consecutive tiles, assuming round-robin
                                  dispatch over an XCD's 32 CUs (default: 3D 0; 2D 4 in FP32,
-                                 1 in FP64) */
+                                 1 in FP64, 16 where the 2D block is 128) */
     SPHX_OPT_GRAPH = 4,       /* 1: sphx_step replays a captured hipGraph per step (default 1) */
     SPHX_OPT_LANES = 5,       /* lanes that share one particle's neighbour loop in the renormalisation
                                  pass: 1, 2 or 4 (default 4; 1 for 2D contexts of 2^20

@@ -600,6 +600,13 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
     c->launch.force_lanes = d3 ? 2 : 1;
     c->launch.xcd_remap = d3 ? 0 : (precision == 0 ? 1 : 4);
     c->launch.block = d3 ? (n >= (1 << 19) ? 256 : 128) : 64;
+    // 2D from 2^16 particles (except FP64 from 2^20): 128-thread blocks, 16 tiles per CU
+    // (2D flume FP32 0.105 against 0.113 ms per step, FP64 0.132 against 0.138; 256 FP32
+    // tanks 1.73 against 1.81; the 2k-particle drop and the FP64 tanks keep the above)
+    if (!d3 && n >= (1 << 16) && (precision == 1 || n < (1 << 20))) {
+        c->launch.block = 128;
+        c->launch.xcd_remap = 16;
+    }
     // 2D lists hold about 20 entries: once a million particles fill the device, one lane
     // per particle in Eq. (7) beats four (256 FP32 tanks, 6 M particles: 2.98 against
     // 3.18 ms per step); smaller scenes need the parallelism of four

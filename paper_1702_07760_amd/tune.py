@@ -75,6 +75,8 @@ def tune(scene, precision=binding.FP32_CELLREL, steps=20, warmup=3, skins=SKINS,
     d3 = scene.dim == 3
     best["xcd_remap"] = 0 if d3 else (4 if fp32 else 1)
     best["block"] = (256 if scene.n >= 1 << 19 else 128) if d3 else 64
+    if not d3 and scene.n >= 1 << 16 and (fp32 or scene.n < 1 << 20):
+        best["block"], best["xcd_remap"] = 128, 16
     best["lanes"] = 1 if scene.dim == 2 and scene.n >= 1 << 20 else 4
     results = []
     best_ms = 1e3 * _time(scene, precision, best, steps, warmup)
