@@ -74,7 +74,8 @@ typedef struct {
     double gravity[3];
     double lo[3], hi[3];  /* domain box; cells tile it; periodic period = hi - lo */
     int32_t periodic[3];
-    double skin_coef;     /* cells are >= (2 + skin_coef) h; dt <= 0.5 skin_coef h / max|u| */
+    double skin_coef;     /* cells are >= (2 + skin_coef) h; a step with dt max|u| > 0.5 skin_coef h
+                             is refused (SPHX_E_DT); it does not enter the adaptive step */
     double c_cfl, c_force, c_visc, c_st; /* time-step coefficients */
     double dt_fixed;      /* > 0: fixed step instead of the adaptive one */
     int32_t n_piston;     /* MOVING particles follow x = x0 + d(t) e_x with */

@@ -27,7 +27,7 @@ class _Params(C.Structure):
         ("alpha_s", C.c_double),
         ("gravity", C.c_double * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("periodic", C.c_int32 * 3),
-        ("skin_coef", C.c_double), ("c_cfl", C.c_double), ("c_force", C.c_double),
+        ("c_cfl", C.c_double), ("c_force", C.c_double),
         ("c_visc", C.c_double), ("c_st", C.c_double), ("dt_fixed", C.c_double),
         ("n_piston", C.c_int32), ("piston_t_end", C.c_double),
         ("piston_a", C.c_double * MAX_PISTON), ("piston_w", C.c_double * MAX_PISTON),
@@ -94,7 +94,7 @@ def make_params(p: dict) -> _Params:
     s.visc_form = int(p.get("visc_form", 0))
     s.cont_form = int(p.get("cont_form", 0))
     s.renorm_every = int(p.get("renorm_every", 1))
-    for k in ("h", "gamma", "delta_coef", "alpha_s", "skin_coef", "c_cfl", "c_force",
+    for k in ("h", "gamma", "delta_coef", "alpha_s", "c_cfl", "c_force",
               "c_visc", "c_st", "dt_fixed"):
         setattr(s, k, float(p[k]))
     for k in ("gravity", "lo", "hi"):

@@ -14,7 +14,7 @@
  *   Eq. (7)     sums over i itself and its same-phase neighbours
  *   Eq. (15)    1/|grad C|, and T = 0 where grad C = 0
  *   walls       phase 0 (water); fixed position and velocity; density evolves
- *   time step   min of CFL, force, viscous, capillary and neighbour-skin limits
+ *   time step   min of the CFL, force, viscous and capillary limits
  *   integrator  explicit midpoint predictor-corrector, neighbours rebuilt at
  *               the predicted positions
  */
@@ -568,7 +568,6 @@ double so_dt(so_ctx* c)
     if (numax > 0.0) dt = fmin(dt, c->p.c_visc * h * h / numax);
     if (c->p.alpha_s > 0.0 && c->nphase == 2)
         dt = fmin(dt, c->p.c_st * sqrt(rho0min * h * h * h / (2.0 * M_PI * c->p.alpha_s)));
-    if (umax > 0.0) dt = fmin(dt, 0.5 * c->p.skin_coef * h / umax);
     return dt;
 }
 

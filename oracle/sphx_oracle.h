@@ -32,7 +32,6 @@ typedef struct {
     double gravity[3];
     double lo[3], hi[3];  /* domain; periodic dims have period hi - lo */
     int32_t periodic[3];
-    double skin_coef;     /* time-step limit 0.5 * skin_coef * h / max|u| */
     double c_cfl, c_force, c_visc, c_st;
     double dt_fixed;      /* > 0: use this step instead of the adaptive one */
     int32_t n_piston;     /* MOVING particles: x = x0 + d(t) e_x */

@@ -146,8 +146,9 @@ InstDev make_inst(const sphx_params& p, const sphx_phase* ph2, int nphase, uint3
     const double rl = (2.0 + p.skin_coef) * h;
     I.cutl2 = rl * rl * (1.0 + 2e-5);
     // the list (and the cells) stay valid while no particle moved more than skin/4 since
-    // the build: a predictor half step adds at most skin/4 more (dt <= skin h / (2 max|u|)),
-    // so any pair within 2h at a predicted state was within (2 + skin) h at the build
+    // the build: a predictor half step adds at most skin/4 more (a step with
+    // dt max|u| > skin h / 2 is refused), so any pair within 2h at a predicted state was
+    // within (2 + skin) h at the build
     const double q = 0.25 * p.skin_coef * h;
     I.rebuild_d2 = q * q;
     I.wcoef = alpha;

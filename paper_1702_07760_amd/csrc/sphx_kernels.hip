@@ -1738,7 +1738,6 @@ __device__ __forceinline__ double step_dt(const Dev& d, uint32_t b, double dt_ov
         dt = I.c_cfl * I.h / (I.cmax + umax);
         if (amax > 0.0) dt = fmin(dt, I.c_force * sqrt(I.h / amax));
         dt = fmin(dt, I.dt_const);
-        if (umax > 0.0) dt = fmin(dt, 0.5 * I.skin / umax);
     }
     return dt;
 }
@@ -1750,8 +1749,11 @@ __device__ __forceinline__ void store_steps(const Dev& d, double dt_override, ui
     for (uint32_t b = t0; b < (uint32_t)d.ninst; b += nthr) {
         double umax;
         const double dt = step_dt(d, b, dt_override, umax);
-        // the corrector reuses the cells of S^n: every pair within 2h at the predicted
-        // positions must still lie in neighbouring cells
+        // the corrector reuses the list of S^n: every pair within 2h at the predicted
+        // positions must still be in it, which holds while the half step moves no
+        // particle more than a quarter of the skin.  The adaptive step breaks this only
+        // beyond max|u| = c0 skin / (4 c_cfl - 2 skin) (c0 / 4 at the default skin), far
+        // outside the weakly compressible regime; the step is refused then.
         if (dt * umax > 0.5 * d.inst[b].skin * (1.0 + 1e-12) || !(dt > 0.0)) atomicOr(d.status, ST_DT);
         d.run[b].dt = dt;
         d.run[b].t_next = d.run[b].t + dt;

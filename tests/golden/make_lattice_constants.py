@@ -6,6 +6,8 @@ the oracle nor the GPU library.
   partition   sum_j V W_ij              (j over all sites, i itself included)
   moment      sum_j V (x_j - x_i) (x) grad_i W_ij  = moment * I
   count       number of sites j != i with |x_i - x_j| < 2h
+  m2, m4      kernel-weighted moments sum_j W_ij r_ij^k / sum_j W_ij, k = 2, 4 (i itself
+              included, r in units of dx): the weights of Eq. (7) on a lattice
 """
 import itertools
 import json
@@ -27,7 +29,9 @@ for dim in (2, 3):
     grad = f[:, None] * (-pts)                    # r_ij = x_i - x_j = -pts
     mom = np.einsum("ja,jb->ab", pts, grad)
     out[f"{dim}d"] = {"partition": float(w.sum()), "moment": float(mom[0, 0]),
-                      "count": int((inside & (r > 0)).sum())}
+                      "count": int((inside & (r > 0)).sum()),
+                      "m2": float((w * r ** 2).sum() / w.sum()),
+                      "m4": float((w * r ** 4).sum() / w.sum())}
 with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "lattice_constants.json"), "w") as fh:
     json.dump(out, fh, indent=1)
 print(out)

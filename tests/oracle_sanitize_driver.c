@@ -32,7 +32,6 @@ static so_params base_params(int dim, double h)
     p.gamma = 7.0;
     p.delta_coef = 0.1;
     p.alpha_s = 0.02;
-    p.skin_coef = 0.1;
     p.c_cfl = 0.25;
     p.c_force = 0.25;
     p.c_visc = 0.125;

@@ -42,6 +42,17 @@ MUTANTS = {
                           "xi[d] = xn[3 * i + d] + fdt * un[3 * i + d];", "free_fall"),
     "eos_beta_missing_gamma": ("double beta = rho0 * c0 * c0 / gamma;          /* Eq. (4) */",
                                "double beta = rho0 * c0 * c0;", "tait"),
+    "renorm_rho_i_for_rho_j": ("den += c->m[j] / c->rho[j] * w;", "den += c->m[j] / c->rho[i] * w;",
+                               "renormalisation"),
+    "renorm_mass_of_i": ("num += c->m[j] * w;", "num += c->m[i] * w;", "renormalisation"),
+    "renorm_wrong_weight": ("double w = so_kernel_w(dim, h, sqrt(pair_vector(c, i, j, r)));",
+                            "double w = so_kernel_w(dim, h, 0.9 * sqrt(pair_vector(c, i, j, r)));",
+                            "renormalisation"),
+    "piston_drops_cos_phi": ("(cos(p->piston_w[k] * te + p->piston_phi[k]) - cos(p->piston_phi[k]))",
+                             "(cos(p->piston_w[k] * te + p->piston_phi[k]) - 1.0)", "piston or wavemaker"),
+    "piston_phase_sign": ("(cos(p->piston_w[k] * te + p->piston_phi[k]) - cos(p->piston_phi[k]))",
+                          "(cos(p->piston_w[k] * te - p->piston_phi[k]) - cos(p->piston_phi[k]))",
+                          "piston or wavemaker"),
 }
 
 

@@ -155,6 +155,40 @@ def test_renormalisation_keeps_phases_apart_and_includes_self():
     assert np.allclose(oi.get(oracle.RHO), iso.rho, rtol=1e-15, atol=0)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_renormalisation_weights_on_a_lattice(dim):
+    """Eq. (7) weights each same-phase j by m_j W_ij (numerator) and m_j W_ij / rho_j
+    (denominator).  On a perfect lattice (spacing 1), with s_j = |x_j - x_c|, a mass field
+    m_j = m0 (1 + a s_j^2) and a specific-volume field 1/rho_j = (1 + b s_j^2) / rho0 give
+    at the centre site c, with the kernel-weighted lattice moments M2, M4 (self included):
+        rho_c = rho0 (1 + a M2) / (1 + (a + b) M2 + a b M4)
+    and, with a = 0, at a site i offset by s_i from c (the odd moments vanish):
+        rho_i = rho0 / (1 + b (s_i^2 + M2))."""
+    n = 12
+    m2, m4 = LAT[f"{dim}d"]["m2"], LAT[f"{dim}d"]["m4"]
+    rho0, a, b = 1000.0, 0.03, 0.02
+    s = inputs.lattice_box(dim, n, 1.0, periodic=True)
+    xc = np.full(dim, n / 2 + 0.5)
+    d = s.x[:, :dim] - xc
+    s2 = (d ** 2).sum(1)
+    c = int(np.argmin(s2))
+    assert s2[c] == 0.0
+    s.m[:] = 1.0 * (1 + a * s2)
+    s.rho[:] = rho0 / (1 + b * s2)
+    o = oracle.Oracle(s)
+    o.renormalize()
+    want = rho0 * (1 + a * m2) / (1 + (a + b) * m2 + a * b * m4)
+    assert o.get(oracle.RHO)[c] == pytest.approx(want, rel=1e-13)
+    # uniform mass: every site whose support does not reach the wrap of the field
+    s.m[:] = 1.0
+    o = oracle.Oracle(s)
+    o.renormalize()
+    near = np.all(np.abs(d) <= 2.0, axis=1)
+    assert near.sum() == 5 ** dim
+    want = rho0 / (1 + b * (s2 + m2))
+    assert np.allclose(o.get(oracle.RHO)[near], want[near], rtol=1e-13, atol=0)
+
+
 # ------------------------------------------------------------- Eqs. (3)-(4)
 
 def test_tait_equation_of_state():
@@ -510,13 +544,16 @@ def test_time_step_respects_every_limit():
     c0 = max(ph[2] for ph in s.phases[0])
     assert dt * (c0 + umax) <= 0.25 * h * (1 + 1e-15)
     assert dt <= 0.25 * math.sqrt(h / amax) * (1 + 1e-15)
-    assert dt * umax <= 0.5 * p["skin_coef"] * h * (1 + 1e-15)
     nu = max(ph[1] for ph in s.phases[0])
     assert dt <= 0.125 * h * h / nu
     assert dt == pytest.approx(min(0.25 * h / (c0 + umax), 0.25 * math.sqrt(h / amax),
                                    0.125 * h * h / nu,
-                                   0.25 * math.sqrt(900 * h ** 3 / (2 * math.pi * 0.02)),
-                                   0.5 * p["skin_coef"] * h / umax), rel=1e-15)
+                                   0.25 * math.sqrt(900 * h ** 3 / (2 * math.pi * 0.02))), rel=1e-15)
+    # the neighbour skin of the GPU lists is no limit of the method: the step ignores it
+    o2 = oracle.Oracle(s.with_params(skin_coef=1e-6))
+    o2.renormalize()
+    o2.rates()
+    assert o2.dt() == dt
 
 
 def test_wavemaker_eq18():
@@ -531,6 +568,47 @@ def test_wavemaker_eq18():
     assert v == pytest.approx(EQ18["peak_velocity_m_s"], abs=1e-4)
     d_end, v_end = oracle.piston(p, 2.0)
     assert d_end == pytest.approx(stroke, abs=1e-12) and v_end == 0.0
+
+
+def _piston_params(a, w, phi, t_end):
+    p = inputs.default_params(2, 0.01)
+    p.update(piston_a=list(a), piston_w=list(w), piston_phi=list(phi), piston_t_end=t_end)
+    return p
+
+
+def test_piston_series_with_phases():
+    """The focused-wave series: several components with non-zero phases start from rest
+    position, the velocity is the time derivative of the displacement, the piston stops
+    at t_end, and a phase phi_k = w_k tau is a time advance by tau."""
+    rng = np.random.default_rng(11)
+    a = rng.uniform(-0.05, 0.05, 5)
+    w = 2 * math.pi / rng.uniform(0.7, 1.2, 5)
+    phi = rng.uniform(-math.pi, math.pi, 5)
+    t_end = 3.7
+    p = _piston_params(a, w, phi, t_end)
+    d0, _ = oracle.piston(p, 0.0)
+    assert abs(d0) < 1e-16                                 # x(0) = x0 for any phases
+    e = 1e-6
+    for t in (0.1, 0.83, 1.9, 3.1):
+        d, v = oracle.piston(p, t)
+        dp, _ = oracle.piston(p, t + e)
+        dm, _ = oracle.piston(p, t - e)
+        assert v == pytest.approx((dp - dm) / (2 * e), rel=1e-7, abs=1e-9)
+        assert abs(v) > 1e-3
+    d_end, _ = oracle.piston(p, t_end)
+    for t in (t_end + 0.01, t_end + 5.0):
+        d, v = oracle.piston(p, t)
+        assert d == d_end and v == 0.0
+    # phase = time advance: d_phi(t) = d_0(t + tau) - d_0(tau), the same for v
+    tau = 0.37
+    p0 = _piston_params(a, w, [0.0] * 5, 100.0)
+    pt = _piston_params(a, w, list(w * tau), 100.0)
+    dz_tau, _ = oracle.piston(p0, tau)
+    for t in (0.0, 0.21, 1.3, 2.9):
+        d, v = oracle.piston(pt, t)
+        ds, vs = oracle.piston(p0, t + tau)
+        assert d == pytest.approx(ds - dz_tau, abs=1e-14)
+        assert v == pytest.approx(vs, abs=1e-13)
 
 
 @pytest.mark.slow
