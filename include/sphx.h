@@ -90,7 +90,8 @@ enum {
     SPHX_F_A = 3,            /* total acceleration of the last rate evaluation (0 for non-fluid) */
     SPHX_F_DRHO = 4,         /* density rate of the last rate evaluation */
     SPHX_F_AP = 5, SPHX_F_AV = 6, SPHX_F_AS = 7, /* terms of Eqs. (8), (10)/(11), (17); need SPHX_OPT_DEBUG_TERMS */
-    SPHX_F_P = 12,           /* Tait pressure of the current density */
+    SPHX_F_P = 12,           /* Tait pressure of the current density as the device derived it
+                                (from its stored m P / rho^2; FP32 form: to FP32 rounding) */
     SPHX_F_GRADC = 13        /* colour gradient of the last rate evaluation (Eq. (16)) */
 };
 
@@ -165,6 +166,8 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
                         int32_t nphase, int32_t ninst, const int64_t* counts, void* stream,
                         sphx_ctx** out);
 void sphx_destroy(sphx_ctx* ctx);
+/* Message of the last failing call on ctx; with ctx NULL, why the calling thread's last
+ * sphx_create failed. */
 const char* sphx_last_error(const sphx_ctx* ctx);
 
 /* Bind caller-owned device memory (>= sphx_workspace_size bytes, 256-byte aligned). */

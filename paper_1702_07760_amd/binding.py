@@ -71,6 +71,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library missing: {LIB_PATH}; run __graft_entry__.build()")
+        # torch first: its HIP runtime carries the same soname as the system one that
+        # libsphx.so names, so the library then binds to the runtime torch uses.  Loaded
+        # the other way round, the process would hold two HIP runtimes, and the second
+        # to start finds no device.
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, d, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
         sig = {
@@ -180,7 +185,7 @@ class Sim:
                                counts.ctypes.data_as(C.c_void_p),
                                C.c_void_p(self.stream.cuda_stream), C.byref(ctx))
         if st != 0:
-            raise SphxError(st, "sphx_create")
+            raise SphxError(st, "sphx_create", (lib().sphx_last_error(None) or b"").decode())
         self.ctx = ctx
         size = lib().sphx_workspace_size(precision, params, scene.ninst,
                                          counts.ctypes.data_as(C.c_void_p))

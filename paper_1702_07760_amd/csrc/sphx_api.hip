@@ -130,6 +130,7 @@ InstDev make_inst(const sphx_params& p, const sphx_phase* ph2, int nphase, uint3
         I.g[d] = act ? p.gravity[d] : 0.0;
         I.ncell *= (uint32_t)g.nc[d];
         I.f_cs[d] = (float)g.cs[d];
+        I.f_cs_lo[d] = (float)(g.cs[d] - (double)I.f_cs[d]);
         I.f_g[d] = (float)I.g[d];
     }
     I.cell_base = cell_base;
@@ -324,6 +325,20 @@ sphx_status status_of(sphx_ctx* c)
     if (st & ST_DOMAIN) return fail(c, SPHX_E_DOMAIN, "a particle left a non-periodic domain");
     if (st & ST_DT) return fail(c, SPHX_E_DT, "dt * max|u| exceeded half the neighbour skin");
     return SPHX_OK;
+}
+
+// Why the last sphx_create of this thread failed (sphx_last_error(NULL) returns it).
+thread_local std::string g_create_err;
+
+sphx_status create_fail(sphx_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_create_err = buf;
+    return s;
 }
 
 // The calls that step or read the particle state need one that is whole.
@@ -535,6 +550,31 @@ hipGraphExec_t capture_steps(sphx_ctx* c, int32_t steps)
 }
 } // namespace
 
+namespace {
+// Lays the context's arrays out in dev_ptr (the body of both workspace bindings).
+sphx_status bind_memory(sphx_ctx* c, void* dev_ptr, size_t bytes)
+{
+    if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(c, SPHX_E_WORKSPACE, "workspace must be non-null and 256-byte aligned");
+    Dev d{};
+    const size_t need = carve(d, nullptr, c->precision, c->dim, c->n, c->ncell, c->ninst);
+    if (bytes < need) return fail(c, SPHX_E_WORKSPACE, "workspace too small: %zu < %zu bytes", bytes, need);
+    if (c->stream || c->bound) HIP_OK(c, hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    c->dev = Dev{};
+    carve(c->dev, dev_ptr, c->precision, c->dim, c->n, c->ncell, c->ninst);
+    c->dev.precision = c->precision;
+    c->dev.dim = c->dim;
+    c->dev.ninst = c->ninst;
+    c->dev.n = c->n;
+    c->dev.ncell = c->ncell;
+    c->ws = dev_ptr;
+    c->ws_bytes = bytes;
+    c->bound = true;
+    c->inited = false;
+    return SPHX_OK;
+}
+} // namespace
+
 // ===================================================================== C ABI
 
 extern "C" {
@@ -558,38 +598,42 @@ size_t sphx_workspace_size(int32_t precision, const sphx_params* per_inst, int32
 sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sphx_phase* phases, int32_t nphase,
                         int32_t ninst, const int64_t* counts, void* stream, sphx_ctx** out)
 {
-    if (!out) return SPHX_E_ARG;
+    g_create_err.clear();
+    if (!out) return create_fail(SPHX_E_ARG, "null output pointer");
     *out = nullptr;
-    sphx_ctx tmp;
-    if (!per_inst || !phases || !counts) return fail(&tmp, SPHX_E_ARG, "null argument");
-    if (precision != SPHX_FP64 && precision != SPHX_FP32_CELLREL) return SPHX_E_ARG;
-    if (ninst < 1 || ninst > (1 << 20) || nphase < 1 || nphase > 2) return SPHX_E_ARG;
+    if (!per_inst || !phases || !counts) return create_fail(SPHX_E_ARG, "null argument");
+    if (precision != SPHX_FP64 && precision != SPHX_FP32_CELLREL) return create_fail(SPHX_E_ARG, "unknown precision %d", (int)precision);
+    if (ninst < 1 || ninst > (1 << 20) || nphase < 1 || nphase > 2)
+        return create_fail(SPHX_E_ARG, "ninst must be in [1, 2^20] and nphase 1 or 2");
     int64_t n = 0;
     for (int b = 0; b < ninst; ++b) {
-        if (counts[b] < 1) return SPHX_E_ARG;
+        if (counts[b] < 1) return create_fail(SPHX_E_ARG, "instance %d has no particles", b);
         n += counts[b];
     }
-    if (n >= (1ll << 26)) return SPHX_E_ARG;   // neighbour-list entries hold 26-bit indices
+    if (n >= (1ll << 26)) return create_fail(SPHX_E_ARG, "%lld particles: at most 2^26 - 1 (26-bit list indices)", (long long)n);
     std::string why;
     for (int b = 0; b < ninst; ++b) {
-        if (!check_params(per_inst[b], per_inst[0].dim, why)) return SPHX_E_ARG;
-        if (per_inst[b].renorm_every != per_inst[0].renorm_every) return SPHX_E_ARG;
+        if (!check_params(per_inst[b], per_inst[0].dim, why)) return create_fail(SPHX_E_ARG, "instance %d: %s", b, why.c_str());
+        if (per_inst[b].renorm_every != per_inst[0].renorm_every)
+            return create_fail(SPHX_E_ARG, "every instance needs the same renorm_every");
         for (int q = 0; q < nphase; ++q) {
             const sphx_phase& f = phases[(size_t)b * nphase + q];
             if (!(std::isfinite(f.rho0) && f.rho0 > 0 && std::isfinite(f.nu) && f.nu >= 0 && std::isfinite(f.c0) && f.c0 > 0))
-                return SPHX_E_ARG;
+                return create_fail(SPHX_E_ARG, "instance %d phase %d: rho0, c0 > 0 and nu >= 0 required", b, q);
         }
     }
     std::vector<uint32_t> base;
     uint32_t total;
-    if (!setup_cells(per_inst, ninst, base, total, why)) return SPHX_E_ARG;
+    if (!setup_cells(per_inst, ninst, base, total, why)) return create_fail(SPHX_E_ARG, "%s", why.c_str());
 
     int devid = 0;
-    if (hipGetDevice(&devid) != hipSuccess) return SPHX_E_NODEV;
+    hipError_t he = hipGetDevice(&devid);
+    if (he != hipSuccess) return create_fail(SPHX_E_NODEV, "hipGetDevice: %s", hipGetErrorString(he));
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, devid) != hipSuccess) return SPHX_E_NODEV;
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SPHX_E_NODEV;
-
+    he = hipGetDeviceProperties(&prop, devid);
+    if (he != hipSuccess) return create_fail(SPHX_E_NODEV, "hipGetDeviceProperties: %s", hipGetErrorString(he));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return create_fail(SPHX_E_NODEV, "device %d is %s, not gfx950", devid, prop.gcnArchName);
     sphx_ctx* c = new sphx_ctx();
     c->precision = precision;
     // launch shape, measured (alternating runs, ms per step): 3D runs two force lanes per
@@ -643,29 +687,19 @@ void sphx_destroy(sphx_ctx* c)
     delete c;
 }
 
-const char* sphx_last_error(const sphx_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* sphx_last_error(const sphx_ctx* c)
+{
+    if (c) return c->err.c_str();
+    return g_create_err.empty() ? "null context" : g_create_err.c_str();
+}
+
 
 sphx_status sphx_bind_workspace(sphx_ctx* c, void* dev_ptr, size_t bytes)
 {
     if (!c) return SPHX_E_ARG;
-    if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(c, SPHX_E_WORKSPACE, "workspace must be non-null and 256-byte aligned");
-    Dev d{};
-    const size_t need = carve(d, nullptr, c->precision, c->dim, c->n, c->ncell, c->ninst);
-    if (bytes < need) return fail(c, SPHX_E_WORKSPACE, "workspace too small: %zu < %zu bytes", bytes, need);
-    drop_graphs(c);
-    c->dev = Dev{};
-    carve(c->dev, dev_ptr, c->precision, c->dim, c->n, c->ncell, c->ninst);
-    c->dev.precision = c->precision;
-    c->dev.dim = c->dim;
-    c->dev.ninst = c->ninst;
-    c->dev.n = c->n;
-    c->dev.ncell = c->ncell;
-    c->ws = dev_ptr;
-    c->ws_bytes = bytes;
-    c->bound = true;
-    c->inited = false;
-    return SPHX_OK;
+    return bind_memory(c, dev_ptr, bytes);
 }
+
 
 sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, const double* rho, const double* m,
                                 const uint8_t* phase, const uint8_t* kind)
@@ -1007,9 +1041,9 @@ sphx_status sphx_get_field(sphx_ctx* c, int32_t field, double* out)
     };
     std::vector<float4> lo;
     auto rho_of = [&](const std::vector<double>& r, int64_t k) {
-        if (!f32) return r[k];
+        if (!f32) return r[4 * k + 3];   // density in aux.w
         const InstDev& I = c->inst[info_inst(info[k])];
-        return I.rho0[info_phase(info[k])] + r[k] + (double)lo[k].w;
+        return I.rho0[info_phase(info[k])] + r[4 * k + 3] + (double)lo[k].w;
     };
     std::vector<double> a, b;
     sphx_status e = SPHX_OK;
@@ -1055,21 +1089,21 @@ sphx_status sphx_get_field(sphx_ctx* c, int32_t field, double* out)
     }
     case SPHX_F_RHO:
     case SPHX_F_P: {
-        if ((e = fetch4(S.aux, a))) return e;   // density in aux.w
-        for (int64_t k = 0; k < n; ++k) a[k] = a[4 * k + 3];
+        if ((e = fetch4(S.aux, a))) return e;
         if (f32) {
             lo.resize(n);
             HIP_OK(c, hipMemcpy(lo.data(), S.plo, n * sizeof(float4), hipMemcpyDeviceToHost));
         }
         for (int64_t k = 0; k < n; ++k) {
-            const double r = rho_of(a, k);
-            if (field == SPHX_F_RHO) out[id[k]] = r;
-            else {
-                const InstDev& I = c->inst[info_inst(info[k])];
-                const uint32_t ph = info_phase(info[k]);
-                const double y = r / I.rho0[ph], y2 = y * y, y4 = y2 * y2;
-                out[id[k]] = I.beta[ph] * (y4 * y2 * y - 1.0);
+            if (field == SPHX_F_RHO) {
+                out[id[k]] = rho_of(a, k);
+                continue;
             }
+            // the pressure the device derived: aux holds (m, m P / rho^2, V, rho or rho - rho0),
+            // with rho taken as the device takes it (the FP32 form without its compensation term)
+            const InstDev& I = c->inst[info_inst(info[k])];
+            const double r = f32 ? I.rho0[info_phase(info[k])] + a[4 * k + 3] : a[4 * k + 3];
+            out[id[k]] = a[4 * k + 1] * (r * r) / a[4 * k];
         }
         break;
     }

@@ -63,8 +63,9 @@ struct InstDev {
     // that phase has this mass (the force pass then reads no mass per neighbour)
     int32_t umass;
     double mass[2];
-    // FP32 copies for the cell-relative kernels
-    float f_cs[3], f_inv_h, f_cut2, f_cutl2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3];
+    // FP32 copies for the cell-relative kernels; f_cs_lo = cs - f_cs (the part of the
+    // cell size FP32 drops, carried into the compensation term when offsets re-cell)
+    float f_cs[3], f_cs_lo[3], f_inv_h, f_cut2, f_cutl2, f_fcoef, f_wcoef, f_delta2, f_alpha_s, f_g[3];
     float f_vpair[2][2], f_rho0[2], f_mass[2];
 };
 

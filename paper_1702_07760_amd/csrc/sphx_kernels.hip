@@ -596,13 +596,15 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
             const float s = I.f_cs[dd];
             const float sh = fminf(fmaxf(floorf(o[dd] / s), -1.0e6f), 1.0e6f);
             if (sh != 0.0f) {
-                // o - sh*s with its rounding error kept (TwoSum); sh*s is exact for |sh| <= 2
+                // the offset moves sh cells: o - sh cs = (o - sh s) - sh (cs - s).  o - sh s is
+                // taken with its rounding error (TwoSum; sh s is exact for |sh| <= 2), and that
+                // error and -sh (cs - s) go into the compensation term
                 const float b = -sh * s;
                 const float sum = o[dd] + b;
                 const float bv = sum - o[dd];
                 const float err = (o[dd] - (sum - bv)) + (b - bv);
                 o[dd] = sum;
-                e[dd] += err;
+                e[dd] += err - sh * I.f_cs_lo[dd];
                 int ci = c[dd] + (int)sh;
                 if (I.periodic[dd]) {
                     ci = ((ci % I.nc[dd]) + I.nc[dd]) % I.nc[dd];
