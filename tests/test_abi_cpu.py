@@ -84,6 +84,13 @@ def test_create_without_gpu_reports_no_device():
         pytest.skip("a GPU is present")
     st, ctx = _create(inputs.drop2d())
     assert st == 2 and not ctx.value       # SPHX_E_NODEV
+    assert b"hipGetDevice" in binding.lib().sphx_last_error(None)   # why, for this thread
+
+
+def test_create_failure_message_names_the_argument():
+    s = inputs.drop2d()
+    st, ctx = _create(s, mutate=lambda p, ph, c: setattr(p[0], "gamma", 5.0))
+    assert st == 1 and b"gamma must be 7" in binding.lib().sphx_last_error(None)
 
 
 def test_null_context_calls_are_argument_errors():
@@ -91,7 +98,6 @@ def test_null_context_calls_are_argument_errors():
     assert L.sphx_step(None, 1) == 1
     assert L.sphx_sync(None) == 1
     assert L.sphx_compute_forces(None) == 1
-    assert L.sphx_last_error(None) == b"null context"
 
 
 def test_binding_constants_match_the_header():
