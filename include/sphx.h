@@ -173,6 +173,23 @@ const char* sphx_last_error(const sphx_ctx* ctx);
 /* Bind caller-owned device memory (>= sphx_workspace_size bytes, 256-byte aligned). */
 sphx_status sphx_bind_workspace(sphx_ctx* ctx, void* dev_ptr, size_t bytes);
 
+/* Size of the static workspace below: 64 MiB per device. */
+#define SPHX_STATIC_WORKSPACE_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under graph capture, serving
+ * loops, harnesses that forbid hipMalloc): the variant of sphx_bind_workspace that
+ * binds the library's own static workspace of the context's device instead of caller
+ * memory.  It allocates nothing, device or host.  Each device holds one static
+ * workspace of SPHX_STATIC_WORKSPACE_BYTES from the loading of the library until the
+ * process ends; a context that needs more (sphx_workspace_size) gets SPHX_E_WORKSPACE
+ * and stays as it was.  Every context bound to it on one device shares it, and it keeps
+ * what the last context left there (init_particles sets up everything a run reads):
+ * binding a second context takes the workspace away from the first, whose later calls
+ * return SPHX_E_WORKSPACE until it is bound again and init_particles runs again.  Calls
+ * of two contexts bound to the same device's static workspace that overlap in time
+ * race.  As with sphx_bind_workspace, call init_particles next. */
+sphx_status sphx_bind_static_workspace(sphx_ctx* ctx);
+
 /* Copy the particle state from host arrays in original order (n = sum of counts):
  * x, u: n x 3 FP64 row-major; rho, m: n FP64; phase, kind: n uint8.  Validates every
  * value (finite, inside the box, positive density and mass, phase < nphase, boundary

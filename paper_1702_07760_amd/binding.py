@@ -84,6 +84,7 @@ def lib():
             "sphx_destroy": (None, [vp]),
             "sphx_last_error": (C.c_char_p, [vp]),
             "sphx_bind_workspace": (i32, [vp, vp, sz]),
+            "sphx_bind_static_workspace": (i32, [vp]),
             "sphx_init_particles": (i32, [vp] + [vp] * 6),
             "sphx_build_neighbors": (i32, [vp]),
             "sphx_renormalize_density": (i32, [vp]),
@@ -169,7 +170,7 @@ def _ptr(a):
 class Sim:
     """One sphx context on one GPU: the state of every instance of a scene."""
 
-    def __init__(self, scene, precision=FP64, device="cuda:0", graph=True):
+    def __init__(self, scene, precision=FP64, device="cuda:0", graph=True, static_workspace=False):
         import torch
         self.torch = torch
         self.scene = scene
@@ -187,14 +188,19 @@ class Sim:
         if st != 0:
             raise SphxError(st, "sphx_create", (lib().sphx_last_error(None) or b"").decode())
         self.ctx = ctx
-        size = lib().sphx_workspace_size(precision, params, scene.ninst,
-                                         counts.ctypes.data_as(C.c_void_p))
-        with torch.cuda.device(self.device):
-            self.ws = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
-        base = self.ws.data_ptr()
-        aligned = (base + 255) & ~255
-        self._check(lib().sphx_bind_workspace(self.ctx, C.c_void_p(aligned), size),
-                    "sphx_bind_workspace")
+        if static_workspace:
+            # the library's own per-device workspace: nothing is allocated
+            self.ws = None
+            self._check(lib().sphx_bind_static_workspace(self.ctx), "sphx_bind_static_workspace")
+        else:
+            size = lib().sphx_workspace_size(precision, params, scene.ninst,
+                                             counts.ctypes.data_as(C.c_void_p))
+            with torch.cuda.device(self.device):
+                self.ws = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            aligned = (base + 255) & ~255
+            self._check(lib().sphx_bind_workspace(self.ctx, C.c_void_p(aligned), size),
+                        "sphx_bind_workspace")
         if not graph:
             self.set_option(OPT_GRAPH, 0)
         self.init_particles()

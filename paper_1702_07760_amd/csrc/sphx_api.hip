@@ -4,18 +4,30 @@
 #include "sphx_internal.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace sphx;
 
+// The static workspace of sphx_bind_static_workspace: device memory for callers that
+// cannot allocate.  Each device holds its own copy from the loading of this library
+// until the process ends.  Host code never passes `scratch` itself to the device (on
+// the host the name stands for a host-side shadow, not a device address): it takes
+// each device's address once with hipGetSymbolAddress and uses that.
+static __device__ __align__(256) unsigned char scratch[SPHX_STATIC_WORKSPACE_BYTES];
+
 struct sphx_ctx {
     int precision = 0, dim = 0, ninst = 0, nphase = 0;
+    int device = 0;               // the device current at sphx_create
+    bool static_ws = false;       // bound to the device's static workspace ...
+    uint64_t static_gen = 0;      // ... as its static_gen-th binding
     int64_t n = 0;
     std::vector<sphx_params> params;
     std::vector<sphx_phase> phases;     // ninst * 2 (nphase == 1 duplicates phase 0)
@@ -327,6 +339,22 @@ sphx_status status_of(sphx_ctx* c)
     return SPHX_OK;
 }
 
+// Per device: the address of its static workspace (0 until the first binding there)
+// and the number of bindings so far; a context bound to it owns it while no later
+// binding has taken it.
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices];
+std::atomic<uint64_t> g_static_gen[kMaxDevices];
+
+sphx_status owns_workspace(sphx_ctx* c)
+{
+    if (c->static_ws && g_static_gen[c->device].load(std::memory_order_acquire) != c->static_gen)
+        return fail(c, SPHX_E_WORKSPACE, "another context has since bound the static workspace of this device; "
+                                         "bind a workspace and call init_particles again");
+    return SPHX_OK;
+}
+
 // Why the last sphx_create of this thread failed (sphx_last_error(NULL) returns it).
 thread_local std::string g_create_err;
 
@@ -345,6 +373,7 @@ sphx_status create_fail(sphx_status s, const char* fmt, ...)
 sphx_status have_state(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
+    if (const sphx_status st = owns_workspace(c)) return st;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
     if (c->lost) return fail(c, SPHX_E_STATE, "the state was lost in a stalled build: set_state or init_particles");
     return SPHX_OK;
@@ -571,6 +600,7 @@ sphx_status bind_memory(sphx_ctx* c, void* dev_ptr, size_t bytes)
     c->ws_bytes = bytes;
     c->bound = true;
     c->inited = false;
+    c->static_ws = false;
     return SPHX_OK;
 }
 } // namespace
@@ -634,8 +664,10 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
     if (he != hipSuccess) return create_fail(SPHX_E_NODEV, "hipGetDeviceProperties: %s", hipGetErrorString(he));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return create_fail(SPHX_E_NODEV, "device %d is %s, not gfx950", devid, prop.gcnArchName);
+    if (devid < 0 || devid >= kMaxDevices) return create_fail(SPHX_E_NODEV, "device index %d beyond %d", devid, kMaxDevices);
     sphx_ctx* c = new sphx_ctx();
     c->precision = precision;
+    c->device = devid;
     // launch shape, measured (alternating runs, ms per step): 3D runs two force lanes per
     // particle and tiles in plain dispatch order, in 128-thread blocks (3D drop, FP32:
     // 0.247 against 0.258 for 64 threads with four tiles per CU) or 256 from 2^19
@@ -700,12 +732,42 @@ sphx_status sphx_bind_workspace(sphx_ctx* c, void* dev_ptr, size_t bytes)
     return bind_memory(c, dev_ptr, bytes);
 }
 
+sphx_status sphx_bind_static_workspace(sphx_ctx* c)
+{
+    if (!c) return SPHX_E_ARG;
+    Dev d{};
+    const size_t need = carve(d, nullptr, c->precision, c->dim, c->n, c->ncell, c->ninst);
+    if (need > (size_t)SPHX_STATIC_WORKSPACE_BYTES)
+        return fail(c, SPHX_E_WORKSPACE, "the context needs %zu bytes of workspace; the static workspace holds %zu "
+                                         "(bind caller memory with sphx_bind_workspace instead)",
+                    need, (size_t)SPHX_STATIC_WORKSPACE_BYTES);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    void*& ptr = g_static_ptr[c->device];
+    if (!ptr) {
+        // once per device, with that device current
+        int prev = 0;
+        HIP_OK(c, hipGetDevice(&prev));
+        HIP_OK(c, hipSetDevice(c->device));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        const hipError_t e2 = hipSetDevice(prev);
+        if (e != hipSuccess || !p)
+            return fail(c, SPHX_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        if (e2 != hipSuccess) return fail(c, SPHX_E_HIP, "hipSetDevice: %s", hipGetErrorString(e2));
+        ptr = p;
+    }
+    if (const sphx_status st = bind_memory(c, ptr, (size_t)SPHX_STATIC_WORKSPACE_BYTES)) return st;
+    c->static_ws = true;
+    c->static_gen = g_static_gen[c->device].fetch_add(1, std::memory_order_acq_rel) + 1;
+    return SPHX_OK;
+}
 
 sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, const double* rho, const double* m,
                                 const uint8_t* phase, const uint8_t* kind)
 {
     if (!c) return SPHX_E_ARG;
     if (!c->bound) return fail(c, SPHX_E_STATE, "bind a workspace first");
+    if (const sphx_status st = owns_workspace(c)) return st;
     if (!x || !u || !rho || !m || !phase || !kind) return fail(c, SPHX_E_ARG, "null array");
     const int64_t n = c->n;
     const bool f32 = c->precision == 1;
@@ -980,12 +1042,14 @@ sphx_status sphx_sync(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
     if (!c->bound) return fail(c, SPHX_E_STATE, "no workspace");
+    if (const sphx_status st = owns_workspace(c)) return st;
     return status_of(c);
 }
 
 sphx_status sphx_get_stats(sphx_ctx* c, sphx_stats* out)
 {
     if (!c || !out) return SPHX_E_ARG;
+    if (const sphx_status st = owns_workspace(c)) return st;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
     const sphx_status st = status_of(c);
     InstRun r;
@@ -1012,6 +1076,7 @@ sphx_status sphx_reset_interactions(sphx_ctx* c)
 {
     if (!c) return SPHX_E_ARG;
     if (!c->bound) return fail(c, SPHX_E_STATE, "no workspace");
+    if (const sphx_status st = owns_workspace(c)) return st;
     HIP_OK(c, hipMemsetAsync(c->dev.inter, 0, sizeof(unsigned long long) * kInterSlots * kInterStride, c->stream));
     return SPHX_OK;
 }
@@ -1219,6 +1284,7 @@ sphx_status sphx_get_state(sphx_ctx* c, void* blob, size_t cap, size_t* need)
 sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
 {
     if (!c || !blob) return SPHX_E_ARG;
+    if (const sphx_status st = owns_workspace(c)) return st;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first (same scene layout)");
     BlobHeader h;
     if (bytes < sizeof h) return fail(c, SPHX_E_ARG, "blob too small");

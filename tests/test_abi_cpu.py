@@ -98,6 +98,7 @@ def test_null_context_calls_are_argument_errors():
     assert L.sphx_step(None, 1) == 1
     assert L.sphx_sync(None) == 1
     assert L.sphx_compute_forces(None) == 1
+    assert L.sphx_bind_static_workspace(None) == 1
 
 
 def test_binding_constants_match_the_header():
