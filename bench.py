@@ -25,12 +25,18 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "particle-interactions/s (FP32-relative vs FP64 GPU) at 1e-5 rel. error"
-FP32_VECTOR_PEAK = 157.3e12     # MI355X FP32 vector FLOP/s (packed issue)
-# Algorithmic FLOPs of one force-pass interaction (FMA = 2): Eqs. (6), (8), (10) for a
-# fluid particle, Eq. (6) alone for a boundary particle (see the design notes).
+FP32_VECTOR_PEAK = 157.3e12     # MI355X FP32 vector FLOP/s, published (packed issue)
+# Algorithmic VALU slots per interaction (FMA = 1, square root / reciprocal = 4): the
+# force pass (Eqs. (6), (8), (10)) and the Eq. (7) pass.  A slot is priced as one FMA,
+# 2 FLOP, against the published FP32 peak.
+SLOTS_FORCE = {3: 46, 2: 36}
+SLOTS_RENORM = 20
+# Algorithmic FLOPs of one force-pass interaction (FMA = 2, square root and division 1):
+# Eqs. (6), (8), (10) for a fluid particle, Eq. (6) alone for a boundary particle.
 FLOPS_FLUID = {3: 47, 2: 36}
 FLOPS_BOUNDARY = {3: 28, 2: 21}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_fp32_drop3d_traffic.txt")
+WINDOWS = 5
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1702_07760_amd", "csrc", "sphx_kernels.hip")
 
 
@@ -43,13 +49,15 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per force launch from the committed rocprofv3 counter summary, or None
-    when the kernel source changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(kernel):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 counter summary
+    (``profiles/<kernel>_fp32_drop3d_traffic.txt``), or None when the kernel source
+    changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"{kernel}_fp32_drop3d_traffic.txt")
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as fh:
+    with open(path) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
@@ -62,25 +70,33 @@ def read_traffic():
         return None
 
 
-def timed_steps(sim, steps, warmup, torch):
+def timed_steps(sim, steps, warmup, torch, windows=WINDOWS):
+    """Warm-up steps, then `windows` timed windows of exactly `steps` steps, each
+    bracketed by stream synchronisations.  Returns the window of median duration (its
+    time and statistics) and every window's time."""
     sim.step(warmup)
     sim.sync()
-    sim.reset_interactions()
-    torch.cuda.synchronize()
-    sim.stream.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    sim.stream.synchronize()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st = sim.stats()
-    return t1 - t0, st
+    runs = []
+    for _ in range(windows):
+        sim.reset_interactions()
+        torch.cuda.synchronize()
+        sim.stream.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.stream.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        runs.append((t1 - t0, sim.stats()))
+    order = sorted(range(windows), key=lambda k: runs[k][0])
+    secs, st = runs[order[windows // 2]]
+    return secs, st, [r[0] for r in runs]
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    # five windows of 400 steps after the warm-up: the 2,000 steps of the 3D drop run
+    ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
@@ -103,15 +119,20 @@ def main():
 
     # -- FP32 cell-relative: the headline number
     sim = binding.Sim(scene, precision=binding.FP32_CELLREL)
-    off, _ = sim.get_neighbors()
+    launch = sim.launch_options()
+    off, ids = sim.get_neighbors()
     nb = np.diff(off)
     fluid = scene.kind == 0
     i_fluid, i_bnd = int(nb[fluid].sum()), int(nb[~fluid].sum())
     flops_per_inter = (FLOPS_FLUID[dim] * i_fluid + FLOPS_BOUNDARY[dim] * i_bnd) / (i_fluid + i_bnd)
-    secs, st = timed_steps(sim, args.steps, args.warmup, torch)
+    # Eq. (7) sums over same-phase neighbours only
+    same_phase = float(np.mean(np.repeat(scene.phase, nb) == scene.phase[ids]))
+    del ids
+    secs, st, windows = timed_steps(sim, args.steps, args.warmup, torch)
     value = st["interactions"] / secs
     ms_per_step = 1e3 * secs / args.steps
-    log(f"fp32: {args.steps} steps in {secs:.4f} s, {ms_per_step:.4f} ms/step, "
+    log(f"fp32 ({'tuned' if sim.tuned else 'default'} launch {launch}): {args.steps} steps x {WINDOWS} windows, "
+        f"median {ms_per_step:.4f} ms/step ({', '.join(f'{1e3 * w / args.steps:.4f}' for w in windows)}), "
         f"{value:.4e} interactions/s, t={st['t']:.5f}")
 
     # kernel durations with HIP events on the library's stream (eager replay)
@@ -124,17 +145,22 @@ def main():
     # the force group holds the pure force pass at S^n, one launch per step (the launch at
     # S* also holds the corrector); the interaction count covers both rate evaluations
     force_ms = pst["phase_ms"]["force"] / max(pst["phase_launches"]["force"], 1)
+    renorm_ms = pst["phase_ms"]["renorm"] / max(pst["phase_launches"]["renorm"], 1)
     inter_per_launch = pst["interactions"] / (2 * nprof)
-    flops_per_launch = inter_per_launch * flops_per_inter
-    achieved = flops_per_launch / (force_ms * 1e-3)
     breakdown = {k: round(pst["phase_ms"][k] / nprof, 5) for k in pst["phase_ms"]}
-    log(f"per-step kernel-group ms: {breakdown}; force launch {force_ms:.4f} ms")
-    traffic = read_traffic()
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": traffic,
-                "kernel": "k_force<float,3>", "avg_launch_ms": force_ms,
-                "flops_per_interaction": flops_per_inter,
-                "interactions_per_launch": inter_per_launch}
+    log(f"per-step kernel-group ms: {breakdown}; force launch {force_ms:.4f} ms, Eq. (7) launch {renorm_ms:.4f} ms")
+
+    def alu_roofline(kernel, slots, units, ms):
+        achieved = 2.0 * slots * units / (ms * 1e-3)          # FLOP/s, a slot priced as one FMA
+        return {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": read_traffic(kernel),
+                "kernel": kernel, "avg_launch_ms": ms, "valu_slots_per_interaction": slots,
+                "interactions_per_launch": units, "interactions_per_s": units / (ms * 1e-3)}
+
+    roofline = alu_roofline("k_force", SLOTS_FORCE[dim], inter_per_launch, force_ms)
+    roofline["flops_per_interaction"] = flops_per_inter
+    roofline["achieved_flops"] = flops_per_inter * inter_per_launch / (force_ms * 1e-3) / 1e12
+    renorm_roofline = alu_roofline("k_renorm", SLOTS_RENORM, inter_per_launch * same_phase, renorm_ms)
     sim.close()
 
     if args.calib_copy:
@@ -148,7 +174,7 @@ def main():
     fp64 = None
     if not args.no_fp64:
         s64 = binding.Sim(scene, precision=binding.FP64)
-        secs64, st64 = timed_steps(s64, args.steps, args.warmup, torch)
+        secs64, st64, _ = timed_steps(s64, args.steps, args.warmup, torch)
         fp64 = st64["interactions"] / secs64
         log(f"fp64: {secs64:.4f} s, {1e3 * secs64 / args.steps:.4f} ms/step, {fp64:.4e} interactions/s")
         s64.close()
@@ -210,11 +236,14 @@ def main():
                    "h_over_dx": 1.3, "kernel": "Wendland C2", "steps_per_launch": 1,
                    "interactions_per_step": st["interactions"] / args.steps},
         "particle_steps_per_s": n * args.steps / secs,
+        "windows_ms_per_step": [1e3 * w / args.steps for w in windows],
+        "launch": dict(launch, tuned=bool(sim.tuned)),
         "fp64_gpu_value": fp64,
         "fp32_vs_fp64": (value / fp64) if fp64 else None,
         "accuracy_vs_oracle_1step": accuracy,
         "kernel_ms_per_step": breakdown,
         "roofline": roofline,
+        "roofline_k_renorm": renorm_roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -132,8 +132,9 @@ enum {
 /* Kernel groups timed under SPHX_OPT_PROFILE. */
 enum {
     SPHX_PH_BUILD = 0,        /* hash, scan, sort, gather, cell flags */
-    SPHX_PH_RENORM = 1,       /* Eq. (7) and the state derivation after it */
-    SPHX_PH_COLOUR = 2,       /* Eq. (16) pass */
+    SPHX_PH_RENORM = 1,       /* Eq. (7) pass (with the state derivation after it, outside sphx_step) */
+    SPHX_PH_COLOUR = 2,       /* Eq. (16) passes (in sphx_step, the one at S^n shares a launch with
+                                 the state derivation after Eq. (7)) */
     SPHX_PH_FORCE = 3,        /* Eqs. (6), (8), (10)/(11), (17) pass at S^n (compute_forces, first
                                  rate evaluation of a step) */
     SPHX_PH_INTEGRATE = 4,    /* time step, predictor, and the launch that holds the rates at S*
@@ -236,6 +237,8 @@ sphx_status sphx_step(sphx_ctx* ctx, int32_t nsteps);
 sphx_status sphx_set_moving(sphx_ctx* ctx, int32_t inst, const double* disp, const double* vel);
 
 sphx_status sphx_set_option(sphx_ctx* ctx, int32_t option, int64_t value);
+/* Current value of an option (the defaults chosen at sphx_create included). */
+sphx_status sphx_get_option(sphx_ctx* ctx, int32_t option, int64_t* value);
 
 /* Wait for the stream; map the device status word to a status and clear it. */
 sphx_status sphx_sync(sphx_ctx* ctx);

@@ -92,6 +92,7 @@ def lib():
             "sphx_integrate_step": (i32, [vp, d]),
             "sphx_step": (i32, [vp, i32]),
             "sphx_set_option": (i32, [vp, i32, i64]),
+            "sphx_get_option": (i32, [vp, i32, C.POINTER(i64)]),
             "sphx_set_moving": (i32, [vp, i32, vp, vp]),
             "sphx_sync": (i32, [vp]),
             "sphx_get_stats": (i32, [vp, C.POINTER(Stats)]),
@@ -170,7 +171,8 @@ def _ptr(a):
 class Sim:
     """One sphx context on one GPU: the state of every instance of a scene."""
 
-    def __init__(self, scene, precision=FP64, device="cuda:0", graph=True, static_workspace=False):
+    def __init__(self, scene, precision=FP64, device="cuda:0", graph=True, static_workspace=False,
+                 tuned=True):
         import torch
         self.torch = torch
         self.scene = scene
@@ -203,6 +205,14 @@ class Sim:
                         "sphx_bind_workspace")
         if not graph:
             self.set_option(OPT_GRAPH, 0)
+        # the autotuner's launch shape for scenes of this kind, when it has one (block
+        # size and tile order only: results are bit-identical under any of them)
+        self.tuned = None
+        if tuned:
+            from . import tune
+            self.tuned = tune.best_for(scene.dim, scene.n, precision)
+            if self.tuned:
+                self.set_launch(**self.tuned)
         self.init_particles()
 
     # -- plumbing
@@ -259,6 +269,23 @@ class Sim:
 
     def set_option(self, opt: int, value: int):
         self._check(lib().sphx_set_option(self.ctx, int(opt), int(value)), "sphx_set_option")
+
+    def get_option(self, opt: int) -> int:
+        v = C.c_int64()
+        self._check(lib().sphx_get_option(self.ctx, int(opt), C.byref(v)), "sphx_get_option")
+        return v.value
+
+    def set_launch(self, block=None, xcd_remap=None):
+        if block is not None:
+            self.set_option(OPT_BLOCK, block)
+        if xcd_remap is not None:
+            self.set_option(OPT_XCD_REMAP, xcd_remap)
+
+    def launch_options(self) -> dict:
+        """The launch shape in use: block size and tile order (what the tuner searches),
+        and the lanes per particle of the Eq. (7) and force passes."""
+        return dict(block=self.get_option(OPT_BLOCK), xcd_remap=self.get_option(OPT_XCD_REMAP),
+                    lanes=self.get_option(OPT_LANES), force_lanes=self.get_option(OPT_FORCE_LANES))
 
     def sync(self):
         self._check(lib().sphx_sync(self.ctx), "sphx_sync")

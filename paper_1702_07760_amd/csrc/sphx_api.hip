@@ -248,6 +248,7 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.inst = c.take<InstDev>(ninst);
     d.run = c.take<InstRun>(ninst);
     d.status = c.take<uint32_t>(1);
+    d.fault = c.take<FaultRec>(1);
     d.inter = c.take<unsigned long long>((size_t)kInterSlots * kInterStride);
     d.curp = c.take<int>(1);
     d.prevp = c.take<int>(1);
@@ -334,7 +335,17 @@ sphx_status status_of(sphx_ctx* c)
                                      "or init_particles (builds use seven launches from now on)");
     }
     if (st & ST_NONFINITE) return fail(c, SPHX_E_NONFINITE, "a rate or state value became non-finite");
-    if (st & ST_DOMAIN) return fail(c, SPHX_E_DOMAIN, "a particle left a non-periodic domain");
+    if (st & ST_DOMAIN) {
+        FaultRec f;
+        HIP_OK(c, hipMemcpy(&f, c->dev.fault, sizeof f, hipMemcpyDeviceToHost));
+        HIP_OK(c, hipMemset(c->dev.fault, 0, sizeof f));
+        if (!f.claimed) return fail(c, SPHX_E_DOMAIN, "a particle left a non-periodic domain");
+        const InstDev& I = c->inst[f.inst < (uint32_t)c->ninst ? f.inst : 0];
+        return fail(c, SPHX_E_DOMAIN,
+                    "a particle left a non-periodic domain: particle %u (instance %u) at (%.9g, %.9g, %.9g) m, "
+                    "cell (%d, %d, %d) of a %d x %d x %d grid",
+                    f.id, f.inst, f.x[0], f.x[1], f.x[2], f.cell[0], f.cell[1], f.cell[2], I.nc[0], I.nc[1], I.nc[2]);
+    }
     if (st & ST_DT) return fail(c, SPHX_E_DT, "dt * max|u| exceeded half the neighbour skin");
     return SPHX_OK;
 }
@@ -452,10 +463,17 @@ void enqueue_renorm(sphx_ctx* c, bool force)
 void enqueue_step(sphx_ctx* c)
 {
     enqueue_build(c);
-    {
-        // Eq. (7) when due, then the derive pass and the colour pass at S^n in one launch
-        Timed t(c, SPHX_PH_RENORM);
-        launch_renorm_colour(c->dev, c->launch, c->stream);
+    // Eq. (7) when due, then the derive pass with the colour pass at S^n in one launch
+    // (timed as two groups when profiling)
+    if (c->profile) {
+        {
+            Timed t(c, SPHX_PH_RENORM);
+            launch_renorm_colour(c->dev, c->launch, c->stream, 1);
+        }
+        Timed t(c, SPHX_PH_COLOUR);
+        launch_renorm_colour(c->dev, c->launch, c->stream, 2);
+    } else {
+        launch_renorm_colour(c->dev, c->launch, c->stream, 3);
     }
     enqueue_rates(c, false, true, false);
     enqueue_integrate(c, 0.0);
@@ -852,6 +870,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     std::memset(run.data(), 0, sizeof(InstRun) * c->ninst);
     HIP_OK(c, hipMemcpyAsync(d.run, run.data(), sizeof(InstRun) * c->ninst, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemsetAsync(d.status, 0, sizeof(uint32_t), s));
+    HIP_OK(c, hipMemsetAsync(d.fault, 0, sizeof(FaultRec), s));
     HIP_OK(c, hipMemsetAsync(d.inter, 0, sizeof(unsigned long long) * kInterSlots * kInterStride, s));
     HIP_OK(c, hipMemsetAsync(d.icount, 0, sizeof(uint32_t), s));
     HIP_OK(c, hipMemsetAsync(d.bar, 0, (512 + 4096) * sizeof(unsigned), s));
@@ -1035,6 +1054,24 @@ sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
     default: return fail(c, SPHX_E_ARG, "unknown option %d", (int)option);
     }
     drop_graphs(c);
+    return SPHX_OK;
+}
+
+sphx_status sphx_get_option(sphx_ctx* c, int32_t option, int64_t* value)
+{
+    if (!c || !value) return SPHX_E_ARG;
+    switch (option) {
+    case SPHX_OPT_DEBUG_TERMS: *value = c->launch.debug_terms; break;
+    case SPHX_OPT_BLOCK: *value = c->launch.block; break;
+    case SPHX_OPT_XCD_REMAP: *value = c->launch.xcd_remap; break;
+    case SPHX_OPT_LANES: *value = c->launch.lanes; break;
+    case SPHX_OPT_FORCE_LANES: *value = c->launch.force_lanes; break;
+    case SPHX_OPT_GRAPH: *value = c->use_graph; break;
+    case SPHX_OPT_ONE_LAUNCH_BUILD: *value = c->launch.one_launch_build; break;
+    case SPHX_OPT_FORCE_STALL: *value = c->launch.stall_at; break;
+    case SPHX_OPT_PROFILE: *value = c->profile; break;
+    default: return fail(c, SPHX_E_ARG, "unknown option %d", (int)option);
+    }
     return SPHX_OK;
 }
 

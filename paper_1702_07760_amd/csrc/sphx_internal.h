@@ -69,6 +69,15 @@ struct InstDev {
     float f_vpair[2][2], f_rho0[2], f_mass[2];
 };
 
+// The first particle found outside a non-periodic domain: the first hash that sees one
+// claims the record.  Original index, instance, absolute position and the cell index
+// that position maps to (before clamping into the grid).
+struct FaultRec {
+    uint32_t claimed, id, inst, pad;
+    int32_t cell[4];
+    double x[4];
+};
+
 // Per-instance run variables on the device.
 struct InstRun {
     unsigned long long umax2;  // bit pattern of max |u|^2 (FP64, non-negative)
@@ -105,6 +114,7 @@ struct Dev {
     const InstDev* inst; // device
     InstRun* run;        // device
     uint32_t* status;
+    FaultRec* fault;     // details of the first ST_DOMAIN
     unsigned long long* inter;
     int* curp;           // which state set (0/1) holds the current sorted state
     int* prevp;          // during a rebuild: the set being sorted from (the old curp)
@@ -157,7 +167,8 @@ void launch_colour(const Dev& d, bool star, const Launch& L, hipStream_t s);
 void launch_force(const Dev& d, bool star, bool reduce_max, bool correct, const Launch& L, hipStream_t s);
 void launch_derive(const Dev& d, const Launch& L, hipStream_t s);
 void launch_restore(const Dev& d, hipStream_t s);
-void launch_renorm_colour(const Dev& d, const Launch& L, hipStream_t s);   // Eq. (7), derive + colour at S^n
+// Eq. (7) (parts bit 0), then the derive pass and the colour pass at S^n (bit 1)
+void launch_renorm_colour(const Dev& d, const Launch& L, hipStream_t s, int parts = 3);
 void launch_predict(const Dev& d, double dt_override, const Launch& L, hipStream_t s);   // a9 and S*
 // neighbour export: counts (pass 0) or ids (pass 1) in sorted order
 void launch_export(const Dev& d, int pass, const uint32_t* off, uint32_t* out,

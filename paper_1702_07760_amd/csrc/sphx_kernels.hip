@@ -567,6 +567,8 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
     const uint32_t info = O.info[k];
     const InstDev& I = d.inst[info_inst(info)];
     int c[3] = {0, 0, 0};
+    int raw[3] = {0, 0, 0};     // cells before clamping (for the fault record)
+    double xa[3] = {0.0, 0.0, 0.0};
     bool out = false;
     if constexpr (sizeof(R) == 8) {
         const double4 p = ((const double4*)d.S[cur].pos)[k];
@@ -575,6 +577,8 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
             if (!isfinite(x[dd])) atomicOr(d.status, ST_NONFINITE);
             double v = floor((x[dd] - I.lo[dd]) / I.cs[dd]);
             int ci = isfinite(v) ? (int)fmax(fmin(v, 1e9), -1e9) : 0;
+            raw[dd] = ci;
+            xa[dd] = x[dd];
             if (ci < 0 || ci >= I.nc[dd]) {
                 if (!I.periodic[dd]) out = true;
                 ci = ci < 0 ? 0 : I.nc[dd] - 1;
@@ -595,6 +599,8 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
             }
             const float s = I.f_cs[dd];
             const float sh = fminf(fmaxf(floorf(o[dd] / s), -1.0e6f), 1.0e6f);
+            raw[dd] = c[dd] + (int)sh;
+            xa[dd] = I.lo[dd] + (double)c[dd] * I.cs[dd] + (double)o[dd] + (double)e[dd];
             if (sh != 0.0f) {
                 // the offset moves sh cells: o - sh cs = (o - sh s) - sh (cs - s).  o - sh s is
                 // taken with its rounding error (TwoSum; sh s is exact for |sh| <= 2), and that
@@ -618,7 +624,17 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
         pos[k] = make_float4(o[0], o[1], o[2], p.w);
         d.S[cur].plo[k] = make_float4(e[0], e[1], e[2], lo.w);
     }
-    if (out) atomicOr(d.status, ST_DOMAIN);
+    if (out) {
+        atomicOr(d.status, ST_DOMAIN);
+        if (atomicCAS(&d.fault->claimed, 0u, 1u) == 0u) {
+            d.fault->id = O.id[k];
+            d.fault->inst = info_inst(info);
+            for (int dd = 0; dd < 3; ++dd) {
+                d.fault->cell[dd] = raw[dd];
+                d.fault->x[dd] = xa[dd];
+            }
+        }
+    }
     return I.cell_base + (uint32_t)c[0] + (uint32_t)I.nc[0] * ((uint32_t)c[1] + (uint32_t)I.nc[1] * (uint32_t)c[2]);
 }
 
@@ -2078,15 +2094,16 @@ void launch_restore(const Dev& d, hipStream_t s)
     }));
 }
 
-void launch_renorm_colour(const Dev& d, const Launch& L, hipStream_t s)
+void launch_renorm_colour(const Dev& d, const Launch& L, hipStream_t s, int parts)
 {
     const dim3 grid(blocks_for(d.n * L.lanes, L.block)), block(L.block);
     // colour blocks: the list length is known only on the device (grid-stride)
     const unsigned cb = std::min<unsigned>(blocks_for(d.n * kColourLanes, 256), 1024u);
     const unsigned db = blocks_for(d.n, 256);
     SPHX_DISPATCH(d.precision, d.dim, ({
-        SPHX_LANES(L.lanes, ({ hipLaunchKernelGGL((k_renorm<R, D, P>), grid, block, 0, s, d, L.xcd_remap, 0); }));
-        hipLaunchKernelGGL((k_derive_colour<R, D>), dim3(cb + db), dim3(256), 0, s, d, 0, cb);
+        if (parts & 1)
+            SPHX_LANES(L.lanes, ({ hipLaunchKernelGGL((k_renorm<R, D, P>), grid, block, 0, s, d, L.xcd_remap, 0); }));
+        if (parts & 2) hipLaunchKernelGGL((k_derive_colour<R, D>), dim3(cb + db), dim3(256), 0, s, d, 0, cb);
     }));
 }
 

@@ -691,16 +691,34 @@ def test_blocks_above_256_are_rejected():
 def test_tuner_returns_a_working_option_set():
     from paper_1702_07760_amd import tune
     s = inputs.drop2d(perturb=True)
-    best = tune.tune(s, steps=2, warmup=1, skins=(0.1,), blocks=(128, 256), remaps=(1, 16), lanes=(1, 4),
-                     save=False, log=None)
+    best = tune.tune(s, binding.FP32_CELLREL, steps=2, warmup=1, repeats=1, blocks=(64, 256),
+                     remaps=(1, 16), save=False, log=None)
     assert best["ms_per_step"] > 0
-    # the search starts from the defaults (block 64, 4 lanes, 1 force lane, 4 tiles per CU in FP32)
-    assert best["lanes"] in (1, 4) and best["force_lanes"] in (1, 4) and best["block"] in (64, 128, 256)
-    assert best["xcd_remap"] in (1, 4, 16)
-    sim = binding.Sim(s.with_params(skin_coef=best["skin"]), precision=binding.FP32_CELLREL)
-    tune.apply(sim, best)
+    assert best["block"] in (64, 256) and best["xcd_remap"] in (1, 4, 16)
+    sim = binding.Sim(s, precision=binding.FP32_CELLREL, tuned=False)
+    sim.set_launch(block=best["block"], xcd_remap=best["xcd_remap"])
+    assert sim.launch_options()["block"] == best["block"]
     sim.step(2)
     sim.sync()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_tuned_launch_shapes_give_bit_identical_runs(prec):
+    # the options the tuner searches (block size, tile order) must not change any result
+    s = inputs.drop3d(scale=0.3, perturb=True)
+    print(f"case tuned launch precision={prec} n={s.n}", flush=True)
+    runs = []
+    for block, remap in ((None, None), (64, 16), (256, 1), (192, 0)):
+        sim = binding.Sim(s, precision=prec, tuned=False)
+        sim.set_launch(block=block, xcd_remap=remap)
+        sim.step(12)
+        sim.sync()
+        runs.append([sim.get_field(f) for f in (binding.F_X, binding.F_U, binding.F_RHO, binding.F_A)]
+                    + [sim.stats()["interactions"]])
+        sim.close()
+    for r in runs[1:]:
+        for a, b in zip(runs[0], r):
+            assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("remap", [0, 1, 16])
