@@ -267,10 +267,11 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.slot = c.take<uint32_t>(un);
     d.tsrc = c.take<uint32_t>(un);
     d.tid = c.take<uint32_t>(un);
+    // the gathered records have one more slot: index n, the sentinel of padded lists
     for (int s = 0; s < 2; ++s) {
-        d.S[s].pos = c.take<char>(un * 4 * R);
-        d.S[s].vel = c.take<char>(un * 4 * R);
-        d.S[s].aux = c.take<char>(un * 4 * R);
+        d.S[s].pos = c.take<char>((un + 1) * 4 * R);
+        d.S[s].vel = c.take<char>((un + 1) * 4 * R);
+        d.S[s].aux = c.take<char>((un + 1) * 4 * R);
         d.S[s].plo = precision ? c.take<float4>(un) : nullptr;
         d.S[s].vlo = precision ? c.take<float4>(un) : nullptr;
         d.O[s].key = c.take<uint32_t>(un);
@@ -278,14 +279,14 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
         d.O[s].info = c.take<uint32_t>(un);
         d.O[s].ref = c.take<double4>(un);
     }
-    d.star.pos = c.take<char>(un * 4 * R);
-    d.star.vel = c.take<char>(un * 4 * R);
-    d.star.aux = c.take<char>(un * 4 * R);
+    d.star.pos = c.take<char>((un + 1) * 4 * R);
+    d.star.vel = c.take<char>((un + 1) * 4 * R);
+    d.star.aux = c.take<char>((un + 1) * 4 * R);
     d.star.plo = nullptr;
     d.star.vlo = nullptr;
     d.rho_tmp = c.take<char>(un * R);
     d.acc = c.take<char>(un * 4 * R);
-    d.gc = c.take<char>(un * 4 * R);
+    d.gc = c.take<char>((un + 1) * 4 * R);
     d.terms = c.take<char>(un * 12 * R);
     return (c.off + 255) & ~size_t(255);
 }
@@ -658,7 +659,7 @@ sphx_status sphx_create(int32_t precision, const sphx_params* per_inst, const sp
         if (counts[b] < 1) return create_fail(SPHX_E_ARG, "instance %d has no particles", b);
         n += counts[b];
     }
-    if (n >= (1ll << 26)) return create_fail(SPHX_E_ARG, "%lld particles: at most 2^26 - 1 (26-bit list indices)", (long long)n);
+    if (n >= (1ll << 25)) return create_fail(SPHX_E_ARG, "%lld particles: at most 2^25 - 1 (25-bit list indices)", (long long)n);
     std::string why;
     for (int b = 0; b < ninst; ++b) {
         if (!check_params(per_inst[b], per_inst[0].dim, why)) return create_fail(SPHX_E_ARG, "instance %d: %s", b, why.c_str());
@@ -876,7 +877,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemsetAsync(d.bar, 0, (512 + 4096) * sizeof(unsigned), s));
     HIP_OK(c, hipMemsetAsync(d.cnt, 0, sizeof(uint32_t) * c->ncell, s));
     HIP_OK(c, hipMemsetAsync(d.acc, 0, n * 4 * R, s));
-    HIP_OK(c, hipMemsetAsync(d.gc, 0, n * 4 * R, s));
+    HIP_OK(c, hipMemsetAsync(d.gc, 0, (n + 1) * 4 * R, s));
     HIP_OK(c, hipMemsetAsync(d.terms, 0, n * 12 * R, s));
     HIP_OK(c, hipMemcpyAsync(d.S[0].pos, pos.data(), pos.size(), hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(d.S[0].vel, vel.data(), vel.size(), hipMemcpyHostToDevice, s));
@@ -884,6 +885,16 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     if (f32) {
         HIP_OK(c, hipMemcpyAsync(d.S[0].plo, plo.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
         HIP_OK(c, hipMemcpyAsync(d.S[0].vlo, vlo.data(), n * sizeof(float4), hipMemcpyHostToDevice, s));
+    }
+    // the sentinel record at index n of every gathered array (no kernel writes it): a
+    // position far outside every domain, zero velocity, volume and mass
+    std::vector<char> spos(4 * R), szero(4 * R, 0);
+    if (f32) ((float4*)spos.data())[0] = make_float4(1e30f, 1e30f, 1e30f, 0.0f);
+    else ((double4*)spos.data())[0] = make_double4(1e150, 1e150, 1e150, 0.0);
+    for (StateSet* set : {&d.S[0], &d.S[1], &d.star}) {
+        HIP_OK(c, hipMemcpyAsync((char*)set->pos + n * 4 * R, spos.data(), 4 * R, hipMemcpyHostToDevice, s));
+        HIP_OK(c, hipMemcpyAsync((char*)set->vel + n * 4 * R, szero.data(), 4 * R, hipMemcpyHostToDevice, s));
+        HIP_OK(c, hipMemcpyAsync((char*)set->aux + n * 4 * R, szero.data(), 4 * R, hipMemcpyHostToDevice, s));
     }
     HIP_OK(c, hipMemcpyAsync(d.O[0].key, key.data(), n * 4, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(d.O[0].id, id.data(), n * 4, hipMemcpyHostToDevice, s));
@@ -1376,9 +1387,13 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
         for (uint32_t k = 0; k < nc; ++k)
             if (u32(cst, k + 1) < u32(cst, k)) return fail(c, SPHX_E_ARG, "blob: cell table not ascending");
         for (uint32_t i = 0; i < n; ++i) {
-            const uint32_t m = std::min(u32(nbc, i), cap);
-            for (uint32_t e = 0; e < m; ++e)
-                if ((u32(nbl, (size_t)e * n + i) & kIdxMask) >= n)
+            // entries below the count name particles; the padding after them, which the
+            // walks also read, names at most the sentinel record n
+            const uint32_t cnt = u32(nbc, i);
+            const uint32_t m = std::min(cnt, cap);
+            const uint32_t padded = cnt <= cap ? std::min((cnt + kListPad - 1u) & ~(kListPad - 1u), cap) : cap;
+            for (uint32_t e = 0; e < padded; ++e)
+                if ((u32(nbl, (size_t)e * n + i) & kIdxMask) >= (e < m ? n : n + 1))
                     return fail(c, SPHX_E_ARG, "blob: neighbour list of particle %u out of range", i);
         }
         const uint32_t ni = u32(at[13], 0);

@@ -29,16 +29,22 @@ enum : uint32_t { K_FLUID = 0, K_WALL = 1, K_MOVING = 2 };
 // entries, which must divide the capacity for those reads to stay inside the list (the
 // walk checks this at compile time).
 constexpr uint32_t kListCap2 = 48u, kListCap3 = 128u;
+static_assert(kListCap2 % 16u == 0 && kListCap3 % 16u == 0, "capacities are multiples of the padding");
 
 // Interaction count: kInterSlots 64-bit counters, kInterStride words (128 bytes) apart.
 // Wave w of a force launch adds into counter w mod kInterSlots, so the adds of
 // concurrent waves land on different cache lines; the host sums the counters.
 constexpr uint32_t kInterSlots = 256u, kInterStride = 16u;
 
-// Neighbour-list entry: particle index j in the low 26 bits; in FP32 the cell offset
-// delta = c_i - c_j (components in {-1, 0, 1}) as (dx + 1) + 3 (dy + 1) + 9 (dz + 1) in
-// bits 26-30; the phase of j in bit 31 (phases never change, so the list carries them).
-constexpr uint32_t kIdxBits = 26, kIdxMask = (1u << kIdxBits) - 1u, kCodeMask = 31u, kPhaseShift = 31;
+// Neighbour-list entry: particle index j in the low 25 bits; in FP32 the cell offset
+// delta = c_i - c_j (components in {-1, 0, 1}) as two bits per axis, delta_x + 1 in bits
+// 25-26, delta_y + 1 in bits 27-28, delta_z + 1 in bits 29-30; the phase of j in bit 31
+// (phases never change, so the list carries them).  A list is padded with the entry
+// kSentinel-index n up to a multiple of kListPad entries, so that the walks read whole
+// batches without checking each entry against the count: index n is a record placed
+// far outside every domain, so it is never within the cutoff.
+constexpr uint32_t kIdxBits = 25, kIdxMask = (1u << kIdxBits) - 1u, kPhaseShift = 31;
+constexpr uint32_t kListPad = 16u;
 
 struct InstDev {
     double lo[3], hi[3], span[3], cs[3];

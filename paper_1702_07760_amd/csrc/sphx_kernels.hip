@@ -227,7 +227,7 @@ template <> struct Lane<float> {
 // Per-row constants: the y/z cell offsets of a stencil row are fixed.
 template <class R> struct Row {
     uint32_t base;   // key of the row's first cell
-    uint32_t code;   // 3 (delta_y + 1) + 9 (delta_z + 1), delta = c_i - c_j
+    uint32_t code;   // (delta_y + 1) << 2 | (delta_z + 1) << 4, delta = c_i - c_j
     float dy1, dz1;  // delta_y + 1, delta_z + 1 as floats
 };
 
@@ -278,7 +278,7 @@ __device__ __forceinline__ uint32_t pair_r(const IC& I, const Lane<float>& L, co
     r[0] = fmaf((float)(dcx + 1), I.f_cs[0], L.om[0] - pj.x);
     r[1] = fmaf(row.dy1, I.f_cs[1], L.om[1] - pj.y);
     r[2] = DIM == 3 ? fmaf(row.dz1, I.f_cs[2], L.om[2] - pj.z) : 0.0f;
-    return (uint32_t)(dcx + 1) + row.code;
+    return (uint32_t)(dcx + 1) | row.code;
 }
 
 // r_ij for a list entry e (same arithmetic as the stencil form above).
@@ -295,11 +295,7 @@ template <int DIM, class IC>
 __device__ __forceinline__ void list_pair_r(const IC& I, const Lane<float>& L, const float4& pj,
                                             uint32_t e, float r[3])
 {
-    // c = (dx + 1) + 3 (dy + 1) + 9 (dz + 1) < 27: c / 9 = (57 c) >> 9 and, for the
-    // remainder m < 9, m / 3 = (11 m) >> 5 (exact on these ranges; 24-bit multiplies)
-    const uint32_t c = (e >> kIdxBits) & kCodeMask;
-    const uint32_t cz = __umul24(c, 57u) >> 9, m = c - __umul24(cz, 9u);
-    const uint32_t cy = __umul24(m, 11u) >> 5, cx = m - __umul24(cy, 3u);
+    const uint32_t cx = (e >> kIdxBits) & 3u, cy = (e >> (kIdxBits + 2)) & 3u, cz = (e >> (kIdxBits + 4)) & 3u;
     r[0] = fmaf((float)cx, I.f_cs[0], L.om[0] - pj.x);
     r[1] = fmaf((float)cy, I.f_cs[1], L.om[1] - pj.y);
     r[2] = DIM == 3 ? fmaf((float)cz, I.f_cs[2], L.om[2] - pj.z) : 0.0f;
@@ -349,7 +345,7 @@ __device__ __forceinline__ void for_neighbors(const IC& I, const uint32_t* __res
             else if (cy < 0 || cy >= I.nc[1]) continue;
             Row<R> row;
             row.base = I.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)I.nc[1] * (uint32_t)cz);
-            row.code = 3u * (uint32_t)(1 - dy) + 9u * (uint32_t)(1 - dz);
+            row.code = ((uint32_t)(1 - dy) << 2) | ((uint32_t)(1 - dz) << 4);
             row.dy1 = (float)(1 - dy);
             row.dz1 = (float)(1 - dz);
             // runs [a, b) and, per run, dcx = db - (k >= m0) - (k >= m1): m0 and m1 are
@@ -451,9 +447,11 @@ template <class R> struct MaxBlock { static constexpr int value = 256; };
 // (entry q of particle i at q * n + i), so a wave reads them coalesced; U entries are
 // fetched per batch so that their loads are in flight together.  With P lanes per
 // particle, lane `sub` takes the entries q = t P + sub: the row offset t P n is the
-// same for all lanes and the lane part sub n + i is fixed.  A batch may read entries
-// past cnt (never past the capacity, a multiple of U P); they are replaced by a valid
-// index and skipped.
+// same for all lanes (it is taken into scalar registers, so a list load needs no
+// per-lane address arithmetic) and the lane part sub n + i is fixed.  A batch may read
+// entries past cnt: the list is padded with the sentinel entry (index n, a record far
+// outside the domain) up to a multiple of kListPad, which every batch end stays below,
+// so no entry is checked against the count.
 // With SKIP, entries of phase skip_phase (known from the entry) are passed over before
 // anything of them is read.
 template <class R, int DIM, int U, int P, bool SKIP = false, class IC, class PS, class Load, class Body>
@@ -461,15 +459,20 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const PS& po
                                          uint32_t i, const Lane<R>& L, uint32_t cnt, uint32_t sub,
                                          Load&& load, Body&& body, uint32_t skip_phase = 0)
 {
-    static_assert(kListCap2 % (U * P) == 0 && kListCap3 % (U * P) == 0,
-                  "a batch of U entries on P lanes must divide the list capacity");
+    static_assert(kListPad % (U * P) == 0, "a batch of U entries on P lanes must divide the list padding");
     using X = decltype(load(0u));
     const uint32_t n = (uint32_t)d.n;
-    const char* __restrict__ base = (const char*)d.nbl;
-    const uint32_t lane_off = (sub * n + i) * 4u;   // < 2^31: n < 2^26, sub < 8
-    const size_t step = (size_t)P * n * 4u;
+    const uint32_t lane_off = (sub * n + i) * 4u;   // < 2^30: n < 2^25, sub < 8
     const R cut2 = cut2_of<R>(I);
-    auto entry = [&](uint32_t q) { return *(const uint32_t*)(base + (size_t)q * step + lane_off); };
+    // t is the same in every active lane (all lanes run the same batches; lanes only
+    // leave the loop early), so the row address is wave-uniform: a list load is a buffer
+    // load whose resource (the row's base) is built in scalar registers, with the lane's
+    // fixed 32-bit offset
+    auto entry = [&](uint32_t t) {
+        const uint32_t* row = d.nbl + (size_t)ufirst(t) * ((size_t)P * n);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)row, (short)0, 0x7fffffff, 0x00020000);
+        return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)lane_off, 0, 0);
+    };
     // the entries of the next batch are in flight while a batch is computed; they are
     // requested after the current gathers: vector loads retire in order, so a wait for
     // the gathers does not wait for the list entries too
@@ -480,19 +483,14 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const PS& po
     }
     for (uint32_t t0 = 0; t0 * P + sub < cnt; t0 += U) {
         uint32_t e[U];
-        bool ok[U];
         R4<R> pj[U];
         X x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool in = (t0 + (uint32_t)u) * P + sub < cnt;
-            e[u] = in ? nxt[u] : 0u;
-            ok[u] = SKIP ? in && entry_phase(e[u]) != skip_phase : in;
-        }
+        for (int u = 0; u < U; ++u) e[u] = nxt[u];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t k = e[u] & kIdxMask;
-            if (!SKIP || ok[u]) {
+            if (!SKIP || entry_phase(e[u]) != skip_phase) {
                 pj[u] = pos[k];
                 x[u] = load(k);
             }
@@ -503,7 +501,7 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const PS& po
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (ok[u]) {
+            if (!SKIP || entry_phase(e[u]) != skip_phase) {
                 R r[3];
                 list_pair_r<DIM>(I, L, pj[u], e[u], r);
                 const R r2 = dist2<DIM>(r[0], r[1], r[2]);
@@ -917,6 +915,11 @@ __device__ __forceinline__ void nlist_one(const Dev& d, uint32_t i, uint32_t sub
                 }
                 cnt += (uint32_t)__popc(grp);
             });
+        // pad with the sentinel entry (index n, code 0, phase 0) to a multiple of kListPad
+        if (cnt <= cap) {
+            const uint32_t end = (cnt + kListPad - 1u) & ~(kListPad - 1u);
+            for (uint32_t q = cnt + sub; q < end; q += P) nb[(size_t)q * n] = (uint32_t)n;
+        }
         const bool gother = ((uint32_t)(__ballot(other) >> gbase) & gmask) != 0u;
         if (sub == 0) {
             d.nbc[i] = cnt;
@@ -1154,22 +1157,49 @@ __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_a
 // F = -5 alpha / h^2 (1 - q/2)^3, q = |r| / h.
 template <class R, class IC> __device__ __forceinline__ R kernel_w(const IC& I, R r2)
 {
+    // 1 - q/2 and 2q + 1 as fused multiply-adds of |r| (wave-uniform factors)
     if constexpr (sizeof(R) == 8) {
-        const double q = sqrt(r2) * I.inv_h, t = 1.0 - 0.5 * q, t2 = t * t;
-        return I.wcoef * (t2 * t2) * (2.0 * q + 1.0);
+        const double s = sqrt(r2), t = fma(s, -0.5 * I.inv_h, 1.0), t2 = t * t;
+        return I.wcoef * (t2 * t2) * fma(s, 2.0 * I.inv_h, 1.0);
     } else {
-        const float q = fsqrt(r2) * I.f_inv_h, t = 1.0f - 0.5f * q, t2 = t * t;
-        return I.f_wcoef * (t2 * t2) * (2.0f * q + 1.0f);
+        const float s = fsqrt(r2), t = fmaf(s, -0.5f * I.f_inv_h, 1.0f), t2 = t * t;
+        return I.f_wcoef * (t2 * t2) * fmaf(s, 2.0f * I.f_inv_h, 1.0f);
+    }
+}
+
+// W / alpha_d: Eq. (7) is a ratio of two kernel sums, so the constant factor cancels.
+template <class R, class IC> __device__ __forceinline__ R kernel_w_shape(const IC& I, R r2)
+{
+    if constexpr (sizeof(R) == 8) {
+        const double s = sqrt(r2), t = fma(s, -0.5 * I.inv_h, 1.0), t2 = t * t;
+        return (t2 * t2) * fma(s, 2.0 * I.inv_h, 1.0);
+    } else {
+        const float s = fsqrt(r2), t = fmaf(s, -0.5f * I.f_inv_h, 1.0f), t2 = t * t;
+        return (t2 * t2) * fmaf(s, 2.0f * I.f_inv_h, 1.0f);
+    }
+}
+
+// (1 - q/2)^3 = F / (-5 alpha_d / h^2): the force pass sums with it and applies the
+// constant factor once per particle.
+template <class R, class IC> __device__ __forceinline__ R kernel_t3(const IC& I, R r2)
+{
+    if constexpr (sizeof(R) == 8) {
+        const double t = fma(sqrt(r2), -0.5 * I.inv_h, 1.0);
+        return t * t * t;
+    } else {
+        const float t = fmaf(fsqrt(r2), -0.5f * I.f_inv_h, 1.0f);
+        return t * t * t;
     }
 }
 
 template <class R, class IC> __device__ __forceinline__ R kernel_f(const IC& I, R r2)
 {
+    // t = 1 - q/2 as one fused multiply-add of |r| (the factor -1/(2h) is wave-uniform)
     if constexpr (sizeof(R) == 8) {
-        const double t = 1.0 - 0.5 * (sqrt(r2) * I.inv_h);
+        const double t = fma(sqrt(r2), -0.5 * I.inv_h, 1.0);
         return I.fcoef * (t * t * t);
     } else {
-        const float t = 1.0f - 0.5f * (fsqrt(r2) * I.f_inv_h);
+        const float t = fmaf(fsqrt(r2), -0.5f * I.f_inv_h, 1.0f);
         return I.f_fcoef * (t * t * t);
     }
 }
@@ -1194,8 +1224,9 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
     per_instance(d, info_inst(info), [&](const InstU& I) {
         Lane<R> L;
         L.load(I, pi, O.key[i]);
-        // the self term once per particle, on its first lane
-        const R w0 = sub == 0 ? kernel_w<R>(I, (R)0) : (R)0;
+        // the self term once per particle, on its first lane; every sum below carries W
+        // without its constant factor alpha_d, which cancels in the quotient of Eq. (7)
+        const R w0 = sub == 0 ? (R)1 : (R)0;
         const double rho0 = ph ? I.rho0[1] : I.rho0[0];
         if (qpos && I.umass) {
             // every j in the sums has i's phase and so i's mass m: Eq. (7) becomes
@@ -1206,7 +1237,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
                 [](uint32_t) { return NoExtra{}; },
                 [&](uint32_t, const R*, R r2, const R4<R>& pj, uint32_t phj, NoExtra) {
                     if (phj != ph) return;
-                    const R w = kernel_w<R>(I, r2);
+                    const R w = kernel_w_shape<R>(I, r2);
                     sw += w;
                     sq += w * pj.w;
                 });
@@ -1230,7 +1261,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
                 [&](uint32_t k) { return Pair{aux[k].x, aux[k].z}; },
                 [&](uint32_t, const R*, R r2, const R4<R>&, uint32_t phj, const Pair& x) {
                     if (phj != ph) return;
-                    const R w = kernel_w<R>(I, r2);
+                    const R w = kernel_w_shape<R>(I, r2);
                     num += x.a * w;
                     den += x.b * w;
                 });
@@ -1247,7 +1278,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
                 },
                 [&](uint32_t, const R*, R r2, const R4<R>&, uint32_t phj, const Pair& x) {
                     if (phj != ph) return;
-                    const R vw = x.a * kernel_w<R>(I, r2);
+                    const R vw = x.a * kernel_w_shape<R>(I, r2);
                     num += vw * x.b;
                     den += vw;
                 });
@@ -1454,6 +1485,7 @@ template <class R, int DIM> struct ForceLane {
     bool fluid, fli, massform;
     R4<R> vi;
     R mi, Ai, alpha, ci, gi2, vp0, vp1, delta2;
+    R mA0, mA1;   // m_j A_i for a neighbour of phase 0 / 1 (masses uniform per phase)
     R gi[3];
     R cont, ap[3], av[3], as[3];
     uint32_t cnt;
@@ -1491,6 +1523,8 @@ template <class R, int DIM> struct ForceLane {
             delta2 = I.f_delta2;
         }
         massform = I.cont_form == 1;
+        if constexpr (sizeof(R) == 8) { mA0 = I.mass[0] * Ai; mA1 = I.mass[1] * Ai; }
+        else { mA0 = I.f_mass[0] * Ai; mA1 = I.f_mass[1] * Ai; }
         cont = 0;
         for (int q = 0; q < 3; ++q) ap[q] = av[q] = as[q] = 0;
         cnt = 0;
@@ -1498,26 +1532,31 @@ template <class R, int DIM> struct ForceLane {
 
     // One neighbour j = k with r_ij, |r_ij|^2 < 4h^2, position record pj = (x_j, m_j A_j),
     // phase phj, velocity record vk = (u_j, +-V_j), the sign of V_j being j's interface
-    // flag, and mass mj.
-    template <class IC>
+    // flag, mass mj, and m_j A_i.  MF: the mass form of the continuity equation (Eq. (5)).
+    // grad_i W_ij = F r_ij enters through F times scalars of r_ij (u_ij . r_ij, the
+    // pressure factor), so the gradient vector itself is formed only for surface tension.
+    // cont, ap and av are summed without the kernel's constant factor -5 alpha_d / h^2,
+    // which finish() applies once.
+    template <bool MF, class IC>
     __device__ __forceinline__ void pair(const IC& I, const R4<R>* __restrict__ gc, uint32_t k, const R* r,
-                                         R r2, const R4<R>& pj, uint32_t phj, const R4<R>& vk, R mj)
+                                         R r2, const R4<R>& pj, uint32_t phj, const R4<R>& vk, R mj, R mjAi)
     {
         ++cnt;
-        const R F = kernel_f<R>(I, r2);
-        const R w[3] = {F * r[0], F * r[1], F * r[2]};           // grad_i W_ij
+        const R T = kernel_t3<R>(I, r2);                          // F / (-5 alpha_d / h^2)
         const R u[3] = {vi.x - vk.x, vi.y - vk.y, vi.z - vk.z}; // u_ij
-        const R udw = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+        const R ur = u[0] * r[0] + u[1] * r[1] + u[2] * r[2];
         const R Vj = fabs(vk.w);
-        cont += (massform ? mj : Vj) * udw;                       // Eq. (6) / (5)
+        cont += (MF ? mj : Vj) * (T * ur);                         // Eq. (6) / (5)
         if (!fluid) return;
-        const R pc = mj * Ai + pj.w;                              // m_j (A_i + A_j)
-        ap[0] -= pc * w[0]; ap[1] -= pc * w[1]; ap[2] -= pc * w[2];
-        const R lap = (F * r2) * frcp(r2 + delta2);               // r.gradW / (r^2 + delta^2)
+        const R pcT = (mjAi + pj.w) * T;                          // m_j (A_i + A_j) T
+        ap[0] -= pcT * r[0]; ap[1] -= pcT * r[1]; ap[2] -= pcT * r[2];
+        const R lap = (T * r2) * frcp(r2 + delta2);               // r.gradW / (r^2 + delta^2), unscaled
         const R cv = Vj * (phj ? vp1 : vp0) * lap;
         av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
         const bool flk = vk.w < (R)0;
         if (fli || flk) {
+            const R F = (sizeof(R) == 8 ? (R)I.fcoef : (R)I.f_fcoef) * T;
+            const R w[3] = {F * r[0], F * r[1], F * r[2]};       // grad_i W_ij
             R t[3];
             if (fli) {
                 tension_dot<R, DIM>(ci, gi, gi2, w, t);
@@ -1539,10 +1578,11 @@ template <class R, int DIM> struct ForceLane {
     __device__ __forceinline__ void finish(const Dev& d, const IC& I, uint32_t i, uint32_t sub, R rho_stored,
                                            double& umag2, double& amag2)
     {
-        cont = group_sum<P>(cont);
+        const R fc = sizeof(R) == 8 ? (R)I.fcoef : (R)I.f_fcoef;
+        cont = fc * group_sum<P>(cont);
         for (int q = 0; q < 3; ++q) {
-            ap[q] = group_sum<P>(ap[q]);
-            av[q] = group_sum<P>(av[q]);
+            ap[q] = fc * group_sum<P>(ap[q]);
+            av[q] = fc * group_sum<P>(av[q]);
             as[q] = group_sum<P>(as[q]);
         }
         const double rho_i = rho_of<R>(I, ph, rho_stored);
@@ -1706,9 +1746,10 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
             if constexpr (sizeof(R) == 8) { m0 = I.mass[0]; m1 = I.mass[1]; }
             else { m0 = I.f_mass[0]; m1 = I.f_mass[1]; }
             struct VM { R4<R> v; R m; };
-            // one loop per case, so that the walk carries no per-neighbour branch on it
-            auto walk = [&](auto uniform) {
-                constexpr bool UM = decltype(uniform)::value;
+            // one loop per case (masses uniform per phase or not; Eq. (6) or Eq. (5)), so
+            // that the walk carries no per-neighbour branch on them
+            auto walk = [&](auto uniform, auto massform) {
+                constexpr bool UM = decltype(uniform)::value, MF = decltype(massform)::value;
                 for_each_neighbor<R, DIM, ForceBatch<R, P>::U, P>(d, I, O, pos, i, L, sub,
                     [&](uint32_t k) {
                         VM x;
@@ -1718,11 +1759,20 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
                         return x;
                     },
                     [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t phj, const VM& x) {
-                        F.pair(I, gc, k, r, r2, pj, phj, x.v, UM ? (phj ? m1 : m0) : x.m);
+                        if constexpr (UM)
+                            F.template pair<MF>(I, gc, k, r, r2, pj, phj, x.v, MF ? (phj ? m1 : m0) : (R)0,
+                                                phj ? F.mA1 : F.mA0);
+                        else
+                            F.template pair<MF>(I, gc, k, r, r2, pj, phj, x.v, x.m, x.m * F.Ai);
                     });
             };
-            if (I.umass) walk(std::true_type{});
-            else walk(std::false_type{});
+            if (I.umass) {
+                if (I.cont_form == 1) walk(std::true_type{}, std::true_type{});
+                else walk(std::true_type{}, std::false_type{});
+            } else {
+                if (I.cont_form == 1) walk(std::false_type{}, std::true_type{});
+                else walk(std::false_type{}, std::false_type{});
+            }
             nint = F.cnt;
             F.template finish<P, REDUCE, TERMS>(d, I, i, sub, aux[i].w, umag2, amag2);
         });

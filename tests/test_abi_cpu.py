@@ -56,7 +56,7 @@ def test_create_rejects_bad_arguments(case):
         elif case == "count":
             cnt[0] = 0
         elif case == "count_max":
-            cnt[0] = 1 << 26          # list entries hold 26-bit particle indices
+            cnt[0] = 1 << 25          # list entries hold 25-bit particle indices
         elif case == "periodic_small":
             p[0].periodic[0] = 1
             p[0].hi[0] = p[0].lo[0] + 4 * p[0].h

@@ -343,7 +343,7 @@ def test_set_state_rejects_out_of_range_indices():
     key_at = 48 + 48 * n
     nbl_at = key_at + 12 * n + 4 * (ncell + 1) + 64 * s.ninst + 32 * n
     assert np.frombuffer(good, np.uint32, 1, key_at)[0] < ncell
-    assert (np.frombuffer(good, np.uint32, 1, nbl_at)[0] & ((1 << 26) - 1)) < n
+    assert (np.frombuffer(good, np.uint32, 1, nbl_at)[0] & ((1 << 25) - 1)) < n
     for at, bad in ((nbl_at, n), (key_at, ncell)):
         blob = bytearray(good)
         blob[at:at + 4] = np.uint32(bad).tobytes()
