@@ -36,6 +36,20 @@ SLOTS_RENORM = 20
 FLOPS_FLUID = {3: 47, 2: 36}
 FLOPS_BOUNDARY = {3: 28, 2: 21}
 WINDOWS = 5
+# Scenes bench.py can time; "drop3d" is the benchmark's workload, the others are context
+# (the paper's own cases and the batched and flume workloads).
+WORKLOADS = {
+    "drop3d": ("3D oil drop rising in still water, FP32 cell-relative", lambda i: i.drop3d()),
+    "paper_sphere": ("the paper's sphere drop (Sec. III), 0.2 m tank, dx = 5 mm", lambda i: i.paper_drop("sphere")),
+    "paper_cube": ("the paper's cube drop (Sec. III), 0.2 m tank, dx = 5 mm", lambda i: i.paper_drop("cube")),
+    "lab_flume_5mm": ("the paper's lab flume (Sec. IV) in 3D, dx = 5 mm, periodic width 5 cm",
+                      lambda i: i.lab_flume(3, dx=5e-3, width=0.05)),
+    "lab_flume_1mm": ("the paper's lab flume (Sec. IV) in 3D, dx = 1 mm, periodic width 1.5 cm",
+                      lambda i: i.lab_flume(3, dx=1e-3, width=0.015)),
+    "flume2d": ("2D breaking-wave flume with oil slick, 8 m, dx = 5 mm", lambda i: i.flume2d()),
+    "flume3d": ("3D breaking-wave flume section, periodic width, dx = 4 mm", lambda i: i.flume3d()),
+    "tanks256": ("256 independent 2D drop tanks in one context", lambda i: i.batched_drops()),
+}
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SRC = os.path.join(ROOT, "paper_1702_07760_amd", "csrc", "sphx_kernels.hip")
 
@@ -49,11 +63,11 @@ def kernel_source_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def read_traffic(kernel):
+def read_traffic(kernel, workload="drop3d"):
     """HBM bytes per launch of a kernel from its committed rocprofv3 counter summary
-    (``profiles/<kernel>_fp32_drop3d_traffic.txt``), or None when the kernel source
-    changed since the counters were taken."""
-    path = os.path.join(PROFILES, f"{kernel}_fp32_drop3d_traffic.txt")
+    (``profiles/<kernel>_fp32_<workload>_traffic.txt``), or None when there is none or
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(PROFILES, f"{kernel}_fp32_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -103,6 +117,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU leg")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--workload", default="drop3d", choices=sorted(WORKLOADS),
+                    help="scene to time (default: the 3D drop, the benchmark's workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the library has no "
@@ -112,22 +128,28 @@ def main():
     import torch
     from paper_1702_07760_amd import binding, inputs
 
-    scene = inputs.drop3d()
+    wl_name, make = WORKLOADS[args.workload]
+    scene = make(inputs)
     n = scene.n
     dim = scene.dim
-    log(f"workload drop3d: n={n} fluid={(scene.kind == 0).sum()} oil={(scene.phase == 1).sum()}")
+    log(f"workload {args.workload}: n={n} fluid={(scene.kind == 0).sum()} oil={(scene.phase == 1).sum()}")
 
     # -- FP32 cell-relative: the headline number
     sim = binding.Sim(scene, precision=binding.FP32_CELLREL)
     launch = sim.launch_options()
-    off, ids = sim.get_neighbors()
-    nb = np.diff(off)
     fluid = scene.kind == 0
-    i_fluid, i_bnd = int(nb[fluid].sum()), int(nb[~fluid].sum())
-    flops_per_inter = (FLOPS_FLUID[dim] * i_fluid + FLOPS_BOUNDARY[dim] * i_bnd) / (i_fluid + i_bnd)
-    # Eq. (7) sums over same-phase neighbours only
-    same_phase = float(np.mean(np.repeat(scene.phase, nb) == scene.phase[ids]))
-    del ids
+    if n <= 4_000_000:
+        off, ids = sim.get_neighbors()
+        nb = np.diff(off)
+        i_fluid, i_bnd = int(nb[fluid].sum()), int(nb[~fluid].sum())
+        flops_per_inter = (FLOPS_FLUID[dim] * i_fluid + FLOPS_BOUNDARY[dim] * i_bnd) / (i_fluid + i_bnd)
+        # Eq. (7) sums over same-phase neighbours only
+        same_phase = float(np.mean(np.repeat(scene.phase, nb) == scene.phase[ids]))
+        del ids
+    else:
+        # no host copy of the lists at this size: every pair counted as a fluid and
+        # same-phase one
+        flops_per_inter, same_phase = float(FLOPS_FLUID[dim]), 1.0
     secs, st, windows = timed_steps(sim, args.steps, args.warmup, torch)
     value = st["interactions"] / secs
     ms_per_step = 1e3 * secs / args.steps
@@ -153,7 +175,8 @@ def main():
     def alu_roofline(kernel, slots, units, ms):
         achieved = 2.0 * slots * units / (ms * 1e-3)          # FLOP/s, a slot priced as one FMA
         return {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK, "traffic": read_traffic(kernel),
+                "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK,
+                "traffic": read_traffic(kernel, args.workload),
                 "kernel": kernel, "avg_launch_ms": ms, "valu_slots_per_interaction": slots,
                 "interactions_per_launch": units, "interactions_per_s": units / (ms * 1e-3)}
 
@@ -210,7 +233,7 @@ def main():
             elapsed += time.perf_counter() - t0
             steps_cpu += 1
         cpu = {"value": total / elapsed, "unit": "interactions/s", "cores": threads, "kind": "oracle",
-               "sample": f"{steps_cpu} full steps of the same 3D drop ({n} particles), FP64 oracle, "
+               "sample": f"{steps_cpu} full steps of the same {args.workload} scene ({n} particles), FP64 oracle, "
                          f"OpenMP over particles, {elapsed:.1f} s",
                "particle_steps_per_s": n * steps_cpu / elapsed}
         # the same oracle on one host core, over a shorter sample
@@ -231,7 +254,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "3D oil drop rising in still water, FP32 cell-relative",
+        "config": {"workload": wl_name,
                    "particles": n, "fluid": int(fluid.sum()), "dx_m": scene.dx[0],
                    "h_over_dx": 1.3, "kernel": "Wendland C2", "steps_per_launch": 1,
                    "interactions_per_step": st["interactions"] / args.steps},

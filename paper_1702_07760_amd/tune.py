@@ -99,3 +99,38 @@ def tune(scene, precision, steps=20, warmup=3, repeats=3, blocks=BLOCKS, remaps=
         with open(CACHE, "w") as fh:
             json.dump(cache, fh, indent=1, sort_keys=True)
     return best
+
+
+SCENES = {
+    "drop3d": lambda i: i.drop3d(),
+    "paper_sphere": lambda i: i.paper_drop("sphere"),
+    "lab_flume_5mm": lambda i: i.lab_flume(3, dx=5e-3, width=0.05),
+    "flume2d": lambda i: i.flume2d(),
+    "flume3d": lambda i: i.flume3d(),
+    "tanks256": lambda i: i.batched_drops(),
+    "drop2d": lambda i: i.drop2d(),
+}
+
+
+def main(argv=None):
+    """Tune named scenes and merge the results into the cache (or another JSON file):
+    python -m paper_1702_07760_amd.tune drop3d:1 drop3d:0 flume3d:1 [--out FILE]
+    (scene:precision, 0 = FP64, 1 = FP32 cell-relative)."""
+    import argparse
+    from . import inputs
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cases", nargs="+")
+    ap.add_argument("--out", default=None, help="JSON file to merge into (default: the cache)")
+    ap.add_argument("--steps", type=int, default=20)
+    args = ap.parse_args(argv)
+    if args.out:
+        globals()["CACHE"] = args.out
+    for case in args.cases:
+        name, prec = case.split(":")
+        scene = SCENES[name](inputs)
+        best = tune(scene, int(prec), steps=args.steps)
+        print(f"best {name} p{prec} n={scene.n}: {best}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -2,9 +2,12 @@
 launch configuration the benchmark times (default options, graph-replayed steps).
 
 The 3D drop (335,728 particles) and the 2D flume (165,538) are compared whole after one
-step, the paper's sphere and cube drop tests (95,116) after three; the 3D periodic flume (3,222,950) in the FP32 form the benchmark reports; the
-256-tank batch (5,961,716 particles) runs whole on the GPU and a sample of 8 tanks is
-stepped by the oracle, one tank at a time (tanks are independent).
+step, the paper's sphere and cube drop tests (95,116) and its laboratory flume in 3D at
+5 mm with a narrowed periodic width (581,480) after three; the 3D periodic flume
+(3,222,950) in the FP32 form the benchmark reports; the 256-tank batch (5,961,716
+particles) runs whole on the GPU and a sample of 8 tanks is stepped by the oracle, one
+tank at a time (tanks are independent).  The paper's drops also run to the times of its
+shape snapshots.
 """
 import numpy as np
 import pytest
@@ -95,6 +98,53 @@ def test_paper_drops_rise_at_the_added_mass_acceleration(shape):
     print(f"  mean acceleration {a:.3f} m/s^2 between t = {t[1]:.3f} and {t[4]:.3f} s", flush=True)
     assert a_est / 1.5 < a < a_est * 1.5
     assert np.allclose(track[binding.FP32_CELLREL][:, 1], z, rtol=0, atol=1e-5 * 0.005)
+
+
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32_CELLREL])
+def test_paper_lab_flume_3d_5mm_matches_oracle(prec):
+    # Sec. IV: the 6 m flume, water 0.25 m deep, the Eq. (18) piston at x = 0.55 m, the oil
+    # slick at x = 1.5 m, at the paper's 5 mm particle size with a periodic width of 5 cm
+    # (545,000 fluid particles; the paper's 5 mm runs hold about half a million); three
+    # steps with the piston moving
+    s = inputs.lab_flume(3, dx=5e-3, width=0.05)
+    assert s.n == 581480 and int((s.kind == inputs.MOVING).sum()) > 0
+    print(f"case paper lab flume 3D 5 mm n={s.n} precision={prec}", flush=True)
+    o = oracle.Oracle(s)
+    o.set_neighbor_method(2)
+    o.step(3)
+    sim = binding.Sim(s, precision=prec)
+    sim.step(3)
+    sim.sync()
+    assert abs(sim.stats()["t"] - o.t) <= 1e-6 * o.t
+    mov = s.kind == inputs.MOVING
+    assert np.all(o.get(oracle.X)[mov, 0] > s.x[mov, 0])    # the piston has moved forward
+    _compare(s, sim, o, prec)
+
+
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32_CELLREL])
+def test_paper_drops_reach_the_snapshot_times(prec):
+    # Sec. III shows the drops at t = 0.42, 0.74, 1.04 and 1.22 s.  Both drops run to
+    # 1.22 s without a fault, and the oil rises between every two snapshots.  The records
+    # (oil centroid, extent) are printed; the paper gives shapes only, no numbers.
+    for shape in ("sphere", "cube"):
+        s = inputs.paper_drop(shape)
+        oil = s.phase == inputs.OIL
+        print(f"case paper drop history {shape} n={s.n} precision={prec}", flush=True)
+        sim = binding.Sim(s, precision=prec)
+        rows = []
+        for t_snap in (0.42, 0.74, 1.04, 1.22):
+            while sim.stats()["t"] < t_snap:
+                sim.step(50)
+            sim.sync()
+            x = sim.get_field(binding.F_X)[oil]
+            rows.append((sim.stats()["t"], x.mean(0), x.min(0), x.max(0)))
+            t, c, lo, hi = rows[-1]
+            print(f"  t={t:.3f} s centroid {np.round(c * 1e3, 1)} mm, extent {np.round((hi - lo) * 1e3, 1)} mm, "
+                  f"top {hi[2] * 1e3:.1f} mm", flush=True)
+        sim.close()
+        z = [r[1][2] for r in rows]
+        assert np.all(np.diff(z) > 0)
+        assert z[-1] - z[0] > 0.02
 
 
 def test_full_size_periodic_flume3d_fp32():
