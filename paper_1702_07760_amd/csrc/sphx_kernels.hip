@@ -1480,14 +1480,18 @@ template <class R, int P> struct ForceBatch {
 // Per-lane state of the force pass for particle i: its own quantities, the sums of
 // Eqs. (6), (8), (10)/(11), (17) over its neighbours, and the epilogue that turns them
 // into the rates.
-template <class R, int DIM> struct ForceLane {
+// SPLIT keeps the three acceleration terms apart (for the debug output of each); without
+// it they go into one sum, acc, each term pre-scaled so that fc * acc is the acceleration
+// (three registers per lane instead of nine).
+template <class R, int DIM, bool SPLIT = true> struct ForceLane {
     uint32_t info, ph;
     bool fluid, fli, massform;
     R4<R> vi;
     R mi, Ai, alpha, ci, gi2, vp0, vp1, delta2;
     R mA0, mA1;   // m_j A_i for a neighbour of phase 0 / 1 (masses uniform per phase)
+    R sfac;       // !SPLIT: 1 / (m_i fc), the scale of the surface-tension terms in acc
     R gi[3];
-    R cont, ap[3], av[3], as[3];
+    R cont, ap[3], av[3], as[3], acc[3];
     uint32_t cnt;
 
     template <class IC>
@@ -1525,8 +1529,19 @@ template <class R, int DIM> struct ForceLane {
         massform = I.cont_form == 1;
         if constexpr (sizeof(R) == 8) { mA0 = I.mass[0] * Ai; mA1 = I.mass[1] * Ai; }
         else { mA0 = I.f_mass[0] * Ai; mA1 = I.f_mass[1] * Ai; }
+        if constexpr (!SPLIT) {
+            // Eq. (11) carries 1 / rho_i (the vfac of finish); the tension terms carry
+            // 1 / m_i and, against the fc applied to acc, 1 / fc
+            const R fc = sizeof(R) == 8 ? (R)I.fcoef : (R)I.f_fcoef;
+            if (I.visc_form == 1) {
+                const R vfac = (R)(1.0 / rho_of<R>(I, ph, xi.w));
+                vp0 *= vfac;
+                vp1 *= vfac;
+            }
+            sfac = (R)1 / (mi * fc);
+        }
         cont = 0;
-        for (int q = 0; q < 3; ++q) ap[q] = av[q] = as[q] = 0;
+        for (int q = 0; q < 3; ++q) ap[q] = av[q] = as[q] = acc[q] = 0;
         cnt = 0;
     }
 
@@ -1549,10 +1564,14 @@ template <class R, int DIM> struct ForceLane {
         cont += (MF ? mj : Vj) * (T * ur);                         // Eq. (6) / (5)
         if (!fluid) return;
         const R pcT = (mjAi + pj.w) * T;                          // m_j (A_i + A_j) T
-        ap[0] -= pcT * r[0]; ap[1] -= pcT * r[1]; ap[2] -= pcT * r[2];
         const R lap = (T * r2) * frcp(r2 + delta2);               // r.gradW / (r^2 + delta^2), unscaled
         const R cv = Vj * (phj ? vp1 : vp0) * lap;
-        av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
+        if constexpr (SPLIT) {
+            ap[0] -= pcT * r[0]; ap[1] -= pcT * r[1]; ap[2] -= pcT * r[2];
+            av[0] += cv * u[0]; av[1] += cv * u[1]; av[2] += cv * u[2];
+        } else {
+            for (int q = 0; q < 3; ++q) acc[q] += cv * u[q] - pcT * r[q];
+        }
         const bool flk = vk.w < (R)0;
         if (fli || flk) {
             const R F = (sizeof(R) == 8 ? (R)I.fcoef : (R)I.f_fcoef) * T;
@@ -1560,14 +1579,16 @@ template <class R, int DIM> struct ForceLane {
             R t[3];
             if (fli) {
                 tension_dot<R, DIM>(ci, gi, gi2, w, t);
-                as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+                if constexpr (SPLIT) { as[0] += t[0]; as[1] += t[1]; as[2] += t[2]; }
+                else { acc[0] += sfac * t[0]; acc[1] += sfac * t[1]; acc[2] += sfac * t[2]; }
             }
             if (flk) {
                 const R4<R> g4 = gc[k];
                 const R gk[3] = {g4.x, g4.y, g4.z};
                 const R ck = fdiv(alpha * (vk.w * vk.w), g4.w);
                 tension_dot<R, DIM>(ck, gk, g4.w * g4.w, w, t);
-                as[0] += t[0]; as[1] += t[1]; as[2] += t[2];
+                if constexpr (SPLIT) { as[0] += t[0]; as[1] += t[1]; as[2] += t[2]; }
+                else { acc[0] += sfac * t[0]; acc[1] += sfac * t[1]; acc[2] += sfac * t[2]; }
             }
         }
     }
@@ -1581,9 +1602,13 @@ template <class R, int DIM> struct ForceLane {
         const R fc = sizeof(R) == 8 ? (R)I.fcoef : (R)I.f_fcoef;
         cont = fc * group_sum<P>(cont);
         for (int q = 0; q < 3; ++q) {
-            ap[q] = fc * group_sum<P>(ap[q]);
-            av[q] = fc * group_sum<P>(av[q]);
-            as[q] = group_sum<P>(as[q]);
+            if constexpr (SPLIT) {
+                ap[q] = fc * group_sum<P>(ap[q]);
+                av[q] = fc * group_sum<P>(av[q]);
+                as[q] = group_sum<P>(as[q]);
+            } else {
+                acc[q] = fc * group_sum<P>(acc[q]);
+            }
         }
         const double rho_i = rho_of<R>(I, ph, rho_stored);
         R4<R> out;
@@ -1592,10 +1617,14 @@ template <class R, int DIM> struct ForceLane {
         if (fluid) {
             const R vfac = I.visc_form == 1 ? (R)(1.0 / rho_i) : (R)1;
             for (int q = 0; q < 3; ++q) {
-                av[q] *= vfac;
-                as[q] /= mi;
                 const R gq = sizeof(R) == 8 ? (R)I.g[q] : (R)I.f_g[q];
-                a[q] = ap[q] + av[q] + as[q] + gq;
+                if constexpr (SPLIT) {
+                    av[q] *= vfac;
+                    as[q] /= mi;
+                    a[q] = ap[q] + av[q] + as[q] + gq;
+                } else {
+                    a[q] = acc[q] + gq;
+                }
             }
         }
         out.x = a[0]; out.y = a[1]; out.z = a[2];
@@ -1737,7 +1766,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
             const R4<R> pi = pos[i];
             Lane<R> L;
             L.load(I, pi, O.key[i]);
-            ForceLane<R, DIM> F;
+            ForceLane<R, DIM, TERMS> F;
             F.init(I, info, vel[i], aux[i], gc, i);
             // per neighbour: the position record (x_j, m_j A_j) and the velocity record
             // (u_j, +-V_j); m_j from the per-phase table when the instance's masses are
