@@ -47,7 +47,9 @@ typedef enum {
     SPHX_E_DOMAIN = 7,     /* device: a particle left a non-periodic domain */
     SPHX_E_DT = 8,         /* device: dt * max|u| exceeded half the neighbour skin */
     SPHX_E_STALL = 9       /* device: a grid barrier of the one-launch neighbour build timed
-                              out; the state is lost (see SPHX_OPT_ONE_LAUNCH_BUILD) */
+                              out; the work queued from that build on was not done and the
+                              state is kept as the build found it (see
+                              SPHX_OPT_ONE_LAUNCH_BUILD) */
 } sphx_status;
 
 typedef enum { SPHX_FP64 = 0, SPHX_FP32_CELLREL = 1 } sphx_precision;
@@ -120,11 +122,13 @@ enum {
                                  meet at grid barriers; without a rebuild it ends after the
                                  decision.  0: seven launches.  A barrier that waits too long (its
                                  blocks were not all resident, e.g. other work shared the device)
-                                 stops that build part-way and every later one until the next
-                                 sphx_sync (or read-back call), which returns SPHX_E_STALL: the
-                                 state is then lost, the calls that step or read it return
-                                 SPHX_E_STATE until sphx_set_state or sphx_init_particles, and the
-                                 context builds with seven launches from then on */
+                                 stops that build part-way, and every pass queued after it returns
+                                 without work until the next sphx_sync (or read-back call).  That
+                                 call rebuilds the neighbour structure from the state the build
+                                 found, which no pass changed (the steps from that build on are
+                                 not taken: sphx_stats tells how many were), and returns
+                                 SPHX_E_STALL; the context builds with seven launches from then
+                                 on */
     SPHX_OPT_FORCE_STALL = 9  /* for tests of that recovery: 1..5 makes grid barrier 1..5 of the next
                                  one-launch build time out at once (0: none, the default) */
 };
@@ -196,7 +200,7 @@ sphx_status sphx_bind_static_workspace(sphx_ctx* ctx);
  * value (finite, inside the box, positive density and mass, phase < nphase, boundary
  * particles in phase 0), then builds the neighbour structure and waits for it.  May be
  * called again to start over with the same layout.  Returns SPHX_E_STALL if that first
- * build stalled (call it again: the build then takes seven launches). */
+ * build stalled (the particles are then in place, built with seven launches). */
 sphx_status sphx_init_particles(sphx_ctx* ctx, const double* x, const double* u, const double* rho,
                                 const double* m, const uint8_t* phase, const uint8_t* kind);
 
@@ -256,7 +260,8 @@ sphx_status sphx_get_neighbors(sphx_ctx* ctx, int64_t* off, int32_t* ids, int64_
 /* Opaque snapshot of the full state (including compensation terms, time, step count
  * and the time step); a restored context continues bit-identically.  sphx_set_state
  * takes a blob from a context of the same layout, checks that every index in it is in
- * range (SPHX_E_ARG and no change otherwise) and clears a state lost to SPHX_E_STALL. */
+ * range (SPHX_E_ARG and no change otherwise); errors still pending from the replaced
+ * state are dropped. */
 sphx_status sphx_get_state(sphx_ctx* ctx, void* host_blob, size_t cap, size_t* need);
 sphx_status sphx_set_state(sphx_ctx* ctx, const void* host_blob, size_t bytes);
 

@@ -41,7 +41,6 @@ struct sphx_ctx {
     Dev dev{};
     Launch launch{};
     bool bound = false, inited = false, rates_valid = false;
-    bool lost = false;   // a one-launch build stopped part-way: set_state or init_particles next
     bool has_moving = false;
     bool use_graph = true;
     hipGraphExec_t graph = nullptr;    // one step; the state parity lives on the device
@@ -309,6 +308,8 @@ bool setup_cells(const sphx_params* per, int ninst, std::vector<uint32_t>& base,
 // ---------------------------------------------------------------- stepping
 
 void drop_graphs(sphx_ctx* c);
+sphx_status request_rebuild(sphx_ctx* c);
+void enqueue_build(sphx_ctx* c);
 
 sphx_status status_of(sphx_ctx* c)
 {
@@ -320,20 +321,24 @@ sphx_status status_of(sphx_ctx* c)
         HIP_OK(c, hipMemcpy(c->dev.status, &zero, sizeof zero, hipMemcpyHostToDevice));
     }
     if (st & ST_STALL) {
-        // the build stopped between two phases: the sorted sets, the cell table and the
-        // list no longer agree.  Clear what the next build expects cleared (barrier words
-        // that may hold this launch's epochs, the cell counters) and build with seven
-        // launches from now on.
+        // the build stopped at a grid barrier and every pass after it returned at once.
+        // The current state set is whole (the build writes only the other set before its
+        // last barrier and makes it current after that barrier); the cell table and the
+        // list are not.  Clear what the next build expects cleared (barrier words that
+        // may hold this launch's epochs, the cell counters) and rebuild from the current
+        // set with seven launches, as every later build will be.
         HIP_OK(c, hipMemset(c->dev.bar, 0, (512 + 4096) * sizeof(unsigned)));
         HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * sizeof(uint32_t)));
         c->launch.one_launch_build = false;
         c->launch.stall_at = 0;
-        c->lost = true;
         c->rates_valid = false;
         drop_graphs(c);
+        if (const sphx_status e = request_rebuild(c)) return e;
+        enqueue_build(c);
+        HIP_OK(c, hipStreamSynchronize(c->stream));
         return fail(c, SPHX_E_STALL, "a grid barrier of the one-launch neighbour build timed out (its blocks were "
-                                     "not all resident); the particle state is lost: restore it with set_state "
-                                     "or init_particles (builds use seven launches from now on)");
+                                     "not all resident): the work queued from that build on was not done, the "
+                                     "state is as the build found it, and builds use seven launches from now on");
     }
     if (st & ST_NONFINITE) return fail(c, SPHX_E_NONFINITE, "a rate or state value became non-finite");
     if (st & ST_DOMAIN) {
@@ -387,7 +392,6 @@ sphx_status have_state(sphx_ctx* c)
     if (!c) return SPHX_E_ARG;
     if (const sphx_status st = owns_workspace(c)) return st;
     if (!c->inited) return fail(c, SPHX_E_STATE, "init_particles first");
-    if (c->lost) return fail(c, SPHX_E_STATE, "the state was lost in a stalled build: set_state or init_particles");
     return SPHX_OK;
 }
 
@@ -921,7 +925,6 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     launch_derive(d, c->launch, s);
     enqueue_build(c);
     c->inited = true;
-    c->lost = false;
     c->rates_valid = false;
     HIP_OK(c, hipGetLastError());
     return status_of(c);   // synchronises; reports a first build that stalled
@@ -1423,12 +1426,14 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
     HIP_OK(c, hipMemcpy(c->dev.curp, &cur, sizeof cur, hipMemcpyHostToDevice));
     HIP_OK(c, hipMemcpy(c->dev.flags, flags, sizeof flags, hipMemcpyHostToDevice));
     HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * 4));
+    // errors still pending belong to the state this call replaced
+    HIP_OK(c, hipMemset(c->dev.status, 0, sizeof(uint32_t)));
+    HIP_OK(c, hipMemset(c->dev.fault, 0, sizeof(FaultRec)));
     const Sorted& other = c->dev.O[1 - cur];   // valid (if stale) for a build that stops part-way
     HIP_OK(c, hipMemset(other.key, 0, (size_t)c->n * 4));
     HIP_OK(c, hipMemset(other.id, 0, (size_t)c->n * 4));
     HIP_OK(c, hipMemset(other.info, 0, (size_t)c->n * 4));
     c->rates_valid = h.rates_valid != 0;
-    c->lost = false;
     return SPHX_OK;
 }
 

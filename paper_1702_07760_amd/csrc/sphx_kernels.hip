@@ -553,11 +553,53 @@ __device__ __forceinline__ void lane_split(int remap, uint32_t& i, uint32_t& sub
 
 // ---------------------------------------------------------- neighbour build
 
-// a1: cell hash.  FP64 takes floor((x - lo)/s); FP32 moves an offset that left
-// its cell into the neighbouring cell, folding the rounding of the shift into
-// the compensation term.  Each particle bumps its cell counter (the returned
-// value is its provisional slot) and marks its phase in the cell mask.
-// a1 for one particle: its new cell key (and, in FP32, its offset moved into that cell).
+// a1: cell hash.  FP64 takes floor((x - lo)/s); FP32 finds the cell that an offset
+// which left its cell moved into (the gather then moves the offset, folding the
+// rounding of the shift into the compensation term).  Each particle bumps its cell
+// counter (the returned value is its provisional slot).
+
+// FP32 form: the cell of a particle whose offset o (compensation e) left its cell c.  The
+// offset moves by whole cells, o - sh cs = (o - sh s) - sh (cs - s) with s the FP32 cell
+// size: o - sh s is taken with its rounding error (TwoSum; sh s is exact for |sh| <= 2),
+// and that error and -sh (cs - s) go into the compensation term.  Returns true when the
+// particle left a non-periodic domain (its cell is then clamped); raw receives the cells
+// before clamping.  The hash takes the new cell from it and the gather the moved offset,
+// both from the unchanged old state set, so a build stopped before its end leaves that
+// set as it was.
+template <int DIM>
+__device__ __forceinline__ bool recell(const InstDev& I, uint32_t* status, int c[3], float o[3], float e[3],
+                                       int raw[3])
+{
+    bool out = false;
+    for (int dd = 0; dd < DIM; ++dd) {
+        if (!isfinite(o[dd])) {
+            atomicOr(status, ST_NONFINITE);
+            o[dd] = 0.0f;
+        }
+        const float s = I.f_cs[dd];
+        const float sh = fminf(fmaxf(floorf(o[dd] / s), -1.0e6f), 1.0e6f);
+        raw[dd] = c[dd] + (int)sh;
+        if (sh != 0.0f) {
+            const float b = -sh * s;
+            const float sum = o[dd] + b;
+            const float bv = sum - o[dd];
+            const float err = (o[dd] - (sum - bv)) + (b - bv);
+            o[dd] = sum;
+            e[dd] += err - sh * I.f_cs_lo[dd];
+            int ci = c[dd] + (int)sh;
+            if (I.periodic[dd]) {
+                ci = ((ci % I.nc[dd]) + I.nc[dd]) % I.nc[dd];
+            } else if (ci < 0 || ci >= I.nc[dd]) {
+                out = true;
+                ci = ci < 0 ? 0 : I.nc[dd] - 1;
+            }
+            c[dd] = ci;
+        }
+    }
+    return out;
+}
+
+// a1 for one particle: its new cell key.
 template <class R, int DIM>
 __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
 {
@@ -584,43 +626,14 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
             c[dd] = ci;
         }
     } else {
-        float4* pos = (float4*)d.S[cur].pos;
-        float4 p = pos[k];
-        float4 lo = d.S[cur].plo[k];
+        const float4 p = ((const float4*)d.S[cur].pos)[k];
+        const float4 lo = d.S[cur].plo[k];
         cell_of_key(I, O.key[k], c);
         float o[3] = {p.x, p.y, p.z};
         float e[3] = {lo.x, lo.y, lo.z};
-        for (int dd = 0; dd < DIM; ++dd) {
-            if (!isfinite(o[dd])) {
-                atomicOr(d.status, ST_NONFINITE);
-                o[dd] = 0.0f;
-            }
-            const float s = I.f_cs[dd];
-            const float sh = fminf(fmaxf(floorf(o[dd] / s), -1.0e6f), 1.0e6f);
-            raw[dd] = c[dd] + (int)sh;
+        for (int dd = 0; dd < DIM; ++dd)
             xa[dd] = I.lo[dd] + (double)c[dd] * I.cs[dd] + (double)o[dd] + (double)e[dd];
-            if (sh != 0.0f) {
-                // the offset moves sh cells: o - sh cs = (o - sh s) - sh (cs - s).  o - sh s is
-                // taken with its rounding error (TwoSum; sh s is exact for |sh| <= 2), and that
-                // error and -sh (cs - s) go into the compensation term
-                const float b = -sh * s;
-                const float sum = o[dd] + b;
-                const float bv = sum - o[dd];
-                const float err = (o[dd] - (sum - bv)) + (b - bv);
-                o[dd] = sum;
-                e[dd] += err - sh * I.f_cs_lo[dd];
-                int ci = c[dd] + (int)sh;
-                if (I.periodic[dd]) {
-                    ci = ((ci % I.nc[dd]) + I.nc[dd]) % I.nc[dd];
-                } else if (ci < 0 || ci >= I.nc[dd]) {
-                    out = true;
-                    ci = ci < 0 ? 0 : I.nc[dd] - 1;
-                }
-                c[dd] = ci;
-            }
-        }
-        pos[k] = make_float4(o[0], o[1], o[2], p.w);
-        d.S[cur].plo[k] = make_float4(e[0], e[1], e[2], lo.w);
+        out = recell<DIM>(I, d.status, c, o, e, raw);
     }
     if (out) {
         atomicOr(d.status, ST_DOMAIN);
@@ -637,6 +650,14 @@ __device__ __forceinline__ uint32_t hash_one(const Dev& d, int cur, uint32_t k)
 }
 
 
+// A grid barrier of a one-launch build timed out: every later build and every pass that
+// changes the state or its rates returns at once, so the state stays as that build found
+// it until the host rebuilds.
+__device__ __forceinline__ bool stalled(const Dev& d)
+{
+    return (*d.status & ST_STALL) != 0u;
+}
+
 // Start of a step (or of a rate evaluation): rebuild the sort and the list when the host
 // asked for it or some particle moved more than a quarter of the skin since the last
 // build.  Every block takes the decision from the same inputs (nothing changes them
@@ -650,7 +671,7 @@ __device__ __forceinline__ bool build_decision(const Dev& d)
     for (int b = threadIdx.x; b < d.ninst; b += blockDim.x)
         if (__longlong_as_double((long long)d.run[b].disp2) > d.inst[b].rebuild_d2) atomicOr(&any, 1);
     __syncthreads();
-    const bool rebuild = any != 0 && !(*d.status & ST_STALL);
+    const bool rebuild = any != 0 && !stalled(d);
     if (blockIdx.x == 0 && threadIdx.x == 0) d.flags[0] = rebuild ? 1u : 0u;
     return rebuild;
 }
@@ -733,21 +754,25 @@ __global__ void k_scan_reduce(const uint32_t* __restrict__ gate, const uint32_t*
     scan_reduce_tile(in, n, sums, blockIdx.x);
 }
 
-// After every hash block has taken the decision (one block): the gathered copy becomes
-// the current state set (the rest of the build reads the old one through prevp), and
-// the decision's inputs are reset.
-__device__ __forceinline__ void flip_and_reset(const Dev& d)
+// After every hash block has taken the decision (one block): the decision's inputs are
+// reset, and so is the count of colour-pass particles the list build appends.
+__device__ __forceinline__ void reset_decision(const Dev& d)
+{
+    if (threadIdx.x == 0) {
+        d.flags[1] = 0u;
+        *d.icount = 0u;
+    }
+    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) d.run[b].disp2 = 0ull;
+}
+
+// The gathered copy becomes the current state set (one block); prevp keeps the old one.
+__device__ __forceinline__ void flip_sets(const Dev& d)
 {
     if (threadIdx.x == 0) {
         *d.prevp = *d.curp;
         *d.curp = 1 - *d.curp;
-        d.flags[1] = 0u;
-        *d.icount = 0u;   // the list build appends the colour-pass particles
     }
-    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) {
-        d.run[b].disp2 = 0ull;
-        d.run[b].builds += 1;
-    }
+    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) d.run[b].builds += 1;
 }
 
 // Sum of the tile sums before tile t (the whole block takes part).
@@ -763,7 +788,9 @@ __device__ __forceinline__ uint32_t tile_prefix(const uint32_t* __restrict__ sum
 // Pass 2 (one block): exclusive scan of the tile sums, in place.
 __device__ __forceinline__ void scan_top_block(const Dev& d, uint32_t* __restrict__ sums, uint32_t ntiles)
 {
-    flip_and_reset(d);
+    // the seven-launch build flips here: its later launches read the old set through prevp
+    reset_decision(d);
+    flip_sets(d);
     // one block; each thread owns a run of ceil(ntiles / 256) tile sums
     const uint32_t per = (ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
     const uint32_t a = threadIdx.x * per;
@@ -820,25 +847,26 @@ __global__ void k_scan_down(const uint32_t* __restrict__ gate, uint32_t* __restr
 
 // Provisional scatter into the cell's segment (a slot outside [0, n) can only follow a
 // stalled barrier, whose build is abandoned: it is skipped).
-__device__ __forceinline__ void scatter_one(const Dev& d, uint32_t k)
+__device__ __forceinline__ void scatter_one(const Dev& d, int old, uint32_t k)
 {
     if (k >= d.n) return;
     const uint32_t p = d.cstart[d.newkey[k]] + d.slot[k];
     if (p >= d.n) return;
     d.tsrc[p] = k;
-    d.tid[p] = d.O[*d.prevp].id[k];
+    d.tid[p] = d.O[old].id[k];
 }
 
 __global__ void k_scatter(Dev d)
 {
     if (!d.flags[0]) return;
-    scatter_one(d, blockIdx.x * blockDim.x + threadIdx.x);
+    scatter_one(d, *d.prevp, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // a2 made unique, a3: within a cell, order by original id (rank = number of smaller
-// ids), and copy the particle's state from the old set into its slot of the new one.
-template <class R>
-__device__ __forceinline__ void rank_one(const Dev& d, uint32_t s, int with_ref)
+// ids), and copy the particle's state from the old set (`old`) into its slot of the new
+// one (FP32: with its offset moved into the new cell).
+template <class R, int DIM>
+__device__ __forceinline__ void rank_one(const Dev& d, int old, uint32_t s, int with_ref)
 {
     if (s >= d.n) return;
     const uint32_t src = d.tsrc[s];
@@ -850,7 +878,6 @@ __device__ __forceinline__ void rank_one(const Dev& d, uint32_t s, int with_ref)
     for (uint32_t t = a; t < b; ++t) r += d.tid[t] < me ? 1u : 0u;
     const uint32_t k = a + r;
     if (k >= d.n) return;
-    const int old = *d.prevp;
     const Sorted& A = d.O[old];
     const Sorted& B = d.O[1 - old];
     B.key[k] = key;
@@ -859,20 +886,30 @@ __device__ __forceinline__ void rank_one(const Dev& d, uint32_t s, int with_ref)
     if (with_ref) B.ref[k] = A.ref[src];
     const StateSet& SA = d.S[old];
     const StateSet& SB = d.S[1 - old];
-    ((R4<R>*)SB.pos)[k] = ((const R4<R>*)SA.pos)[src];
     ((R4<R>*)SB.vel)[k] = ((const R4<R>*)SA.vel)[src];
     ((R4<R>*)SB.aux)[k] = ((const R4<R>*)SA.aux)[src];
     if constexpr (sizeof(R) == 4) {
-        SB.plo[k] = SA.plo[src];
+        const InstDev& I = d.inst[info_inst(A.info[src])];
+        const float4 p = ((const float4*)SA.pos)[src];
+        const float4 lo = SA.plo[src];
+        int c[3] = {0, 0, 0}, raw[3];
+        cell_of_key(I, A.key[src], c);
+        float o[3] = {p.x, p.y, p.z};
+        float e[3] = {lo.x, lo.y, lo.z};
+        recell<DIM>(I, d.status, c, o, e, raw);
+        ((float4*)SB.pos)[k] = make_float4(o[0], o[1], o[2], p.w);
+        SB.plo[k] = make_float4(e[0], e[1], e[2], lo.w);
         SB.vlo[k] = SA.vlo[src];
+    } else {
+        ((R4<R>*)SB.pos)[k] = ((const R4<R>*)SA.pos)[src];
     }
 }
 
-template <class R>
+template <class R, int DIM>
 __global__ void k_rank(Dev d, int with_ref)
 {
     if (!d.flags[0]) return;
-    rank_one<R>(d, blockIdx.x * blockDim.x + threadIdx.x, with_ref);
+    rank_one<R, DIM>(d, *d.prevp, blockIdx.x * blockDim.x + threadIdx.x, with_ref);
 }
 
 // Neighbour list at the current positions: every j within the cell size (2 + skin) h
@@ -886,10 +923,9 @@ __global__ void k_rank(Dev d, int with_ref)
 constexpr int kNlistLanes = 4;
 
 template <class R, int DIM>
-__device__ __forceinline__ void nlist_one(const Dev& d, uint32_t i, uint32_t sub)
+__device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uint32_t sub)
 {
     constexpr int P = kNlistLanes;
-    const int cur = *d.curp;
     const Sorted& O = d.O[cur];
     const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
     const R4<R> pi = pos[i];
@@ -951,7 +987,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
     uint32_t i, sub;
     lane_split<kNlistLanes>(remap, i, sub);
     if (i >= d.n) return;
-    nlist_one<R, DIM>(d, i, sub);
+    nlist_one<R, DIM>(d, *d.curp, i, sub);
 }
 
 // Grid-wide barrier of the one-launch build, whose grid is sized so that all its blocks
@@ -961,9 +997,10 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
 // one eighth of the blocks.  Epochs grow across launches (word 0 holds the next base),
 // so no slot needs clearing.  Every wait is bounded: a block that waits too long
 // records ST_STALL and returns false, as do the blocks that wait on it after; later
-// builds are then skipped and the host declares the state lost (the build stopped
-// part-way).  `forced` makes every wait of this barrier time out at once, so that
-// tests can take the stall path without waiting.
+// builds and every pass of the step are then skipped, and the host rebuilds from the
+// current state set, which the stopped build has not touched.  `forced` makes every
+// wait of this barrier time out at once, so that tests can take the stall path without
+// waiting.
 constexpr uint32_t kBarrierSpins = 1u << 20;
 constexpr uint32_t kBarRelease = 32;     // release word r at bar[kBarRelease * (1 + r)], r < 8
 constexpr uint32_t kBarSlots = 512;      // arrival slot of block b at bar[kBarSlots + b]
@@ -1022,7 +1059,10 @@ __global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_
 {
     if (!build_decision(d)) return;
     const uint32_t n = d.n, T = gridDim.x * blockDim.x;
-    const int old = *d.curp;   // the scan's middle pass flips the current set
+    // the phases read the old set and write the other one; the current-set word flips
+    // only after the last barrier, so a build that stops at a barrier leaves the old set
+    // current and whole
+    const int old = *d.curp;
     // this launch's barrier epochs are base + 1 .. base + 5; block 0 advances the base
     // after the last barrier, when every block has read it
     const unsigned base = __hip_atomic_load(&d.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1031,20 +1071,22 @@ __global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) scan_reduce_tile(d.cnt, d.ncell, d.scan_tmp, t);
     if (!grid_sync(d, base + 2, stall_at == 2)) return;
     // each tile sums the tile sums before it (few), so the scan needs no middle pass
-    if (blockIdx.x == 0) flip_and_reset(d);
+    if (blockIdx.x == 0) reset_decision(d);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x)
         scan_down_tile(d.cnt, d.ncell, tile_prefix(d.scan_tmp, t), d.cstart, t);
     if (!grid_sync(d, base + 3, stall_at == 3)) return;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) scatter_one(d, k);
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) scatter_one(d, old, k);
     if (!grid_sync(d, base + 4, stall_at == 4)) return;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) rank_one<R>(d, k, with_ref);
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) rank_one<R, DIM>(d, old, k, with_ref);
     if (!grid_sync(d, base + 5, stall_at == 5)) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        __hip_atomic_store(&d.bar[0], base + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (blockIdx.x == 0) {
+        flip_sets(d);   // read by the launches after this one; the list below takes 1 - old
+        if (threadIdx.x == 0) __hip_atomic_store(&d.bar[0], base + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     const uint32_t lanes = n * (uint32_t)kNlistLanes;
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < lanes; b0 += T) {
         const uint32_t t = b0 + threadIdx.x;
-        if (t < lanes) nlist_one<R, DIM>(d, t / kNlistLanes, t % kNlistLanes);
+        if (t < lanes) nlist_one<R, DIM>(d, 1 - old, t / kNlistLanes, t % kNlistLanes);
     }
 }
 
@@ -1113,6 +1155,7 @@ __device__ __forceinline__ bool renorm_due(const Dev& d)
 template <class R>
 __global__ void k_derive(Dev d, int mode, int force)
 {
+    if (stalled(d)) return;
     const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0 && mode != 0) d.flags[2] = 0u;
@@ -1207,7 +1250,7 @@ template <class R, class IC> __device__ __forceinline__ R kernel_f(const IC& I, 
 template <class R, int DIM, int P>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap, int force)
 {
-    if (!force && !renorm_due(d)) return;
+    if (stalled(d) || (!force && !renorm_due(d))) return;
     uint32_t i, sub;
     lane_split<P>(remap, i, sub);
     if (i >= d.n) return;
@@ -1394,6 +1437,7 @@ template <class R, int DIM>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
 {
     constexpr int P = kColourLanes;
+    if (stalled(d)) return;
     const int cur = *d.curp;
     const uint32_t count = *d.icount;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1412,6 +1456,7 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
 template <class R, int DIM>
 __global__ void __launch_bounds__(256) k_derive_colour(Dev d, int force, uint32_t cblocks)
 {
+    if (stalled(d)) return;
     const int cur = *d.curp;
     const bool fresh = force || renorm_due(d);
     if (blockIdx.x < cblocks) {
@@ -1746,6 +1791,7 @@ __device__ __forceinline__ void disp_reduce(const Dev& d, bool mine, uint32_t b,
 template <class R, int DIM, int P, bool REDUCE, bool TERMS, bool CORRECT>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, int remap)
 {
+    if (stalled(d)) return;
     const int cur = *d.curp;
     uint32_t i, sub;
     lane_split<P>(remap, i, sub);
@@ -1963,6 +2009,7 @@ __device__ __forceinline__ void predict_state(const Dev& d, int cur, uint32_t k,
 template <class R, int DIM>
 __global__ void k_predict(Dev d, double dt_override)
 {
+    if (stalled(d)) return;
     const int cur = *d.curp;
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     store_steps(d, dt_override, k, gridDim.x * blockDim.x);
@@ -2110,7 +2157,7 @@ static void build_impl(const Dev& d, const Launch& L, hipStream_t s)
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, d, d.scan_tmp, ntiles);
     hipLaunchKernelGGL(k_scan_down, dim3(ntiles), dim3(SCAN_THREADS), 0, s, gate, d.cnt, d.ncell, d.scan_tmp, d.cstart);
     hipLaunchKernelGGL(k_scatter, dim3(blocks_for(d.n, B)), dim3(B), 0, s, d);
-    hipLaunchKernelGGL((k_rank<R>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, d.O[0].ref ? 1 : 0);
+    hipLaunchKernelGGL((k_rank<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, d.O[0].ref ? 1 : 0);
     // 256-thread blocks: most steps skip the build, and a skipped launch costs in
     // proportion to its workgroup count
     hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n * kNlistLanes, 256)), dim3(256), 0, s, d,
