@@ -205,9 +205,13 @@ sphx_status sphx_init_particles(sphx_ctx* ctx, const double* x, const double* u,
                                 const double* m, const uint8_t* phase, const uint8_t* kind);
 
 /* Neighbour search at the current positions: cell hash, stable sort by cell (ties by
- * original index), reorder of the state, cell start table, neighbour list.  The other
- * calls rebuild by themselves whenever a particle has moved more than a quarter of the
- * skin since the last build; this call forces a rebuild. */
+ * original index), reorder of the state, cell start table, neighbour list.  The sums of
+ * Sec. II (Eqs. (5)-(17)) run over the neighbours j of particle i, the particles within
+ * the kernel's support 2h; the paper leaves the search to the code it builds on, so the
+ * cells of (2 + skin) h and the list radius with its skin are this library's (skin_coef
+ * in sphx_params).  The other calls rebuild by themselves whenever a particle has moved
+ * more than a quarter of the skin since the last build; this call forces a rebuild.
+ * No arguments besides the context; errors as for sphx_step. */
 sphx_status sphx_build_neighbors(sphx_ctx* ctx);
 
 /* Eq. (7): rho_i = sum m_j W_ij / sum (m_j/rho_j) W_ij over i and its same-phase
@@ -221,7 +225,13 @@ sphx_status sphx_compute_forces(sphx_ctx* ctx);
 
 /* One midpoint predictor-corrector step from the rates of the last compute_forces:
  * time step (dt > 0 fixes it, dt <= 0 takes the adaptive one on the device),
- * predictor, rates at the predicted state, corrector. */
+ * predictor, rates at the predicted state, corrector.  The paper gives the rates
+ * (Eqs. (3)-(17)) and no time integrator; the integrator and the adaptive step (CFL
+ * with the reduced sound speed of Sec. II.A, force, viscous and capillary limits) are
+ * the usual WCSPH ones.  Moving (piston) particles follow Eq. (18) or sphx_set_moving;
+ * boundary particles keep their positions.  SPHX_E_STATE without fresh rates,
+ * SPHX_E_ARG for a non-finite dt; a step longer than the neighbour skin allows is
+ * refused on the device (SPHX_E_DT at the next sync). */
 sphx_status sphx_integrate_step(sphx_ctx* ctx, double dt);
 
 /* nsteps full steps: neighbour rebuild when due, Eq. (7) when due, rates, integrate.
