@@ -157,6 +157,8 @@ typedef struct {
     int64_t builds;           /* neighbour builds (sort + list) so far, instance 0 */
     double phase_ms[5];       /* SPHX_OPT_PROFILE: summed event time per kernel group */
     int64_t phase_launches[5];/* SPHX_OPT_PROFILE: timed launches per kernel group */
+    int64_t colour_particles; /* particles with another phase in their neighbour list at the
+                                 last build: the work list of the colour pass (Eq. (16)) */
 } sphx_stats;
 
 /* Bytes of device workspace for ninst instances holding counts[b] particles. */

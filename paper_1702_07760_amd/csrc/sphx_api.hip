@@ -283,7 +283,7 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.star.aux = c.take<char>((un + 1) * 4 * R);
     d.star.plo = nullptr;
     d.star.vlo = nullptr;
-    d.rho_tmp = c.take<char>(un * R);
+    d.rho_tmp = c.take<char>((un + 1) * R);
     d.acc = c.take<char>(un * 4 * R);
     d.gc = c.take<char>((un + 1) * 4 * R);
     d.terms = c.take<char>(un * 12 * R);
@@ -1115,6 +1115,9 @@ sphx_status sphx_get_stats(sphx_ctx* c, sphx_stats* out)
     out->interactions = (int64_t)inter;
     out->ncells = c->ncell;
     out->builds = r.builds;
+    uint32_t icount = 0;
+    HIP_OK(c, hipMemcpy(&icount, c->dev.icount, sizeof icount, hipMemcpyDeviceToHost));
+    out->colour_particles = icount;
     collect_events(c);
     for (int q = 0; q < SPHX_NPH; ++q) {
         out->phase_ms[q] = c->phase_ms[q];

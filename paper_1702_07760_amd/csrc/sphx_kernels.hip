@@ -511,17 +511,62 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const PS& po
     }
 }
 
+// The list walk of a pass with many lanes per particle (U P entries per round, more
+// than the padding): an entry past the count reads as the sentinel, and the entry loads
+// take plain 64-bit addresses.  Entries of phase skip_phase are passed over before their
+// records are read.  For the short walks of the colour pass, whose time is the latency
+// of one walk: with 64 lanes, one round covers a whole list.
+template <class R, int DIM, int U, int P, class IC, class PS, class Load, class Body>
+__device__ __forceinline__ void for_list_wide(const Dev& d, const IC& I, const PS& pos, uint32_t i,
+                                              const Lane<R>& L, uint32_t cnt, uint32_t sub, Load&& load,
+                                              Body&& body, uint32_t skip_phase)
+{
+    using X = decltype(load(0u));
+    const size_t n = (size_t)d.n;
+    const R cut2 = cut2_of<R>(I);
+    for (uint32_t q0 = sub; q0 < cnt; q0 += (uint32_t)(U * P)) {
+        uint32_t e[U];
+        R4<R> pj[U];
+        X x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t q = q0 + (uint32_t)(u * P);
+            e[u] = q < cnt ? d.nbl[(size_t)q * n + i] : (uint32_t)n;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (entry_phase(e[u]) != skip_phase) {
+                const uint32_t k = e[u] & kIdxMask;
+                pj[u] = pos[k];
+                x[u] = load(k);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (entry_phase(e[u]) != skip_phase) {
+                R r[3];
+                list_pair_r<DIM>(I, L, pj[u], e[u], r);
+                const R r2 = dist2<DIM>(r[0], r[1], r[2]);
+                if (r2 < cut2) body(e[u] & kIdxMask, r, r2, pj[u], entry_phase(e[u]), x[u]);
+            }
+        }
+    }
+}
+
 // Either the list (normal case) or, for a particle whose list overflowed, the stencil.
 // The stencil fallback is rare and walks one candidate at a time: batching it would
 // raise the register count, and so lower the occupancy, of the common list path.
-template <class R, int DIM, int U, int P, bool SKIP = false, class IC, class PS, class Load, class Body>
+// WIDE: the list walk of for_list_wide (SKIP implied).
+template <class R, int DIM, int U, int P, bool SKIP = false, bool WIDE = false, class IC, class PS, class Load,
+          class Body>
 __device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, const Sorted& O,
                                                   const PS& pos, uint32_t i, const Lane<R>& L,
                                                   uint32_t sub, Load&& load, Body&& body, uint32_t skip_phase = 0)
 {
     const uint32_t cnt = d.nbc[i];
     if (cnt <= d.cap) {
-        for_list<R, DIM, U, P, SKIP>(d, I, pos, i, L, cnt, sub, load, body, skip_phase);
+        if constexpr (WIDE) for_list_wide<R, DIM, U, P>(d, I, pos, i, L, cnt, sub, load, body, skip_phase);
+        else for_list<R, DIM, U, P, SKIP>(d, I, pos, i, L, cnt, sub, load, body, skip_phase);
     } else {
         for_neighbors<R, DIM, P, 1>(I, d.cstart, O, pos, i, L, cut2_of<R>(I), sub,
                                  [&](uint32_t k, const R* r, R r2, const R4<R>& pj, uint32_t phj, uint32_t) {
@@ -530,15 +575,18 @@ __device__ __forceinline__ void for_each_neighbor(const Dev& d, const IC& I, con
     }
 }
 
-// Sum over the P consecutive lanes that share one particle (P = 1, 2, 4 or 8; the
-// lanes of a group are all active or all inactive).
+// Sum over the P consecutive lanes that share one particle (P a power of two up to 64;
+// the lanes of a group are all active or all inactive).
 template <int P, class T>
 __device__ __forceinline__ T group_sum(T v)
 {
-    static_assert(P == 1 || P == 2 || P == 4 || P == 8, "lanes per particle");
+    static_assert(P >= 1 && P <= 64 && (P & (P - 1)) == 0, "lanes per particle");
     if (P >= 2) v += __shfl_xor(v, 1, 64);
     if (P >= 4) v += __shfl_xor(v, 2, 64);
     if (P >= 8) v += __shfl_xor(v, 4, 64);
+    if (P >= 16) v += __shfl_xor(v, 8, 64);
+    if (P >= 32) v += __shfl_xor(v, 16, 64);
+    if (P >= 64) v += __shfl_xor(v, 32, 64);
     return v;
 }
 
@@ -1334,12 +1382,15 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_renorm(Dev d, int remap,
 
 // ----------------------------------------------- Eq. (16) colour gradient (pass A)
 
-// Lanes per particle and list entries per batch of the colour pass.  It runs over the
-// compact list of particles with another phase in their neighbour list (about 1 % of
-// the particles in the drop), so its time is the latency of one particle's walk: many
-// lanes per particle shorten that walk.  kColourLanes * kColourBatch divides the list
-// capacity.
-constexpr int kColourLanes = 8, kColourBatch = 2;
+// Lanes per particle of the colour pass.  It runs over the compact list of particles
+// with another phase in their neighbour list.  When that list is short (about 1 % of
+// the particles in a drop), the pass takes the time of one particle's walk, and a whole
+// wave per particle (kColourWide lanes, two entries each) takes a list of up to 128
+// entries in one round.  When the list holds more particles than the grid has waves
+// (many drops, long slicks) the pass is bound by throughput instead: kColourLanes lanes
+// per particle then walk it grid-stride, kColourBatch entries per batch (their product
+// divides the list padding).
+constexpr int kColourLanes = 8, kColourWide = 64, kColourBatch = 2;
 
 template <class R, class IC>
 __device__ __forceinline__ R v_of(const IC& I, uint32_t phase, R m, R stored)
@@ -1390,11 +1441,10 @@ template <class R> struct ColourFromRho {
 // Eq. (16) for colour-list entry g on the P lanes of its group; writes the gradient and
 // the interface flag (the sign of V in the velocity record `vel_out`).  make_src(I)
 // gives the source for i's instance.
-template <class R, int DIM, class MakeSrc>
+template <class R, int DIM, int P, bool WIDE, class MakeSrc>
 __device__ __forceinline__ void colour_one(const Dev& d, int cur, uint32_t g, uint32_t sub, R4<R>* vel_out,
                                            MakeSrc&& make_src)
 {
-    constexpr int P = kColourLanes;
     const Sorted& O = d.O[cur];
     R4<R>* gc = (R4<R>*)d.gc;
     const uint32_t i = d.ilist[g];
@@ -1408,7 +1458,7 @@ __device__ __forceinline__ void colour_one(const Dev& d, int cur, uint32_t g, ui
         L.load(I, src.pos[i], O.key[i]);
         vi = src.vi(I, i, ph);
         // C_j^y = 1 only for the other phase: the list walk skips i's own phase
-        for_each_neighbor<R, DIM, kColourBatch, P, true>(d, I, O, src.pos, i, L, sub,
+        for_each_neighbor<R, DIM, kColourBatch, P, true, WIDE>(d, I, O, src.pos, i, L, sub,
             [&](uint32_t k) { return src.load(k); },
             [&](uint32_t, const R* r, R r2, const R4<R>&, uint32_t phj, const MV<R>& x) {
                 if (phj == ph) return;                           // (the stencil fallback)
@@ -1433,20 +1483,34 @@ __device__ __forceinline__ void colour_one(const Dev& d, int cur, uint32_t g, ui
     }
 }
 
+// The colour list on nthr threads (this one is thread t): a whole wave per particle
+// when the list fits the threads that way, else kColourLanes lanes per particle,
+// grid-stride.
+template <class R, int DIM, class MakeSrc>
+__device__ __forceinline__ void colour_walk(const Dev& d, int cur, uint32_t t, uint32_t nthr, R4<R>* vel_out,
+                                            MakeSrc&& make_src)
+{
+    const uint32_t count = *d.icount;
+    if ((uint64_t)count * kColourWide <= nthr) {
+        const uint32_t g = t / kColourWide;
+        if (g < count) colour_one<R, DIM, kColourWide, true>(d, cur, g, t % kColourWide, vel_out, make_src);
+    } else {
+        constexpr int P = kColourLanes;
+        for (uint32_t g = t / P; g < count; g += nthr / P)
+            colour_one<R, DIM, P, false>(d, cur, g, t % P, vel_out, make_src);
+    }
+}
+
 template <class R, int DIM>
 __global__ void __launch_bounds__(MaxBlock<R>::value) k_colour(Dev d, int star)
 {
-    constexpr int P = kColourLanes;
     if (stalled(d)) return;
     const int cur = *d.curp;
-    const uint32_t count = *d.icount;
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t sub = t % P, stride = gridDim.x * blockDim.x / P;
     const StateSet& S = star ? d.star : d.S[cur];
-    for (uint32_t g = t / P; g < count; g += stride)
-        colour_one<R, DIM>(d, cur, g, sub, (R4<R>*)S.vel, [&](const InstU&, uint32_t) {
-            return ColourFromVel<R>{(const R4<R>*)S.pos, (const R4<R>*)S.vel};
-        });
+    colour_walk<R, DIM>(d, cur, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, (R4<R>*)S.vel,
+                        [&](const InstU&, uint32_t) {
+                            return ColourFromVel<R>{(const R4<R>*)S.pos, (const R4<R>*)S.vel};
+                        });
 }
 
 // The derive pass after Eq. (7) and the colour pass at S^n in one launch: the first
@@ -1460,19 +1524,15 @@ __global__ void __launch_bounds__(256) k_derive_colour(Dev d, int force, uint32_
     const int cur = *d.curp;
     const bool fresh = force || renorm_due(d);
     if (blockIdx.x < cblocks) {
-        constexpr int P = kColourLanes;
-        const uint32_t count = *d.icount;
-        const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-        const uint32_t sub = t % P, stride = cblocks * blockDim.x / P;
         const StateSet& S = d.S[cur];
         const R* aux = (const R*)S.aux;
         // the density derived from: renormalised (rho_tmp) or stored (aux.w)
         const R* dens = fresh ? (const R*)d.rho_tmp : aux + 3;
         const uint32_t dstride = fresh ? 1u : 4u;
-        for (uint32_t g = t / P; g < count; g += stride)
-            colour_one<R, DIM>(d, cur, g, sub, (R4<R>*)S.vel, [&](const InstU& I, uint32_t) {
-                return ColourFromRho<R>{(const R4<R>*)S.pos, aux, dens, dstride, I.umass != 0};
-            });
+        colour_walk<R, DIM>(d, cur, blockIdx.x * blockDim.x + threadIdx.x, cblocks * blockDim.x, (R4<R>*)S.vel,
+                            [&](const InstU& I, uint32_t) {
+                                return ColourFromRho<R>{(const R4<R>*)S.pos, aux, dens, dstride, I.umass != 0};
+                            });
         return;
     }
     const uint32_t k = (blockIdx.x - cblocks) * blockDim.x + threadIdx.x;

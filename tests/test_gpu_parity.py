@@ -128,6 +128,25 @@ def test_rates_match_oracle(name, prec, lanes, oracle_rates):
     assert rel_to(P, ref[oracle.P], np.abs(ref[oracle.P]).max()) < 10 * tol
 
 
+def test_colour_walks_cover_both_forms():
+    # the colour pass (Eq. (16)) walks its work list with a whole wave per particle when
+    # the list fits the launch that way (count * 64 lanes within the colour blocks of the
+    # derive launch: 8 threads per particle, at most 1024 blocks of 256), else with 8
+    # lanes per particle grid-stride; the scenes of the rate tests take both forms
+    forms = {}
+    for name in ("drop2d", "periodic2d", "periodic3d", "drop3d_small"):
+        s = SCENES[name]()
+        sim = binding.Sim(s, precision=binding.FP64)
+        count = sim.stats()["colour_particles"]
+        nthr = min(-(-8 * s.n // 256), 1024) * 256
+        forms[name] = count * 64 <= nthr
+        print(f"  {name}: n={s.n} colour list {count}: {'wave per particle' if forms[name] else '8 lanes'}",
+              flush=True)
+        assert 0 < count < s.n
+        sim.close()
+    assert set(forms.values()) == {True, False}
+
+
 def _one_step(scene, prec, nsteps=1, lanes=1):
     o = oracle.Oracle(scene)
     o.step(nsteps)
