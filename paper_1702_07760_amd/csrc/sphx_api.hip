@@ -257,7 +257,8 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.cstart = c.take<uint32_t>((size_t)ncell + 1);
     d.scan_tmp = c.take<uint32_t>((ncell + 2047) / 2048 + 1);
     d.cap = list_cap(dim);
-    d.nbl = c.take<uint32_t>(un * d.cap);
+    d.lstride = (uint32_t)((un + 31) & ~(size_t)31);
+    d.nbl = c.take<uint32_t>((size_t)d.lstride * d.cap);
     d.nbc = c.take<uint32_t>(un);
     d.ilist = c.take<uint32_t>(un);
     d.icount = c.take<uint32_t>(1);
@@ -567,7 +568,7 @@ std::vector<Span> state_spans(sphx_ctx* c, int s)
         {d.S[s].pos, n * 4 * R}, {d.S[s].vel, n * 4 * R}, {d.S[s].aux, n * 4 * R},
         {d.O[s].key, n * 4}, {d.O[s].id, n * 4}, {d.O[s].info, n * 4}, {d.cstart, ((size_t)c->ncell + 1) * 4},
         {d.run, sizeof(InstRun) * c->ninst}, {d.acc, n * 4 * R}, {d.gc, n * 4 * R},
-        {d.nbl, n * d.cap * 4}, {d.nbc, n * 4}, {d.ilist, n * 4}, {d.icount, 4}, {d.xb, n * 4 * R}};
+        {d.nbl, (size_t)d.lstride * d.cap * 4}, {d.nbc, n * 4}, {d.ilist, n * 4}, {d.icount, 4}, {d.xb, n * 4 * R}};
     if (c->precision) {
         v.push_back({d.S[s].plo, n * 16});
         v.push_back({d.S[s].vlo, n * 16});
@@ -1399,7 +1400,7 @@ sphx_status sphx_set_state(sphx_ctx* c, const void* blob, size_t bytes)
             const uint32_t m = std::min(cnt, cap);
             const uint32_t padded = cnt <= cap ? std::min((cnt + kListPad - 1u) & ~(kListPad - 1u), cap) : cap;
             for (uint32_t e = 0; e < padded; ++e)
-                if ((u32(nbl, (size_t)e * n + i) & kIdxMask) >= (e < m ? n : n + 1))
+                if ((u32(nbl, (size_t)e * c->dev.lstride + i) & kIdxMask) >= (e < m ? n : n + 1))
                     return fail(c, SPHX_E_ARG, "blob: neighbour list of particle %u out of range", i);
         }
         const uint32_t ni = u32(at[13], 0);

@@ -136,12 +136,14 @@ struct Dev {
     uint32_t* slot;      // n
     uint32_t* tsrc;      // n
     uint32_t* tid;       // n
-    // neighbour list of the current sort order, column-major: entry q of i at q * n + i
-    uint32_t* nbl;       // n * cap entries (index | cell-offset code << 26)
+    // neighbour list of the current sort order, column-major: entry q of i at
+    // q * lstride + i, the row stride n rounded up to whole 128-byte lines
+    uint32_t* nbl;       // lstride * cap entries (index | cell-offset code << 25 | phase << 31)
     uint32_t* nbc;       // n counts (> cap: overflowed, the passes walk the stencil)
     uint32_t* ilist;     // colour-pass particles (another phase in the list), in build order
     uint32_t* icount;    // their number
     uint32_t cap;
+    uint32_t lstride;
     void* xb;            // R4: positions at the last build (FP32: cell offsets)
     // state
     StateSet S[2];       // double-buffered current state

@@ -444,11 +444,12 @@ template <class R> struct MaxBlock { static constexpr int value = 256; };
 // Visit the entries of i's neighbour list with |r_ij|^2 < 4h^2 at the positions `pos`
 // (an array of records, or anything that gives particle k's record as pos[k]):
 // body(j, r_ij, |r_ij|^2, record of j, phase of j, load(j)).  Entries are stored column-major
-// (entry q of particle i at q * n + i), so a wave reads them coalesced; U entries are
+// (entry q of particle i at q * lstride + i), so a wave reads them coalesced; U entries are
 // fetched per batch so that their loads are in flight together.  With P lanes per
-// particle, lane `sub` takes the entries q = t P + sub: the row offset t P n is the
-// same for all lanes (it is taken into scalar registers, so a list load needs no
-// per-lane address arithmetic) and the lane part sub n + i is fixed.  A batch may read
+// particle, lane `sub` takes the entries q = t P + sub: the row offset t P lstride is
+// the same for all lanes (it is taken into scalar registers, so a list load needs no
+// per-lane address arithmetic) and the lane part sub lstride + i is fixed.  The row
+// stride is n rounded up to 32 entries, so that every row starts on a 128-byte line.  A batch may read
 // entries past cnt: the list is padded with the sentinel entry (index n, a record far
 // outside the domain) up to a multiple of kListPad, which every batch end stays below,
 // so no entry is checked against the count.
@@ -461,15 +462,15 @@ __device__ __forceinline__ void for_list(const Dev& d, const IC& I, const PS& po
 {
     static_assert(kListPad % (U * P) == 0, "a batch of U entries on P lanes must divide the list padding");
     using X = decltype(load(0u));
-    const uint32_t n = (uint32_t)d.n;
-    const uint32_t lane_off = (sub * n + i) * 4u;   // < 2^30: n < 2^25, sub < 8
+    const uint32_t ls = d.lstride;
+    const uint32_t lane_off = (sub * ls + i) * 4u;   // < 2^30: lstride <= 2^25, sub < 8
     const R cut2 = cut2_of<R>(I);
     // t is the same in every active lane (all lanes run the same batches; lanes only
     // leave the loop early), so the row address is wave-uniform: a list load is a buffer
     // load whose resource (the row's base) is built in scalar registers, with the lane's
     // fixed 32-bit offset
     auto entry = [&](uint32_t t) {
-        const uint32_t* row = d.nbl + (size_t)ufirst(t) * ((size_t)P * n);
+        const uint32_t* row = d.nbl + (size_t)ufirst(t) * ((size_t)P * ls);
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)row, (short)0, 0x7fffffff, 0x00020000);
         return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)lane_off, 0, 0);
     };
@@ -531,7 +532,7 @@ __device__ __forceinline__ void for_list_wide(const Dev& d, const IC& I, const P
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const uint32_t q = q0 + (uint32_t)(u * P);
-            e[u] = q < cnt ? d.nbl[(size_t)q * n + i] : (uint32_t)n;
+            e[u] = q < cnt ? d.nbl[(size_t)q * d.lstride + i] : (uint32_t)n;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -985,7 +986,7 @@ __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uin
         L.load(I, pi, O.key[i]);
         const uint32_t ph = info_phase(O.info[i]);
         uint32_t* nb = d.nbl + i;
-        const size_t n = (size_t)d.n;
+        const size_t n = (size_t)d.n, ls = d.lstride;
         const uint32_t cap = d.cap;
         uint32_t cnt = 0;
         bool other = false;
@@ -994,7 +995,7 @@ __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uin
                 const uint32_t grp = (uint32_t)(__ballot(in) >> gbase) & gmask;
                 if (in) {
                     const uint32_t q = cnt + (uint32_t)__popc(grp & below);
-                    if (q < cap) nb[(size_t)q * n] = k | (code << kIdxBits) | (phj << kPhaseShift);
+                    if (q < cap) nb[(size_t)q * ls] = k | (code << kIdxBits) | (phj << kPhaseShift);
                     other |= phj != ph;
                 }
                 cnt += (uint32_t)__popc(grp);
@@ -1002,7 +1003,7 @@ __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uin
         // pad with the sentinel entry (index n, code 0, phase 0) to a multiple of kListPad
         if (cnt <= cap) {
             const uint32_t end = (cnt + kListPad - 1u) & ~(kListPad - 1u);
-            for (uint32_t q = cnt + sub; q < end; q += P) nb[(size_t)q * n] = (uint32_t)n;
+            for (uint32_t q = cnt + sub; q < end; q += P) nb[(size_t)q * ls] = (uint32_t)n;
         }
         const bool gother = ((uint32_t)(__ballot(other) >> gbase) & gmask) != 0u;
         if (sub == 0) {

@@ -351,7 +351,7 @@ def test_set_state_rejects_out_of_range_indices():
     # a 48-byte header holding n at byte 24 and the cell count at byte 32, then in FP32
     # pos, vel, aux (16 B per particle each), key, id, info (4 B), the cell table
     # (4 B per cell + 1), the run block (64 B per instance), acc and gc (16 B) and the
-    # list, entry e of particle i at 4 (e n + i)
+    # list, entry e of particle i at 4 (e s + i) with s = n rounded up to 32
     s = inputs.drop2d(perturb=True)
     print("case set_state validation", flush=True)
     a = binding.Sim(s, precision=binding.FP32_CELLREL)
