@@ -45,7 +45,9 @@ typedef enum {
     SPHX_E_STATE = 5,      /* call out of order (e.g. step before init_particles) */
     SPHX_E_NONFINITE = 6,  /* device: a rate or state value became NaN/Inf */
     SPHX_E_DOMAIN = 7,     /* device: a particle left a non-periodic domain */
-    SPHX_E_DT = 8,         /* device: dt * max|u| exceeded half the neighbour skin */
+    SPHX_E_DT = 8,         /* device: a step would take a particle more than half the
+                              neighbour skin from its position at the last build (a
+                              fixed or explicit dt too long for the particles' speed) */
     SPHX_E_STALL = 9       /* device: a grid barrier of the one-launch neighbour build timed
                               out; the work queued from that build on was not done and the
                               state is kept as the build found it (see
@@ -76,8 +78,10 @@ typedef struct {
     double gravity[3];
     double lo[3], hi[3];  /* domain box; cells tile it; periodic period = hi - lo */
     int32_t periodic[3];
-    double skin_coef;     /* cells are >= (2 + skin_coef) h; a step with dt max|u| > 0.5 skin_coef h
-                             is refused (SPHX_E_DT); it does not enter the adaptive step */
+    double skin_coef;     /* cells are >= (2 + skin_coef) h, the list radius (2 + skin_coef) h; a
+                             step that would take a particle more than skin_coef h / 2 from
+                             its position at the last build is refused (SPHX_E_DT); it does
+                             not enter the adaptive step */
     double c_cfl, c_force, c_visc, c_st; /* time-step coefficients */
     double dt_fixed;      /* > 0: fixed step instead of the adaptive one */
     int32_t n_piston;     /* MOVING particles follow x = x0 + d(t) e_x with */
@@ -211,8 +215,10 @@ sphx_status sphx_init_particles(sphx_ctx* ctx, const double* x, const double* u,
  * Sec. II (Eqs. (5)-(17)) run over the neighbours j of particle i, the particles within
  * the kernel's support 2h; the paper leaves the search to the code it builds on, so the
  * cells of (2 + skin) h and the list radius with its skin are this library's (skin_coef
- * in sphx_params).  The other calls rebuild by themselves whenever a particle has moved
- * more than a quarter of the skin since the last build; this call forces a rebuild.
+ * in sphx_params).  The other calls rebuild by themselves whenever a particle's
+ * displacement since the last build, plus the half step the next predictor can take
+ * (half the fixed step, or of the CFL step at zero speed, times the largest speed),
+ * could exceed 99 % of half the skin; this call forces a rebuild.
  * No arguments besides the context; errors as for sphx_step. */
 sphx_status sphx_build_neighbors(sphx_ctx* ctx);
 
@@ -245,7 +251,8 @@ sphx_status sphx_step(sphx_ctx* ctx, int32_t nsteps);
  * of Sec. IV driven from outside, in place of the piston series of sphx_params): each
  * sits at its reference position + disp + vel (t - t_call) with velocity vel, t_call
  * being the instance's time at the call (read from the device: the call synchronises the
- * stream).  disp, vel: 3 doubles, m and m/s; components beyond the dimension are
+ * stream).  The call places them there at once, and the next step rebuilds the
+ * neighbour structure.  disp, vel: 3 doubles, m and m/s; components beyond the dimension are
  * ignored.  The steps take the motion at t, t + dt/2 and t + dt like the series.
  * SPHX_E_ARG for a bad instance, non-finite values or motion along a periodic axis;
  * SPHX_E_STATE if the scene has no MOVING particles.  sphx_init_particles returns the

@@ -637,6 +637,17 @@ void so_set_moving(so_ctx* c, const double disp[3], const double vel[3])
         c->mv_vel[d] = d < c->p.dim ? vel[d] : 0.0;
     }
     c->mv_t0 = c->t;
+    /* the MOVING particles take the new motion at once: reference position + disp,
+     * velocity vel */
+    for (int64_t i = 0; i < c->n; ++i) {
+        if (c->kind[i] != SO_MOVING) continue;
+        for (int d = 0; d < 3; ++d) {
+            c->x[3 * i + d] = c->x0[3 * i + d] + c->mv_disp[d];
+            c->u[3 * i + d] = c->mv_vel[d];
+        }
+    }
+    c->nb_valid = 0;
+    c->have_rates = 0;
 }
 
 int64_t so_step(so_ctx* c, int32_t nsteps)

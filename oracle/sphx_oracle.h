@@ -68,7 +68,8 @@ so_ctx* so_create(const so_params* p, const so_phase* phases, int32_t nphase, in
                   const uint8_t* phase, const uint8_t* kind);
 void so_destroy(so_ctx* c);
 /* From now on the MOVING particles sit at their initial position + disp + vel (t - t_now)
- * with velocity vel, in place of the piston (components beyond dim are ignored). */
+ * with velocity vel, in place of the piston (components beyond dim are ignored); they
+ * are placed there at once.  Not from the paper: the library's motion set from outside. */
 void so_set_moving(so_ctx* c, const double disp[3], const double vel[3]);
 void so_set_threads(int32_t nthreads);
 int32_t so_get_threads(void);

@@ -157,12 +157,12 @@ InstDev make_inst(const sphx_params& p, const sphx_phase* ph2, int nphase, uint3
     // neighbour-list radius: the cell size (2 + skin) h, with a margin far above FP32 rounding
     const double rl = (2.0 + p.skin_coef) * h;
     I.cutl2 = rl * rl * (1.0 + 2e-5);
-    // the list (and the cells) stay valid while no particle moved more than skin/4 since
-    // the build: a predictor half step adds at most skin/4 more (a step with
-    // dt max|u| > skin h / 2 is refused), so any pair within 2h at a predicted state was
-    // within (2 + skin) h at the build
-    const double q = 0.25 * p.skin_coef * h;
-    I.rebuild_d2 = q * q;
+    // the list (and the cells) stay valid while no particle is more than skin/2 from its
+    // position at the build, at S^n and at the predicted state S*: a pair within 2h there
+    // was then within (2 + skin) h at the build.  The rebuild rule keeps the displacement
+    // at S^n plus the half step dt/2 max|u| below 99 % of skin/2 (dt_bound bounds dt);
+    // the predictor refuses a step that would break it (SPHX_E_DT)
+    I.rebuild_e = 0.495 * p.skin_coef * h;
     I.wcoef = alpha;
     I.fcoef = -5.0 * alpha / (h * h);
     const double delta = p.delta_coef * h;
@@ -198,6 +198,7 @@ InstDev make_inst(const sphx_params& p, const sphx_phase* ph2, int nphase, uint3
     I.c_cfl = p.c_cfl;
     I.c_force = p.c_force;
     I.cmax = cmax;
+    I.dt_bound = p.dt_fixed > 0 ? p.dt_fixed : (cmax > 0 ? p.c_cfl * h / cmax : 0.0);
     double lim = std::numeric_limits<double>::infinity();
     if (numax > 0) lim = std::min(lim, p.c_visc * h * h / numax);
     if (p.alpha_s > 0 && nphase == 2) lim = std::min(lim, p.c_st * std::sqrt(rho0min * h * h * h / (2.0 * M_PI * p.alpha_s)));
@@ -353,7 +354,8 @@ sphx_status status_of(sphx_ctx* c)
                     "cell (%d, %d, %d) of a %d x %d x %d grid",
                     f.id, f.inst, f.x[0], f.x[1], f.x[2], f.cell[0], f.cell[1], f.cell[2], I.nc[0], I.nc[1], I.nc[2]);
     }
-    if (st & ST_DT) return fail(c, SPHX_E_DT, "dt * max|u| exceeded half the neighbour skin");
+    if (st & ST_DT) return fail(c, SPHX_E_DT, "a step would take a particle more than half the neighbour skin "
+                                               "from its position at the last neighbour build");
     return SPHX_OK;
 }
 
@@ -524,7 +526,7 @@ struct BlobHeader {
     int64_t n;
     uint32_t ncell, rates_valid, cap, qpos;   // qpos: device flag 2 (pos.w holds q)
 };
-constexpr uint64_t kMagic = 0x5350485853543034ull;   // "SPHXST04"
+constexpr uint64_t kMagic = 0x5350485853543035ull;   // "SPHXST05"
 
 struct Span { void* p; size_t bytes; };
 
@@ -874,6 +876,14 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemcpyAsync((void*)d.inst, c->inst.data(), sizeof(InstDev) * c->ninst, hipMemcpyHostToDevice, s));
     std::vector<InstRun> run(c->ninst);
     std::memset(run.data(), 0, sizeof(InstRun) * c->ninst);
+    // the largest speed of the particles that move, for the first rebuild decisions
+    for (int b = 0; b < c->ninst; ++b) {
+        double v2 = 0.0;
+        for (int64_t i = c->offsets[b]; i < c->offsets[b + 1]; ++i)
+            if (kind[i] != SPHX_WALL)
+                v2 = std::max(v2, u[3 * i] * u[3 * i] + u[3 * i + 1] * u[3 * i + 1] + u[3 * i + 2] * u[3 * i + 2]);
+        std::memcpy(&run[b].vmax2, &v2, sizeof v2);
+    }
     HIP_OK(c, hipMemcpyAsync(d.run, run.data(), sizeof(InstRun) * c->ninst, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemsetAsync(d.status, 0, sizeof(uint32_t), s));
     HIP_OK(c, hipMemsetAsync(d.fault, 0, sizeof(FaultRec), s));
@@ -1031,6 +1041,12 @@ sphx_status sphx_set_moving(sphx_ctx* c, int32_t inst, const double* disp, const
     }
     I.mv_t0 = r.t;
     HIP_OK(c, hipMemcpy((void*)(c->dev.inst + inst), &I, sizeof I, hipMemcpyHostToDevice));
+    // the particles take the new motion at once, and the next build sorts them where
+    // they now are
+    launch_place_moving(c->dev, (uint32_t)inst, c->stream);
+    if (const sphx_status e = request_rebuild(c)) return e;
+    c->rates_valid = false;
+    HIP_OK(c, hipGetLastError());
     return SPHX_OK;
 }
 

@@ -53,7 +53,11 @@ struct InstDev {
     uint32_t cell_base, ncell;
     int32_t dim, visc_form, cont_form, renorm_every;
     double h, inv_h, cut2, cutl2, wcoef, fcoef, delta2, alpha_s, skin;
-    double rebuild_d2;    // rebuild once some particle moved more than skin/4 since the build
+    // rebuild once some particle's displacement since the build plus the longest half
+    // step any particle can take next (dt_bound / 2 times the largest speed) exceeds
+    // rebuild_e (99 % of half the skin); dt_bound: the fixed step, else the CFL step at
+    // zero speed, c_cfl h / max c0, which no adaptive step exceeds
+    double rebuild_e, dt_bound;
     double g[3];
     double rho0[2], beta[2], nu[2];
     double vpair[2][2];   // 2 nu_ij (Eq. (10)) or 2 mu_ij (Eq. (11)) by phase pair
@@ -89,6 +93,8 @@ struct InstRun {
     unsigned long long umax2;  // bit pattern of max |u|^2 (FP64, non-negative)
     unsigned long long amax2;  // bit pattern of max |a|^2
     unsigned long long disp2;  // bit pattern of max |x - x_build|^2 since the last build
+    unsigned long long vmax2;  // bit pattern of max |u|^2 over fluid and moving particles of
+                               // the last corrector's state (or of the initial state)
     double dt, t, t_next;
     long long step;
     long long builds;          // neighbour builds so far
@@ -178,6 +184,7 @@ void launch_restore(const Dev& d, hipStream_t s);
 // Eq. (7) (parts bit 0), then the derive pass and the colour pass at S^n (bit 1)
 void launch_renorm_colour(const Dev& d, const Launch& L, hipStream_t s, int parts = 3);
 void launch_predict(const Dev& d, double dt_override, const Launch& L, hipStream_t s);   // a9 and S*
+void launch_place_moving(const Dev& d, uint32_t inst, hipStream_t s);   // sphx_set_moving
 // neighbour export: counts (pass 0) or ids (pass 1) in sorted order
 void launch_export(const Dev& d, int pass, const uint32_t* off, uint32_t* out,
                    const Launch& L, hipStream_t s);

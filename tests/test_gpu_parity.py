@@ -188,6 +188,74 @@ def test_neighbour_sets_stay_exact_after_gpu_steps():
     assert np.array_equal(goff, off) and np.array_equal(gids, ids)
 
 
+def _blob_lists(blob, s):
+    """Positions, velocities (sorted order) and the neighbour list of an FP64 state blob:
+    a 48-byte header, then pos, vel, aux (32 B per particle each), key, id, info (4 B),
+    the cell table (4 B per cell + 1), the run block (72 B per instance), acc and gc
+    (32 B), the list (entry e of particle i at 4 (e s + i), s = n rounded up to 32) and
+    the counts (4 B)."""
+    n = int(np.frombuffer(blob, np.int64, 1, 24)[0])
+    ncell = int(np.frombuffer(blob, np.uint32, 1, 32)[0])
+    cap = int(np.frombuffer(blob, np.uint32, 1, 40)[0])
+    at = 48
+    pos = np.frombuffer(blob, np.float64, 4 * n, at).reshape(n, 4)[:, :3]
+    vel = np.frombuffer(blob, np.float64, 4 * n, at + 32 * n).reshape(n, 4)[:, :3]
+    at += 96 * n + 12 * n + 4 * (ncell + 1) + 72 * s.ninst + 64 * n
+    ls = (n + 31) // 32 * 32
+    nbl = np.frombuffer(blob, np.uint32, ls * cap, at).reshape(cap, ls)
+    nbc = np.frombuffer(blob, np.uint32, n, at + 4 * ls * cap)
+    return pos, vel, nbl, nbc, cap
+
+
+def _missing_pairs(pos, nbl, nbc, cap, s):
+    """Pairs (i, j) within 2h (minimal image in a periodic box) that are not in i's list."""
+    h = s.params[0]["h"]
+    span = np.array(s.params[0]["hi"]) - np.array(s.params[0]["lo"])
+    per = np.array(s.params[0]["periodic"], bool)
+    d = pos[:, None, :] - pos[None, :, :]
+    for a in range(3):
+        if per[a]:
+            d[..., a] -= span[a] * np.round(d[..., a] / span[a])
+    near = (d ** 2).sum(-1) < 4 * h * h
+    np.fill_diagonal(near, False)
+    listed = np.zeros_like(near)
+    for i in range(len(pos)):
+        if nbc[i] <= cap:
+            listed[i, nbl[:nbc[i], i] & ((1 << 25) - 1)] = True
+        else:
+            listed[i] = True          # the stencil walk serves an overflowed list
+    return int((near & ~listed).sum())
+
+
+@pytest.mark.parametrize("name", ["periodic2d", "periodic3d"])
+def test_list_holds_every_pair_between_rebuilds(name):
+    # the rebuild rule: a list serves the states S^n and S* of every step until the next
+    # build, so every pair within 2h at those states must be in it.  Fast particles
+    # (rebuilds every few steps); after each step the state blob gives the positions and
+    # the list, and when the next step rebuilds nothing, the pairs within 2h at its S^n
+    # and at its predicted state x + dt/2 u (no walls or pistons here) are all listed
+    s = SCENES[name]()
+    rng = np.random.default_rng(5)
+    s.u[:, :s.dim] = rng.uniform(-0.15, 0.15, (s.n, s.dim))
+    print(f"case list coverage {name} n={s.n}", flush=True)
+    sim = binding.Sim(s, precision=binding.FP64)
+    sim.set_option(binding.OPT_GRAPH, 0)
+    checked, rebuilt = 0, 0
+    for _ in range(40):
+        pos, vel, nbl, nbc, cap = _blob_lists(sim.get_state(), s)
+        b0 = sim.stats()["builds"]
+        sim.step(1)
+        st = sim.stats()
+        if st["builds"] != b0:
+            rebuilt += 1
+            continue
+        assert _missing_pairs(pos, nbl, nbc, cap, s) == 0
+        assert _missing_pairs(pos + 0.5 * st["dt"] * vel, nbl, nbc, cap, s) == 0
+        checked += 1
+    print(f"  steps checked {checked}, steps that rebuilt {rebuilt}", flush=True)
+    assert checked >= 10 and rebuilt >= 3
+
+
 @pytest.mark.parametrize("lanes", [1, 4])
 @pytest.mark.parametrize("prec", PRECS)
 def test_steps_are_deterministic_and_graph_matches_eager(prec, lanes):
@@ -350,7 +418,7 @@ def test_set_state_rejects_out_of_range_indices():
     # the state blob's layout (header, then the spans of state_spans in the library):
     # a 48-byte header holding n at byte 24 and the cell count at byte 32, then in FP32
     # pos, vel, aux (16 B per particle each), key, id, info (4 B), the cell table
-    # (4 B per cell + 1), the run block (64 B per instance), acc and gc (16 B) and the
+    # (4 B per cell + 1), the run block (72 B per instance), acc and gc (16 B) and the
     # list, entry e of particle i at 4 (e s + i) with s = n rounded up to 32
     s = inputs.drop2d(perturb=True)
     print("case set_state validation", flush=True)
@@ -361,7 +429,7 @@ def test_set_state_rejects_out_of_range_indices():
     ncell = int(np.frombuffer(good, np.uint32, 1, 32)[0])
     assert n == s.n and ncell == a.stats()["ncells"]
     key_at = 48 + 48 * n
-    nbl_at = key_at + 12 * n + 4 * (ncell + 1) + 64 * s.ninst + 32 * n
+    nbl_at = key_at + 12 * n + 4 * (ncell + 1) + 72 * s.ninst + 32 * n
     assert np.frombuffer(good, np.uint32, 1, key_at)[0] < ncell
     assert (np.frombuffer(good, np.uint32, 1, nbl_at)[0] & ((1 << 25) - 1)) < n
     for at, bad in ((nbl_at, n), (key_at, ncell)):
