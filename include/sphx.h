@@ -216,9 +216,9 @@ sphx_status sphx_init_particles(sphx_ctx* ctx, const double* x, const double* u,
  * the kernel's support 2h; the paper leaves the search to the code it builds on, so the
  * cells of (2 + skin) h and the list radius with its skin are this library's (skin_coef
  * in sphx_params).  The other calls rebuild by themselves whenever a particle's
- * displacement since the last build, plus the half step the next predictor can take
- * (half the fixed step, or of the CFL step at zero speed, times the largest speed),
- * could exceed 99 % of half the skin; this call forces a rebuild.
+ * displacement since the last build, plus the half step the next predictor can give
+ * it (half the fixed step, or of the CFL step at zero speed, times its speed), could
+ * exceed 99 % of half the skin; this call forces a rebuild.
  * No arguments besides the context; errors as for sphx_step. */
 sphx_status sphx_build_neighbors(sphx_ctx* ctx);
 

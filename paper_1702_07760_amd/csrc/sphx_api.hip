@@ -876,14 +876,6 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemcpyAsync((void*)d.inst, c->inst.data(), sizeof(InstDev) * c->ninst, hipMemcpyHostToDevice, s));
     std::vector<InstRun> run(c->ninst);
     std::memset(run.data(), 0, sizeof(InstRun) * c->ninst);
-    // the largest speed of the particles that move, for the first rebuild decisions
-    for (int b = 0; b < c->ninst; ++b) {
-        double v2 = 0.0;
-        for (int64_t i = c->offsets[b]; i < c->offsets[b + 1]; ++i)
-            if (kind[i] != SPHX_WALL)
-                v2 = std::max(v2, u[3 * i] * u[3 * i] + u[3 * i + 1] * u[3 * i + 1] + u[3 * i + 2] * u[3 * i + 2]);
-        std::memcpy(&run[b].vmax2, &v2, sizeof v2);
-    }
     HIP_OK(c, hipMemcpyAsync(d.run, run.data(), sizeof(InstRun) * c->ninst, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemsetAsync(d.status, 0, sizeof(uint32_t), s));
     HIP_OK(c, hipMemsetAsync(d.fault, 0, sizeof(FaultRec), s));

@@ -53,8 +53,8 @@ struct InstDev {
     uint32_t cell_base, ncell;
     int32_t dim, visc_form, cont_form, renorm_every;
     double h, inv_h, cut2, cutl2, wcoef, fcoef, delta2, alpha_s, skin;
-    // rebuild once some particle's displacement since the build plus the longest half
-    // step any particle can take next (dt_bound / 2 times the largest speed) exceeds
+    // rebuild once some particle's reach, its displacement since the build plus the
+    // longest half step it can take next (dt_bound / 2 times its speed), exceeds
     // rebuild_e (99 % of half the skin); dt_bound: the fixed step, else the CFL step at
     // zero speed, c_cfl h / max c0, which no adaptive step exceeds
     double rebuild_e, dt_bound;
@@ -92,9 +92,8 @@ struct FaultRec {
 struct InstRun {
     unsigned long long umax2;  // bit pattern of max |u|^2 (FP64, non-negative)
     unsigned long long amax2;  // bit pattern of max |a|^2
-    unsigned long long disp2;  // bit pattern of max |x - x_build|^2 since the last build
-    unsigned long long vmax2;  // bit pattern of max |u|^2 over fluid and moving particles of
-                               // the last corrector's state (or of the initial state)
+    unsigned long long reach2; // bit pattern of the largest (|x - x_build| + dt_bound |u| / 2)^2
+                               // over the last corrector's state (0 after a build)
     double dt, t, t_next;
     long long step;
     long long builds;          // neighbour builds so far

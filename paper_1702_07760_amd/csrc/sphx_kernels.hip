@@ -708,9 +708,9 @@ __device__ __forceinline__ bool stalled(const Dev& d)
 }
 
 // Start of a step (or of a rate evaluation): rebuild the sort and the list when the host
-// asked for it, or when the displacement since the last build plus the longest half
-// step the coming predictor can take could bring some particle within 1 % of half the
-// skin from its build position.  Every block takes the decision from the same inputs (nothing changes them
+// asked for it, or when some particle's reach (its displacement since the last build
+// plus the longest half step the coming predictor can give it) is within 1 % of half
+// the skin.  Every block takes the decision from the same inputs (nothing changes them
 // before the scan's middle pass, which resets them); block 0 publishes it in flag 0.
 // No rebuild either after a grid barrier of the one-launch build stalled.
 __device__ __forceinline__ bool build_decision(const Dev& d)
@@ -718,12 +718,8 @@ __device__ __forceinline__ bool build_decision(const Dev& d)
     __shared__ int any;
     if (threadIdx.x == 0) any = d.flags[1] ? 1 : 0;
     __syncthreads();
-    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) {
-        const InstDev& I = d.inst[b];
-        const double moved = sqrt(__longlong_as_double((long long)d.run[b].disp2));
-        const double vmax = sqrt(__longlong_as_double((long long)d.run[b].vmax2));
-        if (moved + 0.5 * I.dt_bound * vmax > I.rebuild_e) atomicOr(&any, 1);
-    }
+    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x)
+        if (sqrt(__longlong_as_double((long long)d.run[b].reach2)) > d.inst[b].rebuild_e) atomicOr(&any, 1);
     __syncthreads();
     const bool rebuild = any != 0 && !stalled(d);
     if (blockIdx.x == 0 && threadIdx.x == 0) d.flags[0] = rebuild ? 1u : 0u;
@@ -816,7 +812,7 @@ __device__ __forceinline__ void reset_decision(const Dev& d)
         d.flags[1] = 0u;
         *d.icount = 0u;
     }
-    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) d.run[b].disp2 = 0ull;
+    for (int b = threadIdx.x; b < d.ninst; b += blockDim.x) d.run[b].reach2 = 0ull;
 }
 
 // The gathered copy becomes the current state set (one block); prevp keeps the old one.
@@ -1840,16 +1836,15 @@ __device__ __forceinline__ void force_reduce(const Dev& d, bool valid, uint32_t 
 }
 
 template <class R, int DIM>
-__device__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst, double& speed2);
+__device__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst);
 __device__ void finish_steps(const Dev& d);
 
-// Per instance: the running maximum of the displacement since the last build, and the
-// maximum speed of the new state (for the next rebuild decision).
-__device__ __forceinline__ void move_reduce(const Dev& d, bool mine, uint32_t b, double moved2, double speed2)
+// Per instance: the largest reach of the new state (for the next rebuild decision).
+__device__ __forceinline__ void reach_reduce(const Dev& d, bool mine, uint32_t b, double reach2)
 {
-    const double v[2] = {moved2, speed2};
-    static constexpr unsigned long long InstRun::*f[2] = {&InstRun::disp2, &InstRun::vmax2};
-    block_max<2>(d, mine, b, v, f);
+    const double v[1] = {reach2};
+    static constexpr unsigned long long InstRun::*f[1] = {&InstRun::reach2};
+    block_max<1>(d, mine, b, v, f);
 }
 
 // With CORRECT (the pass at S*), each particle's corrector follows its rates in the same
@@ -1923,10 +1918,10 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_force(Dev d, int star, i
     if constexpr (CORRECT) {
         finish_steps(d);
         const bool mine = valid && sub == 0;
-        double moved2 = 0.0, speed2 = 0.0;
+        double reach2 = 0.0;
         uint32_t b = 0;
-        if (mine) moved2 = correct_one<R, DIM>(d, cur, i, b, speed2);
-        move_reduce(d, mine, b, moved2, speed2);
+        if (mine) reach2 = correct_one<R, DIM>(d, cur, i, b);
+        reach_reduce(d, mine, b, reach2);
     }
 }
 
@@ -1961,16 +1956,18 @@ __device__ __forceinline__ void store_steps(const Dev& d, double dt_override, ui
         const double dt = step_dt(d, b, dt_override, umax);
         // the corrector reuses the list of S^n: every pair within 2h at the predicted
         // positions must still be in it, which holds while no particle gets more than
-        // half the skin from its build position (the rebuild rule keeps room for the
-        // half step of any adaptive or fixed dt).  A step that breaks it is refused: an
-        // override longer than the bound the rule assumed, or, right after a build, a
-        // half step dt max|u| / 2 beyond skin / 2 (the adaptive step allows that only
+        // half the skin from its build position.  A particle's displacement plus
+        // dt_bound / 2 times its speed is at most the largest reach e (none since a
+        // build), and every speed is at most umax, so the half step keeps each particle
+        // within max(e + (dt - dt_bound) umax / 2, dt umax / 2) of its build position;
+        // a step beyond skin / 2 is refused: an override longer than dt_bound, or, right
+        // after a build, dt umax / 2 beyond skin / 2 (the adaptive step allows that only
         // above max|u| = c0 skin / (c_cfl - skin), 2 c0 / 3 at the defaults, far outside
         // the weakly compressible regime).
-        const double moved = sqrt(__longlong_as_double((long long)d.run[b].disp2));
-        if (moved + 0.5 * dt * umax > 0.5 * d.inst[b].skin * (1.0 + 1e-12) || !(dt > 0.0))
-            atomicOr(d.status, ST_DT);
-        d.run[b].vmax2 = 0ull;   // the corrector of this step takes the new maximum
+        const InstDev& I = d.inst[b];
+        const double e = sqrt(__longlong_as_double((long long)d.run[b].reach2));
+        const double far = fmax(e + 0.5 * fmax(dt - I.dt_bound, 0.0) * umax, 0.5 * dt * umax);
+        if (far > 0.5 * I.skin * (1.0 + 1e-12) || !(dt > 0.0)) atomicOr(d.status, ST_DT);
         d.run[b].dt = dt;
         d.run[b].t_next = d.run[b].t + dt;
     }
@@ -2101,7 +2098,7 @@ __global__ void k_predict(Dev d, double dt_override)
 // S^{n+1} = S^n + dt R(S*), in place
 // Corrector for one particle; returns |x - x_build|^2 and its instance.
 template <class R, int DIM>
-__device__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst, double& speed2)
+__device__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst)
 {
     const Sorted& O = d.O[cur];
     const StateSet& S = d.S[cur];
@@ -2153,23 +2150,24 @@ __device__ double correct_one(const Dev& d, int cur, uint32_t k, uint32_t& inst,
     ((R4<R>*)S.pos)[k] = p;
     ((R4<R>*)S.vel)[k] = v;
     ((R4<R>*)S.aux)[k] = x;
-    speed2 = kind == K_WALL ? 0.0 : (double)v.x * v.x + (double)v.y * v.y + (DIM == 3 ? (double)v.z * v.z : 0.0);
+    // the reach: displacement since the build plus the longest half step the next
+    // predictor can give this particle
+    const double speed2 = kind == K_WALL ? 0.0 : (double)v.x * v.x + (double)v.y * v.y + (DIM == 3 ? (double)v.z * v.z : 0.0);
     const R4<R> xb = ((const R4<R>*)d.xb)[k];
     const double ex = (double)p.x - (double)xb.x, ey = (double)p.y - (double)xb.y;
     const double ez = DIM == 3 ? (double)p.z - (double)xb.z : 0.0;
-    return ex * ex + ey * ey + ez * ez;
+    const double e = sqrt(ex * ex + ey * ey + ez * ez) + 0.5 * I.dt_bound * sqrt(speed2);
+    return e * e;
 }
 
 
 // A motion set from outside (sphx_set_moving): the MOVING particles of instance `inst`
 // take its state at the instance's current time at once (FP32: as offsets in their
-// current cells with the compensation cleared, as the corrector places them), and the
-// instance's largest speed takes their new speed into account.
+// current cells with the compensation cleared, as the corrector places them).
 template <class R>
 __global__ void k_place_moving(Dev d, uint32_t inst)
 {
     const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    double speed2 = 0.0;
     if (k < d.n) {
         const int cur = *d.curp;
         const Sorted& O = d.O[cur];
@@ -2187,11 +2185,8 @@ __global__ void k_place_moving(Dev d, uint32_t inst)
                 pl.x = pl.y = pl.z = 0.0f;
                 S.plo[k] = pl;
             }
-            speed2 = (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z;
         }
     }
-    const double m = wave_max(speed2);
-    if ((threadIdx.x & 63) == 0 && m > 0.0) max_update(&d.run[inst].vmax2, m);
 }
 
 // ------------------------------------------------------- neighbour export

@@ -191,7 +191,7 @@ def test_neighbour_sets_stay_exact_after_gpu_steps():
 def _blob_lists(blob, s):
     """Positions, velocities (sorted order) and the neighbour list of an FP64 state blob:
     a 48-byte header, then pos, vel, aux (32 B per particle each), key, id, info (4 B),
-    the cell table (4 B per cell + 1), the run block (72 B per instance), acc and gc
+    the cell table (4 B per cell + 1), the run block (64 B per instance), acc and gc
     (32 B), the list (entry e of particle i at 4 (e s + i), s = n rounded up to 32) and
     the counts (4 B)."""
     n = int(np.frombuffer(blob, np.int64, 1, 24)[0])
@@ -200,7 +200,7 @@ def _blob_lists(blob, s):
     at = 48
     pos = np.frombuffer(blob, np.float64, 4 * n, at).reshape(n, 4)[:, :3]
     vel = np.frombuffer(blob, np.float64, 4 * n, at + 32 * n).reshape(n, 4)[:, :3]
-    at += 96 * n + 12 * n + 4 * (ncell + 1) + 72 * s.ninst + 64 * n
+    at += 96 * n + 12 * n + 4 * (ncell + 1) + 64 * s.ninst + 64 * n
     ls = (n + 31) // 32 * 32
     nbl = np.frombuffer(blob, np.uint32, ls * cap, at).reshape(cap, ls)
     nbc = np.frombuffer(blob, np.uint32, n, at + 4 * ls * cap)
@@ -418,7 +418,7 @@ def test_set_state_rejects_out_of_range_indices():
     # the state blob's layout (header, then the spans of state_spans in the library):
     # a 48-byte header holding n at byte 24 and the cell count at byte 32, then in FP32
     # pos, vel, aux (16 B per particle each), key, id, info (4 B), the cell table
-    # (4 B per cell + 1), the run block (72 B per instance), acc and gc (16 B) and the
+    # (4 B per cell + 1), the run block (64 B per instance), acc and gc (16 B) and the
     # list, entry e of particle i at 4 (e s + i) with s = n rounded up to 32
     s = inputs.drop2d(perturb=True)
     print("case set_state validation", flush=True)
@@ -429,7 +429,7 @@ def test_set_state_rejects_out_of_range_indices():
     ncell = int(np.frombuffer(good, np.uint32, 1, 32)[0])
     assert n == s.n and ncell == a.stats()["ncells"]
     key_at = 48 + 48 * n
-    nbl_at = key_at + 12 * n + 4 * (ncell + 1) + 72 * s.ninst + 32 * n
+    nbl_at = key_at + 12 * n + 4 * (ncell + 1) + 64 * s.ninst + 32 * n
     assert np.frombuffer(good, np.uint32, 1, key_at)[0] < ncell
     assert (np.frombuffer(good, np.uint32, 1, nbl_at)[0] & ((1 << 25) - 1)) < n
     for at, bad in ((nbl_at, n), (key_at, ncell)):
