@@ -657,6 +657,9 @@ def test_set_moving_prescribes_a_linear_motion():
     t_call = o.t
     disp, vel = np.array([0.004, -0.001, 0.0]), np.array([0.15, 0.05, 0.0])
     o.set_moving(disp, vel)
+    # placed on the new motion at once
+    assert np.allclose(o.get(oracle.X)[mov], x0 + disp, rtol=0, atol=1e-15)
+    assert np.all(o.get(oracle.U)[mov] == vel)
     o.step(3)
     t = o.t
     x, u = o.get(oracle.X), o.get(oracle.U)
