@@ -133,8 +133,15 @@ enum {
                                  not taken: sphx_stats tells how many were), and returns
                                  SPHX_E_STALL; the context builds with seven launches from then
                                  on */
-    SPHX_OPT_FORCE_STALL = 9  /* for tests of that recovery: 1..5 makes grid barrier 1..5 of the next
+    SPHX_OPT_FORCE_STALL = 9, /* for tests of that recovery: 1..5 makes grid barrier 1..5 of the next
                                  one-launch build time out at once (0: none, the default) */
+    SPHX_OPT_COLOUR_IN_PREDICT = 10 /* 1: the colour pass at the predicted state runs in the
+                                 predictor's launch, its blocks computing the predicted state
+                                 of each particle of the colour list and of its other-phase
+                                 neighbours themselves (one launch less per step); 0: in a
+                                 launch of its own after the predictor.  Identical results.
+                                 sphx_init_particles sets 1 when at most 1,024 particles have a
+                                 phase other than 0 (a short colour list), else 0 */
 };
 
 /* Kernel groups timed under SPHX_OPT_PROFILE. */

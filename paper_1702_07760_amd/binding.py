@@ -25,6 +25,7 @@ OPT_DEBUG_TERMS, OPT_BLOCK, OPT_XCD_REMAP, OPT_GRAPH, OPT_LANES, OPT_PROFILE = 1
 OPT_FORCE_LANES = 7
 OPT_ONE_LAUNCH_BUILD = 8
 OPT_FORCE_STALL = 9
+OPT_COLOUR_IN_PREDICT = 10
 PHASES = ("build", "renorm", "colour", "force", "integrate")
 STATUS = {0: "SPHX_OK", 1: "SPHX_E_ARG", 2: "SPHX_E_NODEV", 3: "SPHX_E_HIP", 4: "SPHX_E_WORKSPACE",
           5: "SPHX_E_STATE", 6: "SPHX_E_NONFINITE", 7: "SPHX_E_DOMAIN", 8: "SPHX_E_DT", 9: "SPHX_E_STALL"}
@@ -276,16 +277,20 @@ class Sim:
         self._check(lib().sphx_get_option(self.ctx, int(opt), C.byref(v)), "sphx_get_option")
         return v.value
 
-    def set_launch(self, block=None, xcd_remap=None):
+    def set_launch(self, block=None, xcd_remap=None, colour_in_predict=None):
         if block is not None:
             self.set_option(OPT_BLOCK, block)
         if xcd_remap is not None:
             self.set_option(OPT_XCD_REMAP, xcd_remap)
+        if colour_in_predict is not None:
+            self.set_option(OPT_COLOUR_IN_PREDICT, colour_in_predict)
 
     def launch_options(self) -> dict:
-        """The launch shape in use: block size and tile order (what the tuner searches),
-        and the lanes per particle of the Eq. (7) and force passes."""
+        """The launch shape in use: block size, tile order and where the colour pass at S*
+        runs (what the tuner searches), and the lanes per particle of the Eq. (7) and force
+        passes."""
         return dict(block=self.get_option(OPT_BLOCK), xcd_remap=self.get_option(OPT_XCD_REMAP),
+                    colour_in_predict=self.get_option(OPT_COLOUR_IN_PREDICT),
                     lanes=self.get_option(OPT_LANES), force_lanes=self.get_option(OPT_FORCE_LANES))
 
     def sync(self):

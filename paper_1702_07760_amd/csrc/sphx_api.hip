@@ -455,9 +455,10 @@ void enqueue_integrate(sphx_ctx* c, double dt_override)
 {
     {
         Timed t(c, SPHX_PH_INTEGRATE);
-        launch_predict(c->dev, dt_override, c->launch, c->stream);   // a9 inside
+        launch_predict(c->dev, dt_override, c->launch, c->stream);   // a9 (and the colour pass at S*)
     }
-    enqueue_rates(c, true, false);   // the corrector runs in the force launch at S*
+    // the corrector runs in the force launch at S*
+    enqueue_rates(c, true, false, !c->launch.colour_in_predict);
 }
 
 void enqueue_renorm(sphx_ctx* c, bool force)
@@ -820,6 +821,11 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
         }
     }
     c->has_moving = moving;
+    // a short colour list (a few drops) is walked beside the predictor: its wave per
+    // particle covers the list in one round there
+    int64_t other = 0;
+    for (int64_t i = 0; i < n; ++i) other += phase[i] != 0;
+    c->launch.colour_in_predict = other <= 1024;
     drop_graphs(c);
     for (auto& I : c->inst) I.mv_host = 0;   // MOVING particles follow the piston series again
 
@@ -1063,6 +1069,7 @@ sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
         break;
     case SPHX_OPT_GRAPH: c->use_graph = value != 0 && c->stream != nullptr; break;
     case SPHX_OPT_ONE_LAUNCH_BUILD: c->launch.one_launch_build = value != 0; break;
+    case SPHX_OPT_COLOUR_IN_PREDICT: c->launch.colour_in_predict = value != 0; break;
     case SPHX_OPT_FORCE_STALL:
         if (value < 0 || value > 5) return fail(c, SPHX_E_ARG, "force_stall must be 0..5");
         c->launch.stall_at = (int)value;
@@ -1091,6 +1098,7 @@ sphx_status sphx_get_option(sphx_ctx* c, int32_t option, int64_t* value)
     case SPHX_OPT_FORCE_LANES: *value = c->launch.force_lanes; break;
     case SPHX_OPT_GRAPH: *value = c->use_graph; break;
     case SPHX_OPT_ONE_LAUNCH_BUILD: *value = c->launch.one_launch_build; break;
+    case SPHX_OPT_COLOUR_IN_PREDICT: *value = c->launch.colour_in_predict; break;
     case SPHX_OPT_FORCE_STALL: *value = c->launch.stall_at; break;
     case SPHX_OPT_PROFILE: *value = c->profile; break;
     default: return fail(c, SPHX_E_ARG, "unknown option %d", (int)option);

@@ -166,6 +166,7 @@ struct Launch {
     int lanes = 4;       // lanes per particle in the renormalisation pass (1, 2, 4)
     int force_lanes = 1; // lanes per particle in the force pass (1, 2, 4)
     bool one_launch_build = true;   // the build as one launch with grid barriers (else seven)
+    bool colour_in_predict = true;  // the colour pass at S* inside the predictor's launch
     int stall_at = 0;    // test hook: barrier of the one-launch build forced to time out (0: none)
     bool debug_terms = false;
 };

@@ -1403,15 +1403,15 @@ __device__ __forceinline__ R v_of(const IC& I, uint32_t phase, R m, R stored)
 template <class R> struct MV { R a, b; };
 
 // Where the colour pass takes its state.  A source gives the positions (src.pos[k]),
-// what V_k needs, requested with the position (src.load(k)), V_k from that for a
-// neighbour of phase ph (src.vk), and V_i (src.vi).
+// what V_k needs, requested with the position (src.load(k)), V_k from that and the
+// position record for a neighbour of phase ph (src.vk), and V_i (src.vi).
 //
 // At a state whose derive pass has run: V from the velocity record (|w|).
 template <class R> struct ColourFromVel {
     const R4<R>* pos;
     const R4<R>* vel;
     __device__ MV<R> load(uint32_t k) const { return MV<R>{fabs(vel[k].w), (R)0}; }
-    template <class IC> __device__ R vk(const IC&, uint32_t, const MV<R>& x) const { return x.a; }
+    template <class IC> __device__ R vk(const IC&, uint32_t, const MV<R>& x, const R4<R>&) const { return x.a; }
     template <class IC> __device__ R vi(const IC&, uint32_t i, uint32_t) const { return fabs(vel[i].w); }
 };
 
@@ -1427,7 +1427,7 @@ template <class R> struct ColourFromRho {
     {
         return MV<R>{umass ? (R)0 : aux[4 * (size_t)k], dens[(size_t)k * stride]};
     }
-    template <class IC> __device__ R vk(const IC& I, uint32_t ph, const MV<R>& x) const
+    template <class IC> __device__ R vk(const IC& I, uint32_t ph, const MV<R>& x, const R4<R>&) const
     {
         R m;
         if constexpr (sizeof(R) == 8) m = umass ? (ph ? I.mass[1] : I.mass[0]) : x.a;
@@ -1462,9 +1462,9 @@ __device__ __forceinline__ void colour_one(const Dev& d, int cur, uint32_t g, ui
         // C_j^y = 1 only for the other phase: the list walk skips i's own phase
         for_each_neighbor<R, DIM, kColourBatch, P, true, WIDE>(d, I, O, src.pos, i, L, sub,
             [&](uint32_t k) { return src.load(k); },
-            [&](uint32_t, const R* r, R r2, const R4<R>&, uint32_t phj, const MV<R>& x) {
+            [&](uint32_t, const R* r, R r2, const R4<R>& pj, uint32_t phj, const MV<R>& x) {
                 if (phj == ph) return;                           // (the stencil fallback)
-                const R vk = src.vk(I, phj, x);                  // V_k = 1 / sigma_k
+                const R vk = src.vk(I, phj, x, pj);              // V_k = 1 / sigma_k
                 const R f = kernel_f<R>(I, r2) * (vk * vk);
                 s[0] += f * r[0];
                 s[1] += f * r[1];
@@ -2075,14 +2075,56 @@ __device__ __forceinline__ void predict_state(const Dev& d, int cur, uint32_t k,
     derive_one<R>(I, info_phase(info), pred_rho<R>(x.w, hdt, a.w), p, v, x, false);
 }
 
-// S* = S^n + dt/2 R(S^n)
+// The predicted state S* of any particle, computed from S^n and its rates with the
+// predictor's own arithmetic: pos[k] is its position record with V* in w (the sentinel
+// index n gives the far-away record of S^n).  Neighbours share i's instance, so they
+// share its half step hdt.
+template <class R, int DIM> struct PredictedPos {
+    const Dev* d;
+    int cur;
+    double hdt;
+    __device__ R4<R> operator[](uint32_t k) const
+    {
+        if (k >= d->n) return ((const R4<R>*)d->S[cur].pos)[k];
+        const uint32_t info = d->O[cur].info[k];
+        R4<R> p, v, x;
+        predict_state<R, DIM>(*d, cur, k, info, d->inst[info_inst(info)], hdt, p, v, x);
+        p.w = v.w;
+        return p;
+    }
+};
+
+// Colour source at S* computed in the predictor's launch (V* from the predicted record).
+template <class R, int DIM> struct ColourPredicted {
+    PredictedPos<R, DIM> pos;
+    __device__ MV<R> load(uint32_t) const { return MV<R>{(R)0, (R)0}; }
+    template <class IC> __device__ R vk(const IC&, uint32_t, const MV<R>&, const R4<R>& pj) const { return pj.w; }
+    template <class IC> __device__ R vi(const IC&, uint32_t i, uint32_t) const { return pos[i].w; }
+};
+
+// S* = S^n + dt/2 R(S^n), and in the same launch Eq. (16) at S*: the first cblocks
+// blocks walk the colour list, computing the predicted state of i and of its
+// other-phase neighbours themselves, so they need none of the predictor's writes.  The
+// colour blocks write V* with its sign for the particles of the colour list; the
+// predictor blocks write the rest of their velocity records and everything of the
+// other particles.  Without colour blocks (cblocks = 0) the predictor writes every
+// record whole, and the colour pass at S* follows in a launch of its own.
 template <class R, int DIM>
-__global__ void k_predict(Dev d, double dt_override)
+__global__ void __launch_bounds__(256) k_predict(Dev d, double dt_override, uint32_t cblocks)
 {
     if (stalled(d)) return;
     const int cur = *d.curp;
-    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    store_steps(d, dt_override, k, gridDim.x * blockDim.x);
+    if (blockIdx.x < cblocks) {
+        colour_walk<R, DIM>(d, cur, blockIdx.x * blockDim.x + threadIdx.x, cblocks * blockDim.x, (R4<R>*)d.star.vel,
+                            [&](const InstU&, uint32_t info) {
+                                double umax;
+                                const double hdt = 0.5 * step_dt(d, info_inst(info), dt_override, umax);
+                                return ColourPredicted<R, DIM>{PredictedPos<R, DIM>{&d, cur, hdt}};
+                            });
+        return;
+    }
+    const uint32_t k = (blockIdx.x - cblocks) * blockDim.x + threadIdx.x;
+    store_steps(d, dt_override, k, (gridDim.x - cblocks) * blockDim.x);
     if (k >= d.n) return;
     const uint32_t info = d.O[cur].info[k];
     const uint32_t b = info_inst(info);
@@ -2091,7 +2133,14 @@ __global__ void k_predict(Dev d, double dt_override)
     R4<R> p, v, x;
     predict_state<R, DIM>(d, cur, k, info, d.inst[b], hdt, p, v, x);
     ((R4<R>*)d.star.pos)[k] = p;
-    ((R4<R>*)d.star.vel)[k] = v;
+    if (cblocks > 0 && (info & kInfoColour)) {
+        R* vr = (R*)d.star.vel + 4 * (size_t)k;
+        vr[0] = v.x;
+        vr[1] = v.y;
+        vr[2] = v.z;
+    } else {
+        ((R4<R>*)d.star.vel)[k] = v;
+    }
     ((R4<R>*)d.star.aux)[k] = x;
 }
 
@@ -2365,10 +2414,12 @@ void launch_force(const Dev& d, bool star, bool reduce_max, bool correct, const 
     })));
 }
 
-void launch_predict(const Dev& d, double dt_override, const Launch&, hipStream_t s)
+void launch_predict(const Dev& d, double dt_override, const Launch& L, hipStream_t s)
 {
+    // colour blocks first: the list length is known only on the device
+    const unsigned cb = L.colour_in_predict ? std::min<unsigned>(blocks_for(d.n * kColourLanes, 256), 1024u) : 0u;
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_predict<R, D>), dim3(blocks_for(d.n, 256)), dim3(256), 0, s, d, dt_override);
+        hipLaunchKernelGGL((k_predict<R, D>), dim3(cb + blocks_for(d.n, 256)), dim3(256), 0, s, d, dt_override, cb);
     }));
 }
 

@@ -809,6 +809,27 @@ def test_tuned_launch_shapes_give_bit_identical_runs(prec):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("name", ["drop3d_small", "periodic2d"])
+def test_colour_pass_at_the_predicted_state_in_either_launch(name, prec):
+    # the colour pass at S* beside the predictor (computing the predicted states itself)
+    # or in its own launch after it: bit-identical runs; periodic2d's colour list is long
+    # against its launch (8 lanes per particle), drop3d_small's short (a wave each)
+    s = SCENES[name]()
+    print(f"case colour in predict {name} precision={prec} n={s.n}", flush=True)
+    runs = []
+    for inside in (1, 0):
+        sim = binding.Sim(s, precision=prec, tuned=False)
+        sim.set_launch(colour_in_predict=inside)
+        assert sim.launch_options()["colour_in_predict"] == inside
+        sim.step(12)
+        sim.sync()
+        runs.append([sim.get_field(f) for f in (binding.F_X, binding.F_U, binding.F_RHO, binding.F_GRADC)])
+        sim.close()
+    for a, b in zip(*runs):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("remap", [0, 1, 16])
 def test_rates_with_other_tile_orders(remap, oracle_rates):
     s, ref, _ = oracle_rates("drop3d_small")
