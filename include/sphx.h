@@ -110,8 +110,10 @@ enum {
     SPHX_OPT_XCD_REMAP = 3,   /* tile order of the neighbour passes: 0 dispatch order; 1 consecutive
                                  tiles on one XCD; K = 2, 4, ..., 64 also gives the K workgroups
                                  a CU holds at once K consecutive tiles, assuming round-robin
-                                 dispatch over an XCD's 32 CUs (default: 3D 0; 2D 4 in FP32,
-                                 1 in FP64, 16 where the 2D block is 128) */
+                                 dispatch over an XCD's 32 CUs; -C (C = 2, 4, ..., 64) deals
+                                 chunks of C consecutive tiles round-robin to the XCDs
+                                 (default: 3D 0; 2D 4 in FP32, 1 in FP64, 16 where the 2D
+                                 block is 128) */
     SPHX_OPT_GRAPH = 4,       /* 1: sphx_step replays a captured hipGraph per step (default 1) */
     SPHX_OPT_LANES = 5,       /* lanes that share one particle's neighbour loop in the renormalisation
                                  pass: 1, 2 or 4 (default 4; 1 for 2D contexts of 2^20

@@ -1057,11 +1057,13 @@ sphx_status sphx_set_option(sphx_ctx* c, int32_t option, int64_t value)
         if (value < 64 || value > 256 || value % 64) return fail(c, SPHX_E_ARG, "block must be 64, 128, 192 or 256");
         c->launch.block = (int)value;
         break;
-    case SPHX_OPT_XCD_REMAP:
-        if (value < 0 || value > 64 || (value > 1 && (value & (value - 1))))
-            return fail(c, SPHX_E_ARG, "xcd_remap must be 0, 1 or a power of two up to 64");
+    case SPHX_OPT_XCD_REMAP: {
+        const int64_t mag = value < 0 ? -value : value;
+        if (mag > 64 || (mag > 1 && (mag & (mag - 1))) || value == -1)
+            return fail(c, SPHX_E_ARG, "xcd_remap must be 0, 1, or plus or minus a power of two from 2 to 64");
         c->launch.xcd_remap = (int)value;
         break;
+    }
     case SPHX_OPT_LANES:
     case SPHX_OPT_FORCE_LANES:
         if (value != 1 && value != 2 && value != 4) return fail(c, SPHX_E_ARG, "lanes must be 1, 2 or 4");

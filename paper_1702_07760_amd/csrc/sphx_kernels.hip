@@ -33,6 +33,16 @@ __device__ __forceinline__ uint32_t tile_index(int remap)
 {
     const uint32_t b = blockIdx.x, G = gridDim.x;
     if (!remap) return b;
+    if (remap < 0) {
+        // chunks of C = -remap consecutive tiles dealt round-robin to the 8 XCDs: each
+        // XCD's L2 sees runs of neighbouring tiles, and every region's work is spread
+        // over all XCDs (a bijection on the full rounds of 8 C workgroups)
+        constexpr uint32_t X = 8;
+        const uint32_t C = (uint32_t)(-remap), full = (G / (X * C)) * (X * C);
+        if (b >= full) return b;
+        const uint32_t xcd = b % X, j = b / X;
+        return ((j / C) * X + xcd) * C + j % C;
+    }
     // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous run of
     // tiles so that neighbouring particles share one L2.
     const uint32_t X = 8, full = (G / X) * X;

@@ -5,7 +5,8 @@ fastest.  It searches only options that leave every result bit-identical, since
 each particle's arithmetic, and its order, do not depend on them:
   block        threads per block of the neighbour passes (64, 128, 192, 256);
   xcd_remap    tile order: dispatch order (0), consecutive tiles per XCD (1), and K
-               consecutive tiles per CU as well (K = 4, 16).
+               consecutive tiles per CU as well (K = 4, 16), or chunks of C tiles
+               dealt round-robin to the XCDs (-C: C = 4, 16).
 Lanes per particle split a particle's sums differently, and the neighbour skin sets
 the cell size and so the sorted order: both change results at the rounding level,
 so they keep the library's defaults.  The search is coordinate descent from the
@@ -23,7 +24,7 @@ import time
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 BLOCKS = (64, 128, 192, 256)
-REMAPS = (0, 1, 4, 16)
+REMAPS = (0, 1, 4, 16, -4, -16)
 KEYS = ("block", "xcd_remap")
 
 

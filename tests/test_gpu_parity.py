@@ -796,7 +796,7 @@ def test_tuned_launch_shapes_give_bit_identical_runs(prec):
     s = inputs.drop3d(scale=0.3, perturb=True)
     print(f"case tuned launch precision={prec} n={s.n}", flush=True)
     runs = []
-    for block, remap in ((None, None), (64, 16), (256, 1), (192, 0)):
+    for block, remap in ((None, None), (64, 16), (256, 1), (192, 0), (128, -16)):
         sim = binding.Sim(s, precision=prec, tuned=False)
         sim.set_launch(block=block, xcd_remap=remap)
         sim.step(12)
@@ -830,7 +830,7 @@ def test_colour_pass_at_the_predicted_state_in_either_launch(name, prec):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("remap", [0, 1, 16])
+@pytest.mark.parametrize("remap", [0, 1, 16, -4])
 def test_rates_with_other_tile_orders(remap, oracle_rates):
     s, ref, _ = oracle_rates("drop3d_small")
     print(f"case rates remap={remap}", flush=True)
@@ -843,8 +843,9 @@ def test_rates_with_other_tile_orders(remap, oracle_rates):
     assert rel_to(sim.get_field(binding.F_RHO), ref[oracle.RHO], 1000.0) < tol
     total_scale = ref[oracle.SAP] + ref[oracle.SAV] + ref[oracle.SAS]
     assert enorm(sim.get_field(binding.F_A), ref[oracle.A], total_scale) < tol
-    with pytest.raises(binding.SphxError, match="xcd_remap"):
-        sim.set_option(binding.OPT_XCD_REMAP, 3)
+    for bad in (3, -1, -3, 128):
+        with pytest.raises(binding.SphxError, match="xcd_remap"):
+            sim.set_option(binding.OPT_XCD_REMAP, bad)
 
 
 def test_tile_orders_give_identical_rates_on_the_full_drop():
@@ -852,7 +853,7 @@ def test_tile_orders_give_identical_rates_on_the_full_drop():
     # tile permutations (full 32 K chunks only exist at this size) change nothing
     s = inputs.drop3d()
     out = []
-    for remap in (1, 4, 16):
+    for remap in (1, 4, 16, -4, -16):
         sim = binding.Sim(s, precision=binding.FP32_CELLREL)
         sim.set_option(binding.OPT_XCD_REMAP, remap)
         sim.renormalize_density()
