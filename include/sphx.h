@@ -172,6 +172,8 @@ typedef struct {
     int64_t phase_launches[5];/* SPHX_OPT_PROFILE: timed launches per kernel group */
     int64_t colour_particles; /* particles with another phase in their neighbour list at the
                                  last build: the work list of the colour pass (Eq. (16)) */
+    int64_t two_level_builds; /* one-launch rebuilds whose later grid barriers took the
+                                 two-level form (one L2 write-back and invalidation per XCD) */
 } sphx_stats;
 
 /* Bytes of device workspace for ninst instances holding counts[b] particles. */

@@ -55,7 +55,7 @@ class Stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("t", C.c_double), ("dt", C.c_double),
                 ("interactions", C.c_int64), ("ncells", C.c_int64), ("builds", C.c_int64),
                 ("phase_ms", C.c_double * 5), ("phase_launches", C.c_int64 * 5),
-                ("colour_particles", C.c_int64)]
+                ("colour_particles", C.c_int64), ("two_level_builds", C.c_int64)]
 
 
 class SphxError(RuntimeError):
@@ -300,7 +300,7 @@ class Sim:
         s = Stats()
         self._check(lib().sphx_get_stats(self.ctx, C.byref(s)), "sphx_get_stats")
         return dict(steps=s.steps, t=s.t, dt=s.dt, interactions=s.interactions, ncells=s.ncells,
-                    builds=s.builds, colour_particles=s.colour_particles,
+                    builds=s.builds, colour_particles=s.colour_particles, two_level_builds=s.two_level_builds,
                     phase_ms={k: s.phase_ms[q] for q, k in enumerate(PHASES)},
                     phase_launches={k: s.phase_launches[q] for q, k in enumerate(PHASES)})
 

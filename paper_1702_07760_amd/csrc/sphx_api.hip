@@ -252,7 +252,7 @@ size_t carve(Dev& d, void* base, int precision, int dim, int64_t n, uint32_t nce
     d.inter = c.take<unsigned long long>((size_t)kInterSlots * kInterStride);
     d.curp = c.take<int>(1);
     d.prevp = c.take<int>(1);
-    d.bar = c.take<unsigned>(512 + 4096);   // the one-launch build's barrier words and slots
+    d.bar = c.take<unsigned>(kBarWords);   // the one-launch build's barrier words and slots
     d.flags = c.take<uint32_t>(4);
     d.cnt = c.take<uint32_t>(ncell);
     d.cstart = c.take<uint32_t>((size_t)ncell + 1);
@@ -329,7 +329,7 @@ sphx_status status_of(sphx_ctx* c)
         // list are not.  Clear what the next build expects cleared (barrier words that
         // may hold this launch's epochs, the cell counters) and rebuild from the current
         // set with seven launches, as every later build will be.
-        HIP_OK(c, hipMemset(c->dev.bar, 0, (512 + 4096) * sizeof(unsigned)));
+        HIP_OK(c, hipMemset(c->dev.bar, 0, kBarWords * sizeof(unsigned)));
         HIP_OK(c, hipMemset(c->dev.cnt, 0, (size_t)c->ncell * sizeof(uint32_t)));
         c->launch.one_launch_build = false;
         c->launch.stall_at = 0;
@@ -887,7 +887,7 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     HIP_OK(c, hipMemsetAsync(d.fault, 0, sizeof(FaultRec), s));
     HIP_OK(c, hipMemsetAsync(d.inter, 0, sizeof(unsigned long long) * kInterSlots * kInterStride, s));
     HIP_OK(c, hipMemsetAsync(d.icount, 0, sizeof(uint32_t), s));
-    HIP_OK(c, hipMemsetAsync(d.bar, 0, (512 + 4096) * sizeof(unsigned), s));
+    HIP_OK(c, hipMemsetAsync(d.bar, 0, kBarWords * sizeof(unsigned), s));
     HIP_OK(c, hipMemsetAsync(d.cnt, 0, sizeof(uint32_t) * c->ncell, s));
     HIP_OK(c, hipMemsetAsync(d.acc, 0, n * 4 * R, s));
     HIP_OK(c, hipMemsetAsync(d.gc, 0, (n + 1) * 4 * R, s));
@@ -927,8 +927,9 @@ sphx_status sphx_init_particles(sphx_ctx* c, const double* x, const double* u, c
     d.O[0].ref = moving ? lay.O[0].ref : nullptr;
     d.O[1].ref = moving ? lay.O[1].ref : nullptr;
     const int zero = 0;
-    // the first build is requested; the set-up derive leaves q in pos.w
-    const uint32_t flags[3] = {0u, 1u, 1u};
+    // the first build is requested; the set-up derive leaves q in pos.w; no build has
+    // taken the two-level barrier yet
+    const uint32_t flags[4] = {0u, 1u, 1u, 0u};
     HIP_OK(c, hipMemcpyAsync(d.curp, &zero, sizeof zero, hipMemcpyHostToDevice, s));
     HIP_OK(c, hipMemcpyAsync(d.flags, flags, sizeof flags, hipMemcpyHostToDevice, s));
     launch_derive(d, c->launch, s);
@@ -1137,6 +1138,9 @@ sphx_status sphx_get_stats(sphx_ctx* c, sphx_stats* out)
     uint32_t icount = 0;
     HIP_OK(c, hipMemcpy(&icount, c->dev.icount, sizeof icount, hipMemcpyDeviceToHost));
     out->colour_particles = icount;
+    uint32_t two = 0;
+    HIP_OK(c, hipMemcpy(&two, c->dev.flags + 3, sizeof two, hipMemcpyDeviceToHost));
+    out->two_level_builds = two;
     collect_events(c);
     for (int q = 0; q < SPHX_NPH; ++q) {
         out->phase_ms[q] = c->phase_ms[q];

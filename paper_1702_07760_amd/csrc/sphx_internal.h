@@ -46,6 +46,11 @@ constexpr uint32_t kInterSlots = 256u, kInterStride = 16u;
 constexpr uint32_t kIdxBits = 25, kIdxMask = (1u << kIdxBits) - 1u, kPhaseShift = 31;
 constexpr uint32_t kListPad = 16u;
 
+// Words of the one-launch build's barrier area: 1024 words of epoch, release, group and
+// go words (each on a cache line of its own), then 4096 arrival slots and 4096 XCD ids,
+// one of each per block.
+constexpr uint32_t kBarWords = 1024u + 2u * 4096u;
+
 struct InstDev {
     double lo[3], hi[3], span[3], cs[3];
     int32_t nc[3];
@@ -129,10 +134,11 @@ struct Dev {
     unsigned long long* inter;
     int* curp;           // which state set (0/1) holds the current sorted state
     int* prevp;          // during a rebuild: the set being sorted from (the old curp)
-    unsigned* bar;       // the one-launch build's grid barrier: epoch base, release words,
-                         // arrival slots (512 + 4096 words)
+    unsigned* bar;       // the one-launch build's grid barriers: epoch base, release, group and
+                         // go words, then an arrival slot and an XCD id per block (kBarWords)
     uint32_t* flags;     // [0] rebuild in this step, [1] rebuild requested by the host,
-                         // [2] pos.w holds q = (rho - rho0) / rho rather than m P / rho^2
+                         // [2] pos.w holds q = (rho - rho0) / rho rather than m P / rho^2,
+                         // [3] one-launch rebuilds that took the two-level barrier
     // build scratch
     uint32_t* cnt;       // ncell
     uint32_t* cstart;    // ncell + 1

@@ -1063,8 +1063,12 @@ __global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
 // waiting.
 constexpr uint32_t kBarrierSpins = 1u << 20;
 constexpr uint32_t kBarRelease = 32;     // release word r at bar[kBarRelease * (1 + r)], r < 8
-constexpr uint32_t kBarSlots = 512;      // arrival slot of block b at bar[kBarSlots + b]
+constexpr uint32_t kBarGroup = 512;      // two-level barrier: group word of group g at bar[kBarGroup + 32 g]
+constexpr uint32_t kBarGo = 768;         // and its go word at bar[kBarGo + 32 g]
+constexpr uint32_t kBarSlots = 1024;     // arrival slot of block b at bar[kBarSlots + b]
 constexpr uint32_t kBarMaxBlocks = 4096; // the one-launch build uses at most this many blocks
+constexpr uint32_t kBarXcc = kBarSlots + kBarMaxBlocks;   // XCD id of block b at bar[kBarXcc + b]
+static_assert(kBarXcc + kBarMaxBlocks == kBarWords, "barrier area layout");
 
 // Polls with relaxed loads (coherent, without the cache invalidation an acquire load
 // carries on every iteration); the caller fences once after the wait.
@@ -1110,6 +1114,75 @@ __device__ __forceinline__ bool grid_sync(const Dev& d, unsigned epoch, bool for
     return ok != 0;
 }
 
+// The XCD (accelerator complex die) this wave runs on.
+__device__ __forceinline__ uint32_t xcd_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u; }
+
+// Two-level form of grid_sync for a grid whose blocks b = g (mod 8) all run on one XCD
+// (the caller checks this).  An agent-scope release writes back the whole L2 of the
+// issuing wave's XCD and an acquire invalidates it; when every block does both, each of
+// the eight L2s is written back and invalidated once per block (128 times on the 3D
+// drop's grid of 1,024) while the other blocks of that XCD are already loading the next
+// phase's data into it, and the phases after such a barrier ran 3 to 7 times slower than
+// the same work as launches of their own.  Here block g < 8 leads group g: it waits for
+// its members' arrivals, writes its XCD's L2 back once and posts the group word; block 0
+// releases when every group has posted; each leader then invalidates its XCD's L2 once
+// and posts the group's go word, on which the members invalidate only their own CU's L1.
+// A member's stores are in its XCD's L2 once the block's barrier has waited for them,
+// and that L2 is written back after the member arrived; a load after the go word misses
+// an L2 invalidated after the release.  Waits are bounded as in grid_sync.
+__device__ __forceinline__ bool grid_sync_two_level(const Dev& d, unsigned epoch, bool forced)
+{
+    __shared__ int ok;
+    unsigned* bar = d.bar;
+    const uint32_t nb = gridDim.x, G = min(nb, 8u), b = blockIdx.x;
+    __syncthreads();   // every wave's stores have completed in this XCD's L2
+    if (threadIdx.x == 0) {
+        ok = 1;
+        __hip_atomic_store(&bar[kBarSlots + b], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (b < G) {
+        bool good = true;
+        for (uint32_t m = b + 8u * threadIdx.x; m < nb && good; m += 8u * blockDim.x)
+            good = !forced && bar_wait(&bar[kBarSlots + m], epoch);
+        const int arrived = __syncthreads_and(good ? 1 : 0);
+        if (threadIdx.x == 0) {
+            if (arrived) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the group's writes, then its word
+                __hip_atomic_store(&bar[kBarGroup + 32u * b], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                ok = 0;
+            }
+        }
+        if (b == 0) {
+            __syncthreads();
+            bool posted = ok != 0;
+            if (threadIdx.x < G && posted)
+                posted = !forced && bar_wait(&bar[kBarGroup + 32u * threadIdx.x], epoch);
+            const int all = __syncthreads_and(posted ? 1 : 0);
+            if (threadIdx.x == 0) {
+                if (all) {
+                    for (uint32_t r = 0; r < G; ++r)
+                        __hip_atomic_store(&bar[kBarRelease * (1 + r)], epoch, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                } else {
+                    ok = 0;
+                }
+            }
+        }
+        if (threadIdx.x == 0) {
+            if (!ok || forced || !bar_wait(&bar[kBarRelease * (1 + b)], epoch)) ok = 0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // this XCD's L2 and this CU's L1
+            if (ok) __hip_atomic_store(&bar[kBarGo + 32u * b], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (threadIdx.x == 0) {
+        if (forced || !bar_wait(&bar[kBarGo + 32u * (b & 7u)], epoch)) ok = 0;
+        asm volatile("s_waitcnt vmcnt(0)\n\tbuffer_inv sc0" ::: "memory");   // this CU's L1
+    }
+    __syncthreads();
+    if (!ok && threadIdx.x == 0) atomicOr(d.status, ST_STALL);
+    return ok != 0;
+}
+
 // The whole build in one launch.  Every block takes the rebuild decision; on the steps
 // without a rebuild (most of them) the launch ends there, where the seven-launch form
 // pays for seven launches.  On a rebuild the phases above run grid-stride, separated by
@@ -1126,19 +1199,33 @@ __global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_
     // this launch's barrier epochs are base + 1 .. base + 5; block 0 advances the base
     // after the last barrier, when every block has read it
     const unsigned base = __hip_atomic_load(&d.bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&d.bar[kBarXcc + blockIdx.x], xcd_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < n; b0 += T) hash_phase<R, DIM>(d, old, b0 + threadIdx.x);
     if (!grid_sync(d, base + 1, stall_at == 1)) return;
+    // barriers 2-5 take the two-level form when the blocks of each residue mod 8 share an
+    // XCD (the dispatcher deals blocks round-robin over the eight XCDs); every block reads
+    // the same ids after barrier 1, so all take the same form
+    bool same = true;
+    for (uint32_t m = threadIdx.x; m < gridDim.x; m += blockDim.x)
+        same = same && __hip_atomic_load(&d.bar[kBarXcc + m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                           __hip_atomic_load(&d.bar[kBarXcc + (m & 7u)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool two = __syncthreads_and(same ? 1 : 0) != 0;
+    if (two && blockIdx.x == 0 && threadIdx.x == 0) d.flags[3] += 1u;   // counted for sphx_get_stats
+    auto sync = [&](unsigned e, bool forced) {
+        return two ? grid_sync_two_level(d, e, forced) : grid_sync(d, e, forced);
+    };
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) scan_reduce_tile(d.cnt, d.ncell, d.scan_tmp, t);
-    if (!grid_sync(d, base + 2, stall_at == 2)) return;
+    if (!sync(base + 2, stall_at == 2)) return;
     // each tile sums the tile sums before it (few), so the scan needs no middle pass
     if (blockIdx.x == 0) reset_decision(d);
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x)
         scan_down_tile(d.cnt, d.ncell, tile_prefix(d.scan_tmp, t), d.cstart, t);
-    if (!grid_sync(d, base + 3, stall_at == 3)) return;
+    if (!sync(base + 3, stall_at == 3)) return;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) scatter_one(d, old, k);
-    if (!grid_sync(d, base + 4, stall_at == 4)) return;
+    if (!sync(base + 4, stall_at == 4)) return;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += T) rank_one<R, DIM>(d, old, k, with_ref);
-    if (!grid_sync(d, base + 5, stall_at == 5)) return;
+    if (!sync(base + 5, stall_at == 5)) return;
     if (blockIdx.x == 0) {
         flip_sets(d);   // read by the launches after this one; the list below takes 1 - old
         if (threadIdx.x == 0) __hip_atomic_store(&d.bar[0], base + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -16,6 +16,39 @@ def test_library_exports_every_header_symbol():
     assert not missing, missing
 
 
+def _header_structs():
+    """Field (name, C type, array length) lists of the header's typedef structs."""
+    import os
+    import re
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "sphx.h")
+    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    macros = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(\w+)\s+(\d+)", text)}
+    out = {}
+    for m in re.finditer(r"typedef struct\s*\{(.*?)\}\s*(\w+);", text, flags=re.S):
+        fields = []
+        for decl in filter(None, (d.strip() for d in m.group(1).split(";"))):
+            ctype, rest = decl.split(None, 1)
+            for v in rest.split(","):
+                f = re.match(r"(\w+)(?:\[(\w+)\])?$", v.strip())
+                n = f.group(2)
+                fields.append((f.group(1), ctype, None if n is None else int(macros.get(n, n))))
+        out[m.group(2)] = fields
+    return out
+
+
+@pytest.mark.parametrize("cname,cls", [("sphx_params", binding.Params), ("sphx_phase", binding.Phase),
+                                       ("sphx_stats", binding.Stats)])
+def test_binding_structs_match_the_header(cname, cls):
+    # the ctypes mirrors have the header's fields, in its order, with its types and sizes
+    ctypes_of = {"int32_t": C.c_int32, "int64_t": C.c_int64, "double": C.c_double}
+    want = _header_structs()[cname]
+    got = cls._fields_
+    assert [f[0] for f in got] == [w[0] for w in want]
+    for (name, ct), (_, ctype, n) in zip(got, want):
+        base = ctypes_of[ctype]
+        assert ct == (base if n is None else base * n), name
+
+
 def test_workspace_size_scales_with_particles_and_precision():
     s = inputs.drop2d()
     w64 = binding.workspace_size(s, binding.FP64)

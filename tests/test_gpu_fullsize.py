@@ -48,6 +48,8 @@ def test_full_size_step_matches_oracle(name, prec):
     sim.step(1)
     sim.sync()
     assert abs(sim.stats()["t"] - o.t) <= 1e-6 * o.t
+    # the build ran as one launch whose later barriers took the two-level form
+    assert sim.stats()["two_level_builds"] == sim.stats()["builds"] >= 1
     _compare(s, sim, o, prec)
 
 

@@ -303,6 +303,7 @@ def test_one_launch_build_matches_seven_launches(name, prec):
     a = binding.Sim(s, precision=prec)
     b = binding.Sim(s, precision=prec)
     b.set_option(binding.OPT_ONE_LAUNCH_BUILD, 0)
+    b_two = b.stats()["two_level_builds"]   # the build at creation ran as one launch
     for chunk in (1, 12, 20):
         a.step(chunk)
         b.step(chunk)
@@ -312,6 +313,10 @@ def test_one_launch_build_matches_seven_launches(name, prec):
         ob, ib = b.get_neighbors()
         assert np.array_equal(oa, ob) and np.array_equal(ia, ib)
     assert a.stats()["builds"] == b.stats()["builds"] > 1
+    # every one-launch rebuild took the two-level barrier (the blocks of each residue mod 8
+    # share an XCD on this device); the seven launches have no grid barrier
+    assert a.stats()["two_level_builds"] == a.stats()["builds"]
+    assert b.stats()["two_level_builds"] == b_two
 
 
 def _expect(code, call):
