@@ -981,9 +981,150 @@ __global__ void k_rank(Dev d, int with_ref)
 // gradient can be non-zero) are appended to the colour-pass index list; every other
 // particle gets a zero gradient and a cleared interface flag here, once per build.
 constexpr int kNlistLanes = 4;
+constexpr uint32_t kNlistTile = 256u / kNlistLanes;   // particles per block of the list build
+
+// LDS staging of the list build.  The 64 consecutive particles of a block usually lie in
+// a few cells of one cell row; the candidates of all of them are then the runs of nine
+// rows (three in 2D) over that x range plus one cell on each side.  The block copies
+// those runs (position record, phase in w) into LDS once with coalesced loads, and every
+// lane walks its particle's stencil there instead of gathering each candidate from
+// memory (about 540 per particle).  A block whose particles span two rows or two
+// instances, whose x range wraps a periodic x axis, or whose runs exceed the buffer
+// walks memory as before.  The staged walk visits the same candidates in the same order,
+// so the list is the same.
+constexpr uint32_t kStageBytes = 39936u;   // four blocks of the build fit one CU's 160 KB of LDS
+template <class R> struct Stage {
+    static constexpr uint32_t cap = kStageBytes / sizeof(R4<R>);
+    uint32_t g0[9], l0[10];   // per stencil row present: first staged index, its LDS offset
+    int ok;
+};
+
+template <class R> __device__ __forceinline__ R phase_as(uint32_t ph)
+{
+    if constexpr (sizeof(R) == 8) return (double)ph;
+    else return __uint_as_float(ph);
+}
+template <class R> __device__ __forceinline__ uint32_t phase_of(R w)
+{
+    if constexpr (sizeof(R) == 8) return (uint32_t)w;
+    else return __float_as_uint(w);
+}
+
+// Stages the runs for the block's particles i0 .. i0 + 63 (those below n).  Called by
+// every thread of the block; returns the same answer in all of them.
+template <class R, int DIM>
+__device__ bool stage_rows(const Dev& d, int cur, uint32_t i0, R4<R>* rec, Stage<R>& h)
+{
+    const Sorted& O = d.O[cur];
+    const uint32_t n = (uint32_t)d.n;
+    if (threadIdx.x == 0) {
+        h.ok = 0;
+        const uint32_t ie = min(i0 + kNlistTile, n) - 1u;
+        const uint32_t inst = info_inst(O.info[i0]);
+        if (inst == info_inst(O.info[ie])) {
+            const InstDev& I = d.inst[inst];
+            int ca[3], cb[3];
+            cell_of_key(I, O.key[i0], ca);
+            cell_of_key(I, O.key[ie], cb);
+            const int nx = I.nc[0];
+            int xlo = ca[0] - 1, xhi = cb[0] + 1;
+            bool ok = ca[1] == cb[1] && ca[2] == cb[2];
+            if (I.periodic[0]) ok = ok && xlo >= 0 && xhi < nx;
+            xlo = max(xlo, 0);
+            xhi = min(xhi, nx - 1);
+            uint32_t r = 0, tot = 0;
+            const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+            for (int dz = zlo; dz <= zhi && ok; ++dz) {
+                int cz = ca[2] + dz;
+                if (DIM == 3) {
+                    if (I.periodic[2]) cz = wrapi(cz, I.nc[2]);
+                    else if (cz < 0 || cz >= I.nc[2]) continue;
+                }
+                for (int dy = -1; dy <= 1; ++dy) {
+                    int cy = ca[1] + dy;
+                    if (I.periodic[1]) cy = wrapi(cy, I.nc[1]);
+                    else if (cy < 0 || cy >= I.nc[1]) continue;
+                    const uint32_t base = I.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)I.nc[1] * (uint32_t)cz);
+                    const uint32_t g0 = d.cstart[base + (uint32_t)xlo], g1 = d.cstart[base + (uint32_t)xhi + 1];
+                    h.g0[r] = g0;
+                    h.l0[r] = tot;
+                    tot += g1 - g0;
+                    ++r;
+                }
+            }
+            h.l0[r] = tot;
+            h.ok = ok && tot <= Stage<R>::cap ? (int)r + 1 : 0;
+        }
+    }
+    __syncthreads();
+    const int nr = h.ok - 1;
+    if (nr < 0) return false;
+    const uint32_t tot = h.l0[nr];
+    const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
+    for (uint32_t q = threadIdx.x; q < tot; q += blockDim.x) {
+        int r = 0;
+        while (q >= h.l0[r + 1]) ++r;
+        const uint32_t k = h.g0[r] + (q - h.l0[r]);
+        R4<R> v = pos[k];
+        v.w = phase_as<R>(info_phase(O.info[k]));
+        rec[q] = v;
+    }
+    __syncthreads();
+    return true;
+}
+
+// The stencil walk of for_neighbors (ALL form, x axis not wrapping) over the staged runs.
+template <class R, int DIM, int P, int U, class IC, class Body>
+__device__ __forceinline__ void for_staged(const IC& I, const uint32_t* __restrict__ cstart, const R4<R>* rec,
+                                           const Stage<R>& h, uint32_t i, const Lane<R>& L, R cut2,
+                                           uint32_t sub, Body&& body)
+{
+    const int nx = I.nc[0];
+    const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+    int rr = 0;
+    for (int dz = zlo; dz <= zhi; ++dz) {
+        int cz = L.c[2] + dz;
+        if (DIM == 3) {
+            if (I.periodic[2]) cz = wrapi(cz, I.nc[2]);
+            else if (cz < 0 || cz >= I.nc[2]) continue;
+        }
+        for (int dy = -1; dy <= 1; ++dy) {
+            int cy = L.c[1] + dy;
+            if (I.periodic[1]) cy = wrapi(cy, I.nc[1]);
+            else if (cy < 0 || cy >= I.nc[1]) continue;
+            Row<R> row;
+            row.base = I.cell_base + (uint32_t)nx * ((uint32_t)cy + (uint32_t)I.nc[1] * (uint32_t)cz);
+            row.code = ((uint32_t)(1 - dy) << 2) | ((uint32_t)(1 - dz) << 4);
+            row.dy1 = (float)(1 - dy);
+            row.dz1 = (float)(1 - dz);
+            const uint32_t a = cstart[row.base + (uint32_t)max(L.c[0] - 1, 0)];
+            const uint32_t b = cstart[row.base + (uint32_t)min(L.c[0] + 1, nx - 1) + 1];
+            const uint32_t m0 = cstart[row.base + (uint32_t)L.c[0]];
+            const uint32_t m1 = cstart[row.base + (uint32_t)L.c[0] + 1];
+            const R4<R>* rw = rec + h.l0[rr] - h.g0[rr];   // staged record of candidate k: rw[k]
+            ++rr;
+            for (uint32_t kb = a; kb < b; kb += U * P) {
+                const uint32_t k0 = kb + sub;
+                R4<R> pj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) pj[u] = rw[min(k0 + (uint32_t)(u * P), b - 1)];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t k = k0 + (uint32_t)(u * P);
+                    R r[3];
+                    const int dcx = 1 - (int)(k >= m0) - (int)(k >= m1);
+                    const uint32_t code = pair_r<DIM>(I, L, row, pj[u], dcx, r);
+                    const R r2 = dist2<DIM>(r[0], r[1], r[2]);
+                    body(k, r, r2, pj[u], phase_of<R>(pj[u].w), code, k < b && k != i && r2 < cut2);
+                }
+            }
+        }
+    }
+}
 
 template <class R, int DIM>
-__device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uint32_t sub)
+__device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uint32_t sub,
+                                          const R4<R>* rec = nullptr, const Stage<R>* stage = nullptr)
 {
     constexpr int P = kNlistLanes;
     const Sorted& O = d.O[cur];
@@ -1001,16 +1142,19 @@ __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uin
         const uint32_t cap = d.cap;
         uint32_t cnt = 0;
         bool other = false;
-        for_neighbors<R, DIM, P, StencilBatch<R>::U, true>(I, d.cstart, O, pos, i, L, cutl2_of<R>(I), sub,
-            [&](uint32_t k, const R*, R, const R4<R>&, uint32_t phj, uint32_t code, bool in) {
-                const uint32_t grp = (uint32_t)(__ballot(in) >> gbase) & gmask;
-                if (in) {
-                    const uint32_t q = cnt + (uint32_t)__popc(grp & below);
-                    if (q < cap) nb[(size_t)q * ls] = k | (code << kIdxBits) | (phj << kPhaseShift);
-                    other |= phj != ph;
-                }
-                cnt += (uint32_t)__popc(grp);
-            });
+        auto take = [&](uint32_t k, const R*, R, const R4<R>&, uint32_t phj, uint32_t code, bool in) {
+            const uint32_t grp = (uint32_t)(__ballot(in) >> gbase) & gmask;
+            if (in) {
+                const uint32_t q = cnt + (uint32_t)__popc(grp & below);
+                if (q < cap) nb[(size_t)q * ls] = k | (code << kIdxBits) | (phj << kPhaseShift);
+                other |= phj != ph;
+            }
+            cnt += (uint32_t)__popc(grp);
+        };
+        if (stage)
+            for_staged<R, DIM, P, StencilBatch<R>::U>(I, d.cstart, rec, *stage, i, L, cutl2_of<R>(I), sub, take);
+        else
+            for_neighbors<R, DIM, P, StencilBatch<R>::U, true>(I, d.cstart, O, pos, i, L, cutl2_of<R>(I), sub, take);
         // pad with the sentinel entry (index n, code 0, phase 0) to a multiple of kListPad
         if (cnt <= cap) {
             const uint32_t end = (cnt + kListPad - 1u) & ~(kListPad - 1u);
@@ -1040,14 +1184,26 @@ __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uin
     });
 }
 
+// The list of the block's particles i0 .. i0 + 63: staged when the runs allow it.  Every
+// thread of the (256-thread) block calls it.
 template <class R, int DIM>
-__global__ void __launch_bounds__(MaxBlock<R>::value) k_nlist(Dev d, int remap)
+__device__ __forceinline__ void nlist_tile(const Dev& d, int cur, uint32_t i0)
+{
+    __shared__ R4<R> rec[Stage<R>::cap];
+    __shared__ Stage<R> stage;
+    const bool staged = stage_rows<R, DIM>(d, cur, i0, rec, stage);
+    const uint32_t i = i0 + threadIdx.x / kNlistLanes, sub = threadIdx.x % kNlistLanes;
+    if (i < d.n) nlist_one<R, DIM>(d, cur, i, sub, rec, staged ? &stage : nullptr);
+    __syncthreads();   // the buffer is refilled by the block's next tile
+}
+
+template <class R, int DIM>
+__global__ void __launch_bounds__(256) k_nlist(Dev d, int remap)
 {
     if (!d.flags[0]) return;
-    uint32_t i, sub;
-    lane_split<kNlistLanes>(remap, i, sub);
-    if (i >= d.n) return;
-    nlist_one<R, DIM>(d, *d.curp, i, sub);
+    const uint32_t i0 = tile_index(remap) * kNlistTile;
+    if (i0 >= d.n) return;
+    nlist_tile<R, DIM>(d, *d.curp, i0);
 }
 
 // Grid-wide barrier of the one-launch build, whose grid is sized so that all its blocks
@@ -1230,11 +1386,8 @@ __global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_
         flip_sets(d);   // read by the launches after this one; the list below takes 1 - old
         if (threadIdx.x == 0) __hip_atomic_store(&d.bar[0], base + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    const uint32_t lanes = n * (uint32_t)kNlistLanes;
-    for (uint32_t b0 = blockIdx.x * blockDim.x; b0 < lanes; b0 += T) {
-        const uint32_t t = b0 + threadIdx.x;
-        if (t < lanes) nlist_one<R, DIM>(d, 1 - old, t / kNlistLanes, t % kNlistLanes);
-    }
+    for (uint32_t i0 = blockIdx.x * kNlistTile; i0 < n; i0 += gridDim.x * kNlistTile)
+        nlist_tile<R, DIM>(d, 1 - old, i0);
 }
 
 // ------------------------------------------------------ per-particle state
