@@ -974,18 +974,21 @@ __global__ void k_rank(Dev d, int with_ref)
 
 // Neighbour list at the current positions: every j within the cell size (2 + skin) h
 // (with a rounding margin).  Together with the rebuild rule this holds every pair within
-// 2h at any state evaluated before the next rebuild.  kNlistLanes lanes share a particle
-// and take every kNlistLanes-th candidate; a ballot ranks each slot's accepted
+// 2h at any state evaluated before the next rebuild.  NlistLanes lanes share a particle
+// and take every NlistLanes-th candidate; a ballot ranks each slot's accepted
 // candidates, so the list keeps the candidate order (the same as one lane would write).
 // Particles with an other-phase particle in their list (the only ones whose colour
 // gradient can be non-zero) are appended to the colour-pass index list; every other
 // particle gets a zero gradient and a cleared interface flag here, once per build.
-constexpr int kNlistLanes = 4;
-constexpr uint32_t kNlistTile = 256u / kNlistLanes;   // particles per block of the list build
+// Two lanes in FP32 (128 particles per 256-thread block), four in FP64, whose records
+// are twice as large: its staged runs for 128 particles would exceed the LDS buffer.
+template <class R> struct NlistLanes { static constexpr int value = sizeof(R) == 4 ? 2 : 4; };
+template <class R> struct NlistTile { static constexpr uint32_t value = 256u / NlistLanes<R>::value; };
 
-// LDS staging of the list build.  The 64 consecutive particles of a block usually lie in
-// a few cells of one cell row; the candidates of all of them are then the runs of nine
-// rows (three in 2D) over that x range plus one cell on each side.  The block copies
+// LDS staging of the list build.  The consecutive particles of a block (128 in FP32, 64
+// in FP64) usually lie in a few cells of one cell row; the candidates of all of them are
+// then the runs of nine rows (three in 2D) over that x range plus one cell on each side.
+// The block copies
 // those runs (position record, phase in w) into LDS once with coalesced loads, and every
 // lane walks its particle's stencil there instead of gathering each candidate from
 // memory (about 540 per particle).  A block whose particles span two rows or two
@@ -1010,8 +1013,8 @@ template <class R> __device__ __forceinline__ uint32_t phase_of(R w)
     else return __float_as_uint(w);
 }
 
-// Stages the runs for the block's particles i0 .. i0 + 63 (those below n).  Called by
-// every thread of the block; returns the same answer in all of them.
+// Stages the runs for the block's particles i0 .. i0 + NlistTile - 1 (those below n).
+// Called by every thread of the block; returns the same answer in all of them.
 template <class R, int DIM>
 __device__ bool stage_rows(const Dev& d, int cur, uint32_t i0, R4<R>* rec, Stage<R>& h)
 {
@@ -1019,7 +1022,7 @@ __device__ bool stage_rows(const Dev& d, int cur, uint32_t i0, R4<R>* rec, Stage
     const uint32_t n = (uint32_t)d.n;
     if (threadIdx.x == 0) {
         h.ok = 0;
-        const uint32_t ie = min(i0 + kNlistTile, n) - 1u;
+        const uint32_t ie = min(i0 + NlistTile<R>::value, n) - 1u;
         const uint32_t inst = info_inst(O.info[i0]);
         if (inst == info_inst(O.info[ie])) {
             const InstDev& I = d.inst[inst];
@@ -1126,7 +1129,7 @@ template <class R, int DIM>
 __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uint32_t sub,
                                           const R4<R>* rec = nullptr, const Stage<R>* stage = nullptr)
 {
-    constexpr int P = kNlistLanes;
+    constexpr int P = NlistLanes<R>::value;
     const Sorted& O = d.O[cur];
     const R4<R>* pos = (const R4<R>*)d.S[cur].pos;
     const R4<R> pi = pos[i];
@@ -1184,15 +1187,15 @@ __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uin
     });
 }
 
-// The list of the block's particles i0 .. i0 + 63: staged when the runs allow it.  Every
-// thread of the (256-thread) block calls it.
+// The list of the block's particles i0 .. i0 + NlistTile - 1: staged when the runs allow it.
+// Every thread of the (256-thread) block calls it.
 template <class R, int DIM>
 __device__ __forceinline__ void nlist_tile(const Dev& d, int cur, uint32_t i0)
 {
     __shared__ R4<R> rec[Stage<R>::cap];
     __shared__ Stage<R> stage;
     const bool staged = stage_rows<R, DIM>(d, cur, i0, rec, stage);
-    const uint32_t i = i0 + threadIdx.x / kNlistLanes, sub = threadIdx.x % kNlistLanes;
+    const uint32_t i = i0 + threadIdx.x / NlistLanes<R>::value, sub = threadIdx.x % NlistLanes<R>::value;
     if (i < d.n) nlist_one<R, DIM>(d, cur, i, sub, rec, staged ? &stage : nullptr);
     __syncthreads();   // the buffer is refilled by the block's next tile
 }
@@ -1201,7 +1204,7 @@ template <class R, int DIM>
 __global__ void __launch_bounds__(256) k_nlist(Dev d, int remap)
 {
     if (!d.flags[0]) return;
-    const uint32_t i0 = tile_index(remap) * kNlistTile;
+    const uint32_t i0 = tile_index(remap) * NlistTile<R>::value;
     if (i0 >= d.n) return;
     nlist_tile<R, DIM>(d, *d.curp, i0);
 }
@@ -1386,7 +1389,7 @@ __global__ void __launch_bounds__(256) k_build(Dev d, uint32_t ntiles, int with_
         flip_sets(d);   // read by the launches after this one; the list below takes 1 - old
         if (threadIdx.x == 0) __hip_atomic_store(&d.bar[0], base + 5, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    for (uint32_t i0 = blockIdx.x * kNlistTile; i0 < n; i0 += gridDim.x * kNlistTile)
+    for (uint32_t i0 = blockIdx.x * NlistTile<R>::value; i0 < n; i0 += gridDim.x * NlistTile<R>::value)
         nlist_tile<R, DIM>(d, 1 - old, i0);
 }
 
@@ -2533,7 +2536,7 @@ static unsigned build_grid(const Dev& d, uint32_t ntiles)
                                                  hipSuccess)
         ncu = 0;
     const uint64_t resident = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)ncu, kBarMaxBlocks);
-    uint64_t need = std::max<uint64_t>(blocks_for(d.n * kNlistLanes, 256), ntiles);
+    uint64_t need = std::max<uint64_t>(blocks_for(d.n * NlistLanes<R>::value, 256), ntiles);
     if (need < 1) need = 1;
     return (unsigned)std::min<uint64_t>(resident, need);
 }
@@ -2561,7 +2564,7 @@ static void build_impl(const Dev& d, const Launch& L, hipStream_t s)
     hipLaunchKernelGGL((k_rank<R, DIM>), dim3(blocks_for(d.n, B)), dim3(B), 0, s, d, d.O[0].ref ? 1 : 0);
     // 256-thread blocks: most steps skip the build, and a skipped launch costs in
     // proportion to its workgroup count
-    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n * kNlistLanes, 256)), dim3(256), 0, s, d,
+    hipLaunchKernelGGL((k_nlist<R, DIM>), dim3(blocks_for(d.n * NlistLanes<R>::value, 256)), dim3(256), 0, s, d,
                        L.xcd_remap);
 }
 
@@ -2584,7 +2587,7 @@ void launch_build(const Dev& d, const Launch& L, hipStream_t s)
 void launch_nlist(const Dev& d, const Launch& L, hipStream_t s)
 {
     SPHX_DISPATCH(d.precision, d.dim, ({
-        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n * kNlistLanes, 256)), dim3(256), 0, s, d,
+        hipLaunchKernelGGL((k_nlist<R, D>), dim3(blocks_for(d.n * NlistLanes<R>::value, 256)), dim3(256), 0, s, d,
                            L.xcd_remap);
     }));
 }
