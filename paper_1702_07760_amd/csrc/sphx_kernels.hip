@@ -988,13 +988,12 @@ template <class R> struct NlistTile { static constexpr uint32_t value = 256u / N
 // LDS staging of the list build.  The consecutive particles of a block (128 in FP32, 64
 // in FP64) usually lie in a few cells of one cell row; the candidates of all of them are
 // then the runs of nine rows (three in 2D) over that x range plus one cell on each side.
-// The block copies
-// those runs (position record, phase in w) into LDS once with coalesced loads, and every
-// lane walks its particle's stencil there instead of gathering each candidate from
-// memory (about 540 per particle).  A block whose particles span two rows or two
-// instances, whose x range wraps a periodic x axis, or whose runs exceed the buffer
-// walks memory as before.  The staged walk visits the same candidates in the same order,
-// so the list is the same.
+// The block copies those runs (position record, phase in w) into LDS once with coalesced
+// loads, and every lane walks its particle's stencil there instead of gathering each
+// candidate from memory (about 540 per particle).  A block whose particles span two rows
+// or two instances, whose x range wraps a periodic x axis, or whose runs exceed the
+// buffer walks memory as before.  The staged walk visits the same candidates in the same
+// order, so the list is the same.
 constexpr uint32_t kStageBytes = 39936u;   // four blocks of the build fit one CU's 160 KB of LDS
 template <class R> struct Stage {
     static constexpr uint32_t cap = kStageBytes / sizeof(R4<R>);
@@ -1144,15 +1143,27 @@ __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uin
         const size_t n = (size_t)d.n, ls = d.lstride;
         const uint32_t cap = d.cap;
         uint32_t cnt = 0;
-        bool other = false;
+        uint32_t other = 0;
         auto take = [&](uint32_t k, const R*, R, const R4<R>&, uint32_t phj, uint32_t code, bool in) {
-            const uint32_t grp = (uint32_t)(__ballot(in) >> gbase) & gmask;
-            if (in) {
-                const uint32_t q = cnt + (uint32_t)__popc(grp & below);
-                if (q < cap) nb[(size_t)q * ls] = k | (code << kIdxBits) | (phj << kPhaseShift);
-                other |= phj != ph;
+            uint32_t rank, accepted;
+            if constexpr (P == 2) {
+                // the pair's other lane by a lane swap (DPP quad_perm [1, 0, 3, 2]): lane 1's
+                // candidate follows lane 0's
+                const uint32_t mine = in ? 1u : 0u;
+                const uint32_t theirs = (uint32_t)__builtin_amdgcn_mov_dpp((int)mine, 0xB1, 0xF, 0xF, false);
+                rank = sub & theirs;
+                accepted = mine + theirs;
+            } else {
+                const uint32_t grp = (uint32_t)(__ballot(in) >> gbase) & gmask;
+                rank = (uint32_t)__popc(grp & below);
+                accepted = (uint32_t)__popc(grp);
             }
-            cnt += (uint32_t)__popc(grp);
+            if (in) {
+                const uint32_t q = cnt + rank;
+                if (q < cap) nb[(size_t)q * ls] = k | (code << kIdxBits) | (phj << kPhaseShift);
+                other |= phj ^ ph;
+            }
+            cnt += accepted;
         };
         if (stage)
             for_staged<R, DIM, P, StencilBatch<R>::U>(I, d.cstart, rec, *stage, i, L, cutl2_of<R>(I), sub, take);
@@ -1163,7 +1174,7 @@ __device__ __forceinline__ void nlist_one(const Dev& d, int cur, uint32_t i, uin
             const uint32_t end = (cnt + kListPad - 1u) & ~(kListPad - 1u);
             for (uint32_t q = cnt + sub; q < end; q += P) nb[(size_t)q * ls] = (uint32_t)n;
         }
-        const bool gother = ((uint32_t)(__ballot(other) >> gbase) & gmask) != 0u;
+        const bool gother = ((uint32_t)(__ballot(other != 0u) >> gbase) & gmask) != 0u;
         if (sub == 0) {
             d.nbc[i] = cnt;
             const uint32_t f = O.info[i];
