@@ -997,8 +997,10 @@ template <class R> struct NlistTile { static constexpr uint32_t value = 256u / N
 constexpr uint32_t kStageBytes = 39936u;   // four blocks of the build fit one CU's 160 KB of LDS
 template <class R> struct Stage {
     static constexpr uint32_t cap = kStageBytes / sizeof(R4<R>);
+    static constexpr uint32_t slack = 16;   // a batch (U P candidates) may read this far past a run
     uint32_t g0[9], l0[10];   // per stencil row present: first staged index, its LDS offset
-    int ok;
+    uint32_t rbase[9];        // key of the row's cell xlo
+    int xlo, ok;
 };
 
 template <class R> __device__ __forceinline__ R phase_as(uint32_t ph)
@@ -1034,6 +1036,7 @@ __device__ bool stage_rows(const Dev& d, int cur, uint32_t i0, R4<R>* rec, Stage
             if (I.periodic[0]) ok = ok && xlo >= 0 && xhi < nx;
             xlo = max(xlo, 0);
             xhi = min(xhi, nx - 1);
+            ok = ok && xhi - xlo < 256;   // a record's cell index from xlo takes 8 bits
             uint32_t r = 0, tot = 0;
             const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
             for (int dz = zlo; dz <= zhi && ok; ++dz) {
@@ -1050,12 +1053,14 @@ __device__ bool stage_rows(const Dev& d, int cur, uint32_t i0, R4<R>* rec, Stage
                     const uint32_t g0 = d.cstart[base + (uint32_t)xlo], g1 = d.cstart[base + (uint32_t)xhi + 1];
                     h.g0[r] = g0;
                     h.l0[r] = tot;
+                    h.rbase[r] = base + (uint32_t)xlo;
                     tot += g1 - g0;
                     ++r;
                 }
             }
             h.l0[r] = tot;
-            h.ok = ok && tot <= Stage<R>::cap ? (int)r + 1 : 0;
+            h.xlo = xlo;
+            h.ok = ok && tot + Stage<R>::slack <= Stage<R>::cap ? (int)r + 1 : 0;
         }
     }
     __syncthreads();
@@ -1068,7 +1073,8 @@ __device__ bool stage_rows(const Dev& d, int cur, uint32_t i0, R4<R>* rec, Stage
         while (q >= h.l0[r + 1]) ++r;
         const uint32_t k = h.g0[r] + (q - h.l0[r]);
         R4<R> v = pos[k];
-        v.w = phase_as<R>(info_phase(O.info[k]));
+        // w: the phase in bit 0, the cell's x index from xlo in bits 8-15 (at most 34 cells)
+        v.w = phase_as<R>(info_phase(O.info[k]) | ((O.key[k] - h.rbase[r]) << 8));
         rec[q] = v;
     }
     __syncthreads();
@@ -1083,6 +1089,7 @@ __device__ __forceinline__ void for_staged(const IC& I, const uint32_t* __restri
 {
     const int nx = I.nc[0];
     const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+    const float cx1 = (float)(L.c[0] - h.xlo + 1);   // c_i + 1 along x, from xlo
     int rr = 0;
     for (int dz = zlo; dz <= zhi; ++dz) {
         int cz = L.c[2] + dz;
@@ -1101,23 +1108,34 @@ __device__ __forceinline__ void for_staged(const IC& I, const uint32_t* __restri
             row.dz1 = (float)(1 - dz);
             const uint32_t a = cstart[row.base + (uint32_t)max(L.c[0] - 1, 0)];
             const uint32_t b = cstart[row.base + (uint32_t)min(L.c[0] + 1, nx - 1) + 1];
-            const uint32_t m0 = cstart[row.base + (uint32_t)L.c[0]];
-            const uint32_t m1 = cstart[row.base + (uint32_t)L.c[0] + 1];
             const R4<R>* rw = rec + h.l0[rr] - h.g0[rr];   // staged record of candidate k: rw[k]
             ++rr;
+            // a batch reads up to U P - 1 records past b, inside the buffer's slack; those
+            // slots are not taken
             for (uint32_t kb = a; kb < b; kb += U * P) {
                 const uint32_t k0 = kb + sub;
+                const R4<R>* rk = rw + k0;
                 R4<R> pj[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) pj[u] = rw[min(k0 + (uint32_t)(u * P), b - 1)];
+                for (int u = 0; u < U; ++u) pj[u] = rk[u * P];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const uint32_t k = k0 + (uint32_t)(u * P);
+                    const uint32_t wb = phase_of<R>(pj[u].w);
                     R r[3];
-                    const int dcx = 1 - (int)(k >= m0) - (int)(k >= m1);
-                    const uint32_t code = pair_r<DIM>(I, L, row, pj[u], dcx, r);
+                    uint32_t code;
+                    if constexpr (sizeof(R) == 4) {
+                        // c_i - c_j + 1 along x, from the record's cell index
+                        const float fx = cx1 - (float)((wb >> 8) & 0xFFu);
+                        r[0] = fmaf(fx, I.f_cs[0], L.om[0] - pj[u].x);
+                        r[1] = fmaf(row.dy1, I.f_cs[1], L.om[1] - pj[u].y);
+                        r[2] = DIM == 3 ? fmaf(row.dz1, I.f_cs[2], L.om[2] - pj[u].z) : 0.0f;
+                        code = (uint32_t)fx | row.code;
+                    } else {
+                        code = pair_r<DIM>(I, L, row, pj[u], 0, r);
+                    }
                     const R r2 = dist2<DIM>(r[0], r[1], r[2]);
-                    body(k, r, r2, pj[u], phase_of<R>(pj[u].w), code, k < b && k != i && r2 < cut2);
+                    body(k, r, r2, pj[u], wb & 1u, code, k < b && k != i && r2 < cut2);
                 }
             }
         }
