@@ -438,10 +438,12 @@ def flume3d(k_seed: int = 3, *, dx=4e-3, length=4.0, width=0.1, depth=0.5,
 
 
 def lab_flume(dim: int = 2, *, dx=5e-3, width=0.05, seed=SEED_BASE + 10) -> Scene:
-    """The paper's laboratory flume (Sec. IV): 6 m long, water depth 0.25 m, piston at
-    x = 0.55 m driven by Eq. (18) (stroke 45.72 cm at 0.75 Hz, t <= 2/3 s), oil slick
-    25.4 cm long and 0.5 mm thick (one particle layer at this resolution) centred at
-    x = 1.5 m, interfacial tension 0.019 N/m; in 3D a narrowed periodic width."""
+    """The paper's laboratory flume (Sec. IV): 6 m long and 0.6 m high, water depth
+    0.25 m, piston at x = 0.55 m driven by Eq. (18) (stroke 45.72 cm at 0.75 Hz,
+    t <= 2/3 s), oil slick 25.4 cm long and 0.5 mm thick (one particle layer at this
+    resolution) centred at x = 1.5 m, interfacial tension 0.019 N/m; in 3D a narrowed
+    periodic width.  The piston and end wall are the flume's height; the domain reaches
+    0.75 m, so that water running up the piston stays inside it."""
     stroke = 0.4572
     piston = dict(piston_a=[-stroke / 2], piston_w=[2 * math.pi * 0.75], piston_phi=[0.0],
                   piston_t_end=2.0 / 3.0)
@@ -455,7 +457,7 @@ def lab_flume(dim: int = 2, *, dx=5e-3, width=0.05, seed=SEED_BASE + 10) -> Scen
         return (np.abs(pts[:, 0] - xs) < 0.127) & top
     return flume(dim, length, depth, dx, seed=seed, width=width if dim == 3 else None,
                  slick=slick, piston=piston, rho_o=900.0, mu_o=5e-3, alpha_s=0.019,
-                 back=0.05, name="lab_flume")
+                 back=0.05, wall_top=0.6 / depth, headroom=0.75 / depth, name="lab_flume")
 
 
 def batched_drops(k_seed: int = 4, ninst: int = 256, nmin=2000, nmax=40000) -> Scene:
