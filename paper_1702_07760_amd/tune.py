@@ -106,6 +106,7 @@ SCENES = {
     "drop3d": lambda i: i.drop3d(),
     "paper_sphere": lambda i: i.paper_drop("sphere"),
     "lab_flume_5mm": lambda i: i.lab_flume(3, dx=5e-3, width=0.05),
+    "lab_flume_1mm": lambda i: i.lab_flume(3, dx=1e-3, width=0.015),
     "flume2d": lambda i: i.flume2d(),
     "flume3d": lambda i: i.flume3d(),
     "tanks256": lambda i: i.batched_drops(),
